@@ -1,0 +1,150 @@
+"""Seeded synthetic workloads shaped like the paper's benchmark runs.
+
+This module holds input generation only (random initial states, grid sizes,
+stencil sizes and the derived time steps).  It contains none of the method's
+arithmetic, so both the HIP path and the CPU oracle can take their inputs from
+it.  Every generator uses numpy's PCG64 with a fixed seed.
+
+Problems are plain dicts with the keys
+
+    N, n, bc, h, dt, c, nu, delta, react, scheme, nonlin, nl_coef,
+    bc_left, bc_right
+
+describing  u_t = -c u_x + nu u_xx - delta u_xxx + react u + N(u)  on a uniform
+grid of N nodes with spacing h (Sec. 2: grid of N points, stencil size n,
+time step dt, coefficients of the coupled operator, boundary handling).
+
+The five workloads stand in for the paper's experiments (Sec. 4: coupled
+advection-diffusion, Burgers, KdV, Allen-Cahn); the paper ships no data, so
+every input is synthetic.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+BASE_SEED = 1000
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def make_problem(**kw) -> dict:
+    p = dict(N=0, n=5, bc="periodic", h=1.0, dt=1.0, c=0.0, nu=0.0, delta=0.0, react=0.0,
+             scheme="linear", nonlin="none", nl_coef=0.0, bc_left=0.0, bc_right=0.0)
+    unknown = set(kw) - set(p)
+    if unknown:
+        raise KeyError(f"unknown problem keys {sorted(unknown)}")
+    p.update(kw)
+    return p
+
+
+def stencil_p(scheme: str) -> int:
+    """Number of phi-weight vectors beyond W0 that a scheme uses."""
+    return {"linear": 0, "etd1": 1, "etd2rk": 2}[scheme]
+
+
+# ---------------------------------------------------------------- C1 ------
+def advection_diffusion(N: int = 256, cfl: float = 2.0, n: int = 5, c: float = 1.0, nu: float = 1e-3,
+                        seed: int = BASE_SEED + 0):
+    """Periodic u_t + c u_x = nu u_xx on [0, 2pi): periodised Gaussian (centre
+    U[1,5], width 0.3) plus four sine modes with N(0, 0.1) amplitudes."""
+    L = 2.0 * math.pi
+    h = L / N
+    x = h * np.arange(N)
+    g = rng(seed)
+    xc = g.uniform(1.0, 5.0)
+    a = g.normal(0.0, math.sqrt(0.1), 4)
+    u0 = sum(np.exp(-((x - xc - s) ** 2) / (2 * 0.3 ** 2)) for s in (-L, 0.0, L))
+    for k in range(1, 5):
+        u0 = u0 + a[k - 1] * np.sin(k * x)
+    p = make_problem(N=N, n=n, bc="periodic", h=h, dt=cfl * h / c, c=c, nu=nu, scheme="linear")
+    return p, u0
+
+
+# ---------------------------------------------------------------- C2 ------
+def _dirichlet_modes(g: np.random.Generator, x: np.ndarray, length: float, modes: int = 8) -> np.ndarray:
+    a = g.normal(0.0, 1.0, modes) / np.arange(1, modes + 1)  # N(0, 1/k^2)
+    return sum(a[k - 1] * np.sin(k * math.pi * x / length) for k in range(1, modes + 1))
+
+
+def burgers(N: int = 65536, n: int = 7, nu: float = 1e-2, cfl: float = 1.0, mu: float = 0.25,
+            seed: int = BASE_SEED + 1):
+    """Viscous Burgers u_t + u u_x = nu u_xx on [0, (N-1)h], h = 4 nu, with
+    Dirichlet u = 0 ends; frozen-velocity ETD1.  u0 = sum of 8 sine modes with
+    N(0, 1/k^2) amplitudes.  dt = min(cfl h / max|u0|, mu h^2 / nu)."""
+    h = 4.0 * nu
+    length = (N - 1) * h
+    x = h * np.arange(N)
+    u0 = _dirichlet_modes(rng(seed), x, length)
+    dt = min(cfl * h / float(np.max(np.abs(u0))), mu * h * h / nu)
+    p = make_problem(N=N, n=n, bc="dirichlet", h=h, dt=dt, nu=nu, scheme="etd1",
+                     nonlin="burgers_frozen", nl_coef=1.0)
+    return p, u0
+
+
+# ---------------------------------------------------------------- C3 ------
+def kdv(N: int = 2 ** 20, n: int = 9, tau: float = 4.0 / math.pi ** 3, length: float = 200.0,
+        seed: int = BASE_SEED + 2):
+    """Periodic KdV u_t + 6 u u_x + u_xxx = 0 on [0, 200): two solitons
+    (c/2) sech^2(sqrt(c)(x - x0)/2), c ~ U[1,4], x0 ~ U[0,200); ETD2RK;
+    dt = tau h^3 (dispersive number tau = dt/h^3)."""
+    h = length / N
+    x = h * np.arange(N)
+    g = rng(seed)
+    cs = g.uniform(1.0, 4.0, 2)
+    x0 = g.uniform(0.0, length, 2)
+    u0 = np.zeros(N)
+    for cc, xx in zip(cs, x0):
+        for s in (-length, 0.0, length):
+            u0 += 0.5 * cc / np.cosh(0.5 * math.sqrt(cc) * (x - xx - s)) ** 2
+    p = make_problem(N=N, n=n, bc="periodic", h=h, dt=tau * h ** 3, delta=1.0, scheme="etd2rk",
+                     nonlin="kdv", nl_coef=6.0)
+    return p, u0
+
+
+# ---------------------------------------------------------------- C4 ------
+def allen_cahn_batch(count: int = 4096, n_min: int = 512, n_max: int = 65536, stencils=(5, 7, 9, 11),
+                     eps2: float = 1e-4, mu: float = 0.5, seed: int = BASE_SEED + 3):
+    """Independent 1-D Allen-Cahn instances u_t = eps^2 u_xx + u - u^3 on
+    [-1, 1]: N_k ~ U{n_min..n_max}, n_k from `stencils`, periodic or Neumann
+    with probability 1/2 each, dt_k = mu h_k^2 / eps^2, ETD1, u0 ~ U[-0.1, 0.1]."""
+    g = rng(seed)
+    Ns = g.integers(n_min, n_max + 1, count)
+    ns = g.choice(np.asarray(stencils), count)
+    bcs = g.integers(0, 2, count)
+    probs, states = [], []
+    for N, n, b in zip(Ns, ns, bcs):
+        N, n = int(N), int(n)
+        bc = "periodic" if b == 0 else "neumann"
+        h = 2.0 / N if bc == "periodic" else 2.0 / (N - 1)
+        probs.append(make_problem(N=N, n=n, bc=bc, h=h, dt=mu * h * h / eps2, nu=eps2, scheme="etd1",
+                                  nonlin="allen_cahn", nl_coef=1.0))
+        states.append(g.uniform(-0.1, 0.1, N))
+    return probs, states
+
+
+# ---------------------------------------------------------------- C5 ------
+def burgers_adjoint_batch(batch: int = 64, N: int = 262144, n: int = 9, nu: float = 5e-3,
+                          nu_factor: float = 1.1, cfl: float = 1.0, mu: float = 0.25,
+                          seed: int = BASE_SEED + 4):
+    """Batch of viscous-Burgers trajectories for the adjoint workload: the C2
+    recipe with h = 4 nu, trajectory b seeded with seed + b, one common dt.
+    Returns (problem, target_problem, u0 list); the target problem uses
+    nu * nu_factor on the same grid and dt."""
+    h = 4.0 * nu
+    length = (N - 1) * h
+    x = h * np.arange(N)
+    u0s = [_dirichlet_modes(rng(seed + b), x, length) for b in range(batch)]
+    umax = max(float(np.max(np.abs(u))) for u in u0s)
+    dt = min(cfl * h / umax, mu * h * h / nu)
+    p = make_problem(N=N, n=n, bc="dirichlet", h=h, dt=dt, nu=nu, scheme="etd1",
+                     nonlin="burgers_frozen", nl_coef=1.0)
+    pt = dict(p, nu=nu * nu_factor)
+    return p, pt, u0s
+
+
+STEPS = {"advection_diffusion": 100, "burgers": 1000, "kdv": 2000, "allen_cahn_batch": 500,
+         "burgers_adjoint_batch": 500}
