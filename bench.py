@@ -1,0 +1,166 @@
+"""Throughput of the LMEP hot path on one MI355X.
+
+Default workload: viscous Burgers u_t + u u_x = nu u_xx, N = 65536 nodes,
+Dirichlet ends with one-sided edge stencils, n = 7, ETD1 with the phi1 weights
+of the augmented local matrix rebuilt every step from the frozen local
+velocity (one FP64 Pade scaling-and-squaring exponential of an 8x8 local
+matrix per node per step), 1000 steps.  A "step" is one time step of the whole
+hot path: weight build for every node + banded apply.
+
+Prints one JSON line: node-steps/s of the timed K steps (inputs resident in
+HBM), the roofline of the dominant kernel (the weight build, FP64 vector ALU)
+from HIP events recorded around each build launch in a second, profiled pass
+over the same K steps, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+
+def pade_flops(m: int, matrices: int, squarings: int) -> float:
+    """Algorithmic flops of degree-13 Pade scaling-and-squaring on m x m
+    matrices, 2 flops per multiply-add: 6 products for U and V, one LU solve
+    with m right-hand sides (8 m^3 / 3), and one product per squaring."""
+    return matrices * (2.0 * 6 * m ** 3 + 8.0 * m ** 3 / 3.0) + squarings * 2.0 * m ** 3
+
+
+def make_workload(name: str):
+    import workloads
+    if name == "burgers":
+        p, u0 = workloads.burgers()
+        return [p], [u0], "viscous Burgers N=65536 n=7 Dirichlet, frozen-velocity ETD1, weights rebuilt every step"
+    if name == "kdv":
+        p, u0 = workloads.kdv()
+        return [p], [u0], "periodic KdV N=1048576 n=9 ETD2RK, dispersive number 4/pi^3, stationary weights"
+    if name == "allen_cahn_batch":
+        ps, us = workloads.allen_cahn_batch()
+        return ps, us, "4096 Allen-Cahn instances N_k in [512,65536], n_k in {5,7,9,11}, ETD1, stationary weights"
+    if name == "advection_diffusion":
+        p, u0 = workloads.advection_diffusion()
+        return [p], [u0], "periodic advection-diffusion N=256 n=5 CFL 2, LINEAR"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(problem, u0, budget_s: float = 15.0):
+    """The oracle as it stands, on a bounded number of steps of the same workload."""
+    import oracle
+    t = time.perf_counter()
+    u = oracle.run(problem, u0, 1)
+    one = time.perf_counter() - t
+    steps = max(1, min(1000, int(budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    oracle.run(problem, u, steps)
+    el = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": problem["N"] * steps / el, "unit": "node-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} steps of the same workload (N={problem['N']}) after 1 warm step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="burgers")
+    ap.add_argument("--graph", action="store_true", help="replay the step loop from a hipGraph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        raise SystemExit(2)
+
+    import torch
+    import paper_2603_15964_amd as lmep
+
+    problems, states, desc = make_workload(args.workload)
+    dev = "cuda:0"
+    batch = lmep.Batch(problems, device=dev)
+    w = batch.empty_weights()
+    u0 = batch.pack(states)
+    ua, ub = batch.empty_state(), batch.empty_state()
+    frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
+    if not all(p.get("nonlin") == "burgers_frozen" for p in problems):
+        batch.build_weights(w, u0)
+    flags = lmep.LMEP_F_GRAPH if args.graph else 0
+
+    if args.warmup > 0:
+        batch.step(w, u0, args.warmup, flags, u_out=ua)
+    else:
+        ua.copy_(u0)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    batch.step(w, ua, args.steps, flags, u_out=ub)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = start.elapsed_time(stop)
+    node_steps = batch.state_size * args.steps
+    value = node_steps / wall
+
+    # profiled pass: HIP events around every build / apply launch, same K steps
+    # from the same state; then an untimed pass over the same steps that counts
+    # the squarings each local exponential took (for the algorithmic flops)
+    batch.step(w, ua, args.steps, lmep.LMEP_F_PROFILE, u_out=ub)
+    if frozen:
+        batch.step(w, ua, args.steps, lmep.LMEP_F_COUNT, u_out=ub)
+    prof = lmep.lmep_profile_last()
+    roof = None
+    extra = {"gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3}
+    apply_bytes = {"burgers": 128.0, "kdv": 40.0, "allen_cahn_batch": 16.0, "advection_diffusion": 16.0}
+    if frozen and prof["build_launches"] > 0:
+        p0 = problems[0]
+        m = p0["n"] + {"linear": 0, "etd1": 1, "etd2rk": 2}[p0["scheme"]]
+        flops = pade_flops(m, prof["matrices"], prof["squarings"])
+        build_s = prof["build_ms"] / 1e3
+        achieved = flops / build_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "kernel": f"build_pade_kernel<{p0['n']},{m - p0['n']}>",
+                "avg_launch_us": prof["build_ms"] * 1e3 / prof["build_launches"],
+                "flops_per_launch": flops / prof["build_launches"],
+                "mean_squarings": prof["squarings"] / max(1, prof["matrices"])}
+    if prof["apply_launches"] > 0:
+        ab = apply_bytes.get(args.workload, 16.0) * node_steps
+        gbs = ab / (prof["apply_ms"] / 1e3) / 1e9
+        extra["apply"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": gbs / PEAK_HBM_GBS,
+                          "avg_launch_us": prof["apply_ms"] * 1e3 / prof["apply_launches"]}
+        if roof is None:
+            roof = dict(extra["apply"], traffic=None)
+    out = {
+        "metric": "node-steps/s (weight build+apply, FP64)",
+        "value": value,
+        "unit": "node-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "instances": batch.count, "nodes": batch.state_size,
+                   "graph": bool(args.graph)},
+        "roofline": roof,
+        "detail": extra,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problems[0], states[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

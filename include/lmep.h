@@ -1,0 +1,160 @@
+/*
+ * lmep.h -- C ABI of the Local Matrix Exponential Propagator (LMEP) hot path
+ * on AMD Instinct MI355X (gfx950), FP64 throughout.
+ *
+ * The method (Bayona, "Unifying finite differences and semi-Lagrangian schemes
+ * via localized matrix exponentials"): for every grid node, form the local
+ * operator L on the node's n-point stencil (Sec. 2.1 steps 1-2), take the
+ * exponential of the augmented local matrix whose first block row holds
+ * e^{dt L}, dt phi1(dt L), dt^2 phi2(dt L) (Sec. 3.1 steps 1-2), harvest the
+ * node's row of each block (Sec. 2.1 step 3, Sec. 3.1 step 2) and apply the
+ * harvested rows as a banded stencil once per time step (Sec. 3.1 step 3).
+ *
+ * The PDE is  u_t = -c u_x + nu u_xx - delta u_xxx + react u + N(u)  on a
+ * uniform 1-D grid (Sec. 2, problem statement; Remark "No operator splitting";
+ * Sec. 3 semi-linear form).  Stencils are centred; next to Dirichlet ends they
+ * are the n nearest in-domain nodes and the node's own ("edge") row is
+ * harvested (Sec. 2.1 step 3); Neumann ends reflect the stencil evenly.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device memory owned by the caller; prob is host
+ *    memory.  Nothing is retained after return, except inside a graph that a
+ *    call captured itself (LMEP_F_GRAPH), which is replayed and destroyed
+ *    within that same call.
+ *  - All argument checks run before any device work; on failure the call
+ *    returns a negative lmep_status, writes nothing and lmep_last_error()
+ *    describes the problem.
+ *  - Work is enqueued on hip_stream (a hipStream_t; NULL = default stream)
+ *    and is asynchronous.  Errors of earlier asynchronous work surface as
+ *    LMEP_ERR_DEVICE.
+ *  - The library allocates no device memory.  Temporary storage comes from
+ *    the caller's scratch buffer, sized by lmep_scratch_bytes().  The first
+ *    call on a device fills a small static table of stencil weights and waits
+ *    for it; make that first call outside stream capture.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef LMEP_H
+#define LMEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LMEP_OK = 0,
+    LMEP_ERR_ARG = -1,          /* invalid argument (nothing was written)          */
+    LMEP_ERR_UNSUPPORTED = -2,  /* valid but not implemented combination           */
+    LMEP_ERR_DEVICE = -3,       /* HIP runtime error, now or from earlier work     */
+    LMEP_ERR_NONFINITE = -4,    /* LMEP_F_CHECK_FINITE found a NaN / Inf           */
+    LMEP_ERR_SCRATCH = -5       /* scratch buffer NULL or smaller than required    */
+} lmep_status;
+
+enum { LMEP_BC_PERIODIC = 0, LMEP_BC_DIRICHLET = 1, LMEP_BC_NEUMANN = 2 };
+
+/* Time schemes (Sec. 3): LINEAR u+ = W0.u (p = 0 phi-blocks); ETD1 adds
+ * W1.N (ETD-s with s = 1, p = 1); ETD2RK is the Cox-Matthews two-stage
+ * scheme a = W0.u + W1.N(u), u+ = a + W2.(N(a) - N(u)) (p = 2). */
+enum { LMEP_LINEAR = 0, LMEP_ETD1 = 1, LMEP_ETD2RK = 2 };
+
+/* Nonlinear terms N(u), g = nl_coef:
+ *  BURGERS_FROZEN  u_t + g u u_x = ...: the node's own velocity is frozen into
+ *                  its local operator (advection coefficient c + g u_i, so the
+ *                  weights are rebuilt every step) and the remainder
+ *                  N_j = -g (u_j - u_i) (du/dx)_j enters through W1 (ETD1 only);
+ *  KDV             N = -(g/2) d/dx (u^2)  (conservative form of -g u u_x);
+ *  ALLEN_CAHN      N = g (u - u^3). */
+enum { LMEP_NL_NONE = 0, LMEP_NL_BURGERS_FROZEN = 1, LMEP_NL_KDV = 2, LMEP_NL_ALLEN_CAHN = 3 };
+
+/* lmep_step flags */
+#define LMEP_F_GRAPH        0x1u  /* capture the step loop in a hipGraph and replay it          */
+#define LMEP_F_PERSISTENT   0x2u  /* multi-step kernel that keeps each instance on chip          */
+#define LMEP_F_CHECK_FINITE 0x4u  /* scan the result; LMEP_ERR_NONFINITE if any entry is not    */
+                                  /* finite (synchronises the stream)                            */
+#define LMEP_F_PROFILE      0x8u  /* time the weight-build and apply kernels with HIP events    */
+                                  /* (synchronises); read back with lmep_profile_last()          */
+#define LMEP_F_COUNT        0x10u /* count local matrices and scaling-and-squaring squarings     */
+                                  /* (atomics; slows the build; lmep_profile_last())             */
+
+/* One problem instance.  A batch is an array of these; instance k's state
+ * occupies d_u[state_off, state_off + N) of every packed state buffer and its
+ * weights d_w[weight_off, weight_off + lmep_weight_count(&prob[k])). */
+typedef struct {
+    int64_t N;          /* grid nodes; N >= n; Neumann also needs N >= (n+1)/2       */
+    int32_t n;          /* stencil size: odd, 3..15; n + p <= 16                      */
+    int32_t bc;         /* LMEP_BC_*                                                  */
+    double  h;          /* uniform grid spacing, > 0                                  */
+    double  dt;         /* time step, > 0                                             */
+    double  c;          /* advection speed                                            */
+    double  nu;         /* diffusion coefficient                                      */
+    double  delta;      /* dispersion coefficient                                     */
+    double  react;      /* linear reaction coefficient (c0 of Thm 2)                  */
+    int32_t scheme;     /* LMEP_LINEAR / LMEP_ETD1 / LMEP_ETD2RK                      */
+    int32_t nonlin;     /* LMEP_NL_*                                                  */
+    double  nl_coef;    /* g of the nonlinear term                                    */
+    double  bc_left;    /* Dirichlet value held at node 0                             */
+    double  bc_right;   /* Dirichlet value held at node N-1                           */
+    int64_t state_off;  /* offset (in doubles) of the state in packed state buffers   */
+    int64_t weight_off; /* offset (in doubles) of the weights in the weight buffer    */
+} lmep_problem;
+
+/* Number of doubles of harvested weights one instance needs (p = 0, 1, 2 for
+ * LINEAR, ETD1, ETD2RK):
+ *   weights rebuilt per node (BURGERS_FROZEN): (1+p) * n * N, layout
+ *       [kind][k][i]  -- weight k of node i's stencil, kind 0 = W0 (row of
+ *       e^{dt L}), 1 = W1 (row of dt phi1(dt L)), 2 = W2 (row of dt phi2(dt L));
+ *   stationary operators: (1+p) * n * n, layout [kind][r][k] -- the harvest of
+ *       stencil row r (every node harvests row r = -offset of its stencil).
+ * Returns -1 for an invalid problem. */
+int64_t lmep_weight_count(const lmep_problem* prob);
+
+/* Bytes of scratch an operation needs: op 0 = lmep_build_weights,
+ * 1 = lmep_step, 2 = lmep_adjoint_step.  Returns 0 for invalid arguments. */
+size_t lmep_scratch_bytes(const lmep_problem* prob, int32_t count, int32_t op);
+
+/* Build the harvested weights of `count` instances into d_w (steps a1-a6:
+ * stencil, local operator, augmented matrix, FP64 Pade scaling-and-squaring
+ * exponential per local matrix, harvest).  d_u is read only for
+ * BURGERS_FROZEN instances (their frozen velocity) and may be NULL otherwise. */
+int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_u,
+                       double* d_w, void* d_scratch, size_t scratch_bytes, void* hip_stream);
+
+/* Advance every instance n_steps >= 1 steps: d_u_out = (step)^n_steps(d_u_in).
+ * d_w must hold the weights of stationary instances (lmep_build_weights);
+ * for BURGERS_FROZEN instances the weights are rebuilt into d_w every step.
+ * d_u_in is not modified and must not overlap d_u_out. */
+int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in,
+              double* d_u_out, int32_t n_steps, uint32_t flags, void* d_scratch,
+              size_t scratch_bytes, void* hip_stream);
+
+/* Reverse of one LINEAR or ETD1 step (not ETD2RK / KDV).  Given the forward
+ * state d_u_k = u^k and d_lambda_next = d loss / d u^{k+1}, write
+ * d_lambda_k = d loss / d u^k and add this step's parameter derivatives to
+ * d_grad[3 * k + {0, 1, 2}] = (d loss/d nu, d loss/d c, d loss/d delta) of
+ * instance k.  The weights' dependence on the parameters and on the frozen
+ * velocity is taken from the Frechet derivative of each local exponential,
+ * read off the block-triangular exponential [[A, E], [0, A]] (FP64 Pade).
+ * Entries of lambda at Dirichlet end nodes are ignored (those nodes are not
+ * updated).  Summation order is fixed, so results are bitwise reproducible. */
+int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u_k,
+                      const double* d_lambda_next, double* d_lambda_k, double* d_grad,
+                      void* d_scratch, size_t scratch_bytes, void* hip_stream);
+
+/* Measurements of the last lmep_step calls on this thread: weight-build and
+ * apply kernel time of the last LMEP_F_PROFILE call (milliseconds, summed over
+ * launches, from HIP events recorded around each launch on the call's stream),
+ * and, from the last LMEP_F_COUNT call, the number of local matrices
+ * exponentiated and the total number of squarings their scaling-and-squaring
+ * took.  Any pointer may be NULL. */
+int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_ms,
+                      int32_t* apply_launches, int64_t* matrices, int64_t* squarings);
+
+/* Thread-local description of the last non-OK status. */
+const char* lmep_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMEP_H */

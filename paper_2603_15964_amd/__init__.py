@@ -1,0 +1,132 @@
+"""LMEP hot path on AMD Instinct MI355X (gfx950).
+
+The Local Matrix Exponential Propagator builds, for every grid node, the
+exponential of a small local operator on the node's stencil (plus the
+augmented matrix that yields the ETD phi-weights), harvests the node's row,
+and applies the harvested rows as a banded stencil each time step.  All of
+that runs in the HIP kernels of ``liblmep.so``; this package only marshals
+arguments through the C ABI of ``include/lmep.h``.  PyTorch provides device
+memory and streams.
+
+``Batch`` packs a list of problem dicts (keys as in ``workloads``) into flat
+device buffers and calls the three entry points ``lmep_build_weights``,
+``lmep_step`` and ``lmep_adjoint_step``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._native import (  # noqa: F401  (re-exported names of the C ABI)
+    EXPORTED, LIB_PATH, LMEP_BC_DIRICHLET, LMEP_BC_NEUMANN, LMEP_BC_PERIODIC, LMEP_ERR_ARG, LMEP_ERR_DEVICE,
+    LMEP_ERR_NONFINITE, LMEP_ERR_SCRATCH, LMEP_ERR_UNSUPPORTED, LMEP_ETD1, LMEP_ETD2RK, LMEP_F_CHECK_FINITE, LMEP_F_COUNT,
+    LMEP_F_GRAPH, LMEP_F_PERSISTENT, LMEP_F_PROFILE, LMEP_LINEAR, LMEP_NL_ALLEN_CAHN, LMEP_NL_BURGERS_FROZEN,
+    LMEP_NL_KDV, LMEP_NL_NONE, LMEP_OK, OP_ADJOINT, OP_BUILD, OP_STEP, LmepError, library, lmep_adjoint_step,
+    lmep_build_weights, lmep_last_error, lmep_problem, lmep_profile_last, lmep_scratch_bytes, lmep_step,
+    lmep_weight_count, problem_array, to_struct)
+
+_KINDS = {"linear": 1, "etd1": 2, "etd2rk": 3}
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Batch:
+    """A batch of independent LMEP instances packed into flat FP64 buffers.
+
+    Instance k's state occupies ``[state_off[k], state_off[k] + N_k)`` of every
+    state tensor and its weights ``[weight_off[k], ...)`` of the weight tensor
+    (layouts in include/lmep.h).
+    """
+
+    def __init__(self, problems, device="cuda:0"):
+        self.problems = [dict(p) for p in problems]
+        self.device = torch.device(device)
+        self.count = len(self.problems)
+        so, wo = 0, 0
+        self.state_off, self.weight_off, self.weight_len = [], [], []
+        structs = []
+        for p in self.problems:
+            s = to_struct(p, so, wo)
+            wl = lmep_weight_count(s)
+            structs.append(s)
+            self.state_off.append(so)
+            self.weight_off.append(wo)
+            self.weight_len.append(wl)
+            so += int(p["N"])
+            wo += (wl + 31) // 32 * 32
+        self.structs = problem_array(structs)
+        self.state_size = so
+        self.weight_size = wo
+        self._scratch = {}
+
+    # ------------------------------------------------------------ buffers --
+    def scratch(self, op: int):
+        if op not in self._scratch:
+            nbytes = lmep_scratch_bytes(self.structs, self.count, op)
+            t = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            assert t.data_ptr() % 256 == 0
+            self._scratch[op] = t
+        t = self._scratch[op]
+        return t.data_ptr(), t.numel()
+
+    def empty_state(self) -> torch.Tensor:
+        return torch.empty(self.state_size, dtype=torch.float64, device=self.device)
+
+    def empty_weights(self) -> torch.Tensor:
+        return torch.zeros(self.weight_size, dtype=torch.float64, device=self.device)
+
+    def pack(self, states) -> torch.Tensor:
+        if self.count == 1 and isinstance(states, np.ndarray):
+            states = [states]
+        flat = np.concatenate([np.asarray(s, dtype=np.float64) for s in states])
+        assert flat.size == self.state_size
+        return torch.from_numpy(flat).to(self.device)
+
+    def unpack(self, t: torch.Tensor):
+        a = t.detach().cpu().numpy()
+        return [a[o:o + int(p["N"])].copy() for o, p in zip(self.state_off, self.problems)]
+
+    def unpack_weights(self, w: torch.Tensor):
+        """Per instance: [kind, k, N] (frozen velocity) or [kind, r, k] (stationary)."""
+        a = w.detach().cpu().numpy()
+        out = []
+        for o, l, p in zip(self.weight_off, self.weight_len, self.problems):
+            kinds, n = _KINDS[p["scheme"]], int(p["n"])
+            last = int(p["N"]) if p.get("nonlin") == "burgers_frozen" else n
+            out.append(a[o:o + l].reshape(kinds, n, last).copy())
+        return out
+
+    # ------------------------------------------------------- entry points --
+    def build_weights(self, w: torch.Tensor, u: torch.Tensor = None) -> torch.Tensor:
+        sp, sb = self.scratch(OP_BUILD)
+        lmep_build_weights(self.structs, self.count, u.data_ptr() if u is not None else None, w.data_ptr(), sp, sb,
+                           _stream_handle(self.device))
+        return w
+
+    def step(self, w: torch.Tensor, u_in: torch.Tensor, n_steps: int, flags: int = 0,
+             u_out: torch.Tensor = None) -> torch.Tensor:
+        if u_out is None:
+            u_out = self.empty_state()
+        sp, sb = self.scratch(OP_STEP)
+        lmep_step(self.structs, self.count, w.data_ptr(), u_in.data_ptr(), u_out.data_ptr(), int(n_steps),
+                  int(flags), sp, sb, _stream_handle(self.device))
+        return u_out
+
+    def adjoint_step(self, u_k: torch.Tensor, lam_next: torch.Tensor, lam_k: torch.Tensor = None,
+                     grad: torch.Tensor = None):
+        if lam_k is None:
+            lam_k = self.empty_state()
+        if grad is None:
+            grad = torch.zeros(3 * self.count, dtype=torch.float64, device=self.device)
+        sp, sb = self.scratch(OP_ADJOINT)
+        lmep_adjoint_step(self.structs, self.count, u_k.data_ptr(), lam_next.data_ptr(), lam_k.data_ptr(),
+                          grad.data_ptr(), sp, sb, _stream_handle(self.device))
+        return lam_k, grad
+
+
+__all__ = ["Batch", "LmepError", "lmep_problem", "lmep_build_weights", "lmep_step", "lmep_adjoint_step",
+           "lmep_scratch_bytes", "lmep_weight_count", "lmep_last_error", "lmep_profile_last", "library"]

@@ -1,0 +1,204 @@
+// Weight build (steps a3-a6): per local matrix, form the augmented local
+// operator, take its exponential by FP64 Pade scaling-and-squaring, and
+// harvest the node's row of each block.
+//
+// Local matrix (compact, transposed form of the paper's augmented block matrix
+// of Sec. 3.1, size M = n + p):
+//     Mt = dt * [[L^T, e_r, 0], [0, 0, 1], [0, 0, 0]]
+// exp(Mt) holds, in rows < n, column r of e^{dt L^T} (= row r of e^{dt L},
+// the W0 harvest), column n = dt phi1(dt L^T) e_r (= row r of dt phi1(dt L),
+// W1) and column n+1 = dt^2 phi2(dt L^T) e_r (row r of dt^2 phi2, W2 * dt).
+// Transposing puts the harvested rows into columns, so lane k (= stencil
+// position k) ends up holding weight k of every kind, ready for the
+// structure-of-arrays weight layout that the apply kernel reads coalesced.
+//
+// Exponential: degree-13 diagonal Pade approximant with scaling and squaring
+// (Higham 2005, "The scaling and squaring method for the matrix exponential
+// revisited"): s = max(0, ceil(log2(||Mt|| / theta13))) chosen per matrix from
+// its own norm (so no matrix is over-scaled), U and V from A^2, A^4, A^6, one
+// linear solve, s squarings.  The norm is the infinity norm of Mt (the 1-norm
+// of the untransposed augmented matrix).  One local matrix per 16-lane DPP
+// row, lane i holding row i; four matrices per wavefront.
+#include "lmep_device.hpp"
+
+namespace lmep {
+namespace {
+
+constexpr double kTheta13 = 5.371920351148152;  // Higham 2005, Table 2.3
+
+// [13/13] Pade coefficients of e^x normalised to c_0 = 1:
+// c_j = (26 - j)! 13! / (26! j! (13 - j)!), via c_{j+1} = c_j (13 - j) / ((26 - j)(j + 1)).
+constexpr double pade13c(int j) {
+    double c = 1.0;
+    for (int i = 0; i < j; ++i) c = c * (double)(13 - i) / ((double)(26 - i) * (double)(i + 1));
+    return c;
+}
+
+template <int M>
+__device__ __forceinline__ void add_identity(double (&X)[M], double a, int lane) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) X[j] += (j == lane) ? a : 0.0;
+}
+
+// P = V + U, Q = V - U for the degree-13 approximant of A (row matrices).
+template <int M, int NB>
+__device__ __forceinline__ void pade13(const double (&A)[M], double (&P)[M], double (&Q)[M], int lane) {
+    constexpr double c[14] = {pade13c(0), pade13c(1), pade13c(2),  pade13c(3),  pade13c(4),
+                              pade13c(5), pade13c(6), pade13c(7),  pade13c(8),  pade13c(9),
+                              pade13c(10), pade13c(11), pade13c(12), pade13c(13)};
+    double A2[M], A4[M], A6[M], T[M];
+    mul<M, NB>(A, A, A2);
+    mul<M, NB>(A2, A2, A4);
+    mul<M, NB>(A4, A2, A6);
+    // U = A (A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I)
+#pragma unroll
+    for (int j = 0; j < M; ++j) T[j] = c[13] * A6[j] + c[11] * A4[j] + c[9] * A2[j];
+    mul<M, NB>(A6, T, P);  // P used as scratch for the inner sum
+#pragma unroll
+    for (int j = 0; j < M; ++j) P[j] += c[7] * A6[j] + c[5] * A4[j] + c[3] * A2[j];
+    add_identity(P, c[1], lane);
+    mul<M, NB>(A, P, T);  // T = U
+    // V = A6 (c12 A6 + c10 A4 + c8 A2) + c6 A6 + c4 A4 + c2 A2 + c0 I
+#pragma unroll
+    for (int j = 0; j < M; ++j) P[j] = c[12] * A6[j] + c[10] * A4[j] + c[8] * A2[j];
+#pragma unroll
+    for (int j = 0; j < M; ++j) Q[j] = c[6] * A6[j] + c[4] * A4[j] + c[2] * A2[j];
+    add_identity(Q, c[0], lane);
+    mul_acc<M, NB>(A6, P, Q);  // Q = V
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const double v = Q[j], u = T[j];
+        P[j] = v + u;
+        Q[j] = v - u;
+    }
+}
+
+template <int NN, int PP>
+__global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restrict__ probs, int nprob, int64_t items,
+                                                         const double* __restrict__ fd, const double* __restrict__ u,
+                                                         double* __restrict__ w,
+                                                         unsigned long long* __restrict__ stats) {
+    constexpr int M = NN + PP;
+    static_assert(M <= kMaxM, "local matrix exceeds one DPP row");
+    const int lane = threadIdx.x & 15;
+    const int64_t item = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (item >= items) return;  // the whole 16-lane row leaves together
+
+    const DevProb& P = probs[find_instance(probs, nprob, item)];
+    const int64_t local = item - P.item_begin;
+    const bool frozen = P.frozen != 0;
+    const int64_t node = frozen ? local : 0;
+    const int r = frozen ? (int)(-window_offset(node, P.N, NN, P.bc)) : (int)local;
+    const double dt = P.dt;
+    double ceff = P.c;
+    if (frozen) ceff += P.nl_coef * u[P.state_off + node];
+
+    // Row `lane` of Mt: dt * L[k][lane] for k < n (column `lane` of the local
+    // operator L = -c D1 + nu D2 - delta D3 + react I on the stencil).
+    const double ih = 1.0 / P.h;
+    const double a1 = -ceff * ih * dt, a2 = P.nu * ih * ih * dt, a3 = -P.delta * ih * ih * ih * dt;
+    const double ar = P.react * dt;
+    double A[M];
+    const int lc = lane < NN ? lane : 0;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+        const double d1 = fd[fd_index(NN, 0, k, lc)], d2 = fd[fd_index(NN, 1, k, lc)],
+                     d3 = fd[fd_index(NN, 2, k, lc)];
+        const double v = a1 * d1 + a2 * d2 + a3 * d3 + (k == lane ? ar : 0.0);
+        A[k] = lane < NN ? v : 0.0;
+    }
+    if constexpr (PP >= 1) A[NN] = (lane == r) ? dt : 0.0;
+    if constexpr (PP == 2) A[NN + 1] = (lane == NN) ? dt : 0.0;
+
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) rs += fabs(A[k]);
+    const double nrm = row_max16(rs);
+    int s = 0;
+    if (nrm > kTheta13) {
+        int e;
+        const double f = frexp(nrm / kTheta13, &e);
+        s = (f == 0.5) ? e - 1 : e;
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) A[k] = ldexp(A[k], -s);
+
+    double X[M], Q[M];
+    pade13<M, NN>(A, X, Q, lane);
+    solve_inplace<M>(Q, X, lane);
+    // s squarings, alternating between X and A
+    int q = s;
+    while (q >= 2) {
+        mul<M, NN>(X, X, A);
+        mul<M, NN>(A, A, X);
+        q -= 2;
+    }
+    if (q == 1) {
+        mul<M, NN>(X, X, A);
+#pragma unroll
+        for (int j = 0; j < M; ++j) X[j] = A[j];
+    }
+
+    if (stats && lane == 0) {  // profiling only: matrices built and squarings done
+        atomicAdd(stats, 1ull);
+        atomicAdd(stats + 1, (unsigned long long)s);
+    }
+    if (lane >= NN) return;
+    double w0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) w0 = (k == r) ? X[k] : w0;
+    double* __restrict__ wb = w + P.weight_off;
+    if (frozen) {
+        const int64_t N = P.N;
+        wb[(int64_t)lane * N + node] = w0;
+        if constexpr (PP >= 1) wb[(int64_t)(NN + lane) * N + node] = X[NN];
+        if constexpr (PP == 2) wb[(int64_t)(2 * NN + lane) * N + node] = X[NN + 1] / dt;
+    } else {
+        wb[r * NN + lane] = w0;
+        if constexpr (PP >= 1) wb[(NN + r) * NN + lane] = X[NN];
+        if constexpr (PP == 2) wb[(2 * NN + r) * NN + lane] = X[NN + 1] / dt;
+    }
+}
+
+template <int NN, int PP>
+hipError_t launch_np(const DevProb* d_probs, int nprob, int64_t items, const double* fd, const double* d_u,
+                     double* d_w, unsigned long long* stats, hipStream_t stream) {
+    if constexpr (NN + PP > kMaxM) {
+        return hipErrorInvalidValue;
+    } else {
+        const int64_t blocks = (items + 15) / 16;
+        hipLaunchKernelGGL((build_pade_kernel<NN, PP>), dim3((unsigned)blocks), dim3(256), 0, stream, d_probs, nprob,
+                           items, fd, d_u, d_w, stats);
+        return hipGetLastError();
+    }
+}
+
+template <int NN>
+hipError_t launch_n(int p, const DevProb* d_probs, int nprob, int64_t items, const double* fd, const double* d_u,
+                    double* d_w, unsigned long long* stats, hipStream_t stream) {
+    switch (p) {
+        case 0: return launch_np<NN, 0>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 1: return launch_np<NN, 1>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 2: return launch_np<NN, 2>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t items, const double* fd,
+                        const double* d_u, double* d_w, unsigned long long* stats, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    switch (n) {
+        case 3: return launch_n<3>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 5: return launch_n<5>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 7: return launch_n<7>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 9: return launch_n<9>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 11: return launch_n<11>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 13: return launch_n<13>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 15: return launch_n<15>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lmep

@@ -1,0 +1,82 @@
+// Step a2 -- finite-difference weights on the stencil (Sec. 2.1 step 1: the
+// standard differentiation matrix of the stencil, computed with Fornberg's
+// recursion for arbitrarily spaced nodes).  On a uniform grid the stencil
+// matrix does not depend on where the stencil sits, so one table per stencil
+// size serves every node: weights on the centred integer nodes
+// x_k = k - (n-1)/2, scaled by h^-d where they are used.  The table is a
+// static device array filled once per device by fd_table_kernel.
+#include <mutex>
+
+#include "lmep_device.hpp"
+
+namespace lmep {
+namespace {
+
+__device__ double g_fd_table[kFdTableDoubles];
+
+// Fornberg (1988), "Generation of finite difference formulas on arbitrarily
+// spaced grids": weights c[j][d] of node j for the d-th derivative at z,
+// built up one node at a time; derivatives up to order 3.
+__device__ void fornberg_weights(int n, double z, const double* x, double (*c)[4]) {
+    for (int j = 0; j < n; ++j)
+        for (int d = 0; d < 4; ++d) c[j][d] = 0.0;
+    c[0][0] = 1.0;
+    double c1 = 1.0, c4 = x[0] - z;
+    for (int i = 1; i < n; ++i) {
+        const int mn = i < 3 ? i : 3;
+        double c2 = 1.0;
+        const double c5 = c4;
+        c4 = x[i] - z;
+        for (int j = 0; j < i; ++j) {
+            const double c3 = x[i] - x[j];
+            c2 *= c3;
+            if (j == i - 1) {  // new node i, from node i-1's weights before they are updated
+                for (int d = mn; d >= 1; --d) c[i][d] = c1 * (d * c[i - 1][d - 1] - c5 * c[i - 1][d]) / c2;
+                c[i][0] = -c1 * c5 * c[i - 1][0] / c2;
+            }
+            for (int d = mn; d >= 1; --d) c[j][d] = (c4 * c[j][d] - d * c[j][d - 1]) / c3;
+            c[j][0] = c4 * c[j][0] / c3;
+        }
+        c1 = c2;
+    }
+}
+
+// One thread per (stencil size, evaluation node a).
+__global__ void fd_table_kernel(double* __restrict__ tab) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kNumN * kMaxN) return;
+    const int n = 3 + 2 * (t / kMaxN);
+    const int a = t % kMaxN;
+    if (a >= n) return;
+    double x[kMaxN];
+    for (int k = 0; k < n; ++k) x[k] = (double)k - 0.5 * (double)(n - 1);
+    double c[kMaxN][4];
+    fornberg_weights(n, x[a], x, c);
+    for (int d = 0; d < kFdDerivs; ++d)
+        for (int k = 0; k < n; ++k) tab[fd_index(n, d, a, k)] = c[k][d + 1];
+}
+
+std::mutex g_mu;
+const double* g_ptr[64] = {};
+
+}  // namespace
+
+hipError_t fd_table_init(const double** d_table_out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_fd_table))) != hipSuccess) return e;
+        hipLaunchKernelGGL(fd_table_kernel, dim3(1), dim3(kNumN * kMaxN), 0, nullptr, (double*)p);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+        g_ptr[dev] = (const double*)p;
+    }
+    *d_table_out = g_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace lmep

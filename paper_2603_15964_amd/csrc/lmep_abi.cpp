@@ -1,0 +1,508 @@
+// C-ABI of liblmep (declared in include/lmep.h): argument checks, grouping of
+// instances by kernel variant, scratch layout, upload of the device problem
+// tables, and the launch sequence of each entry point.  All arithmetic of the
+// method runs in the kernels; this file only plans and enqueues.
+#include "lmep.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "lmep_internal.hpp"
+
+using namespace lmep;
+
+namespace {
+
+thread_local char t_err[512] = "";
+thread_local double t_prof_build_ms = 0.0, t_prof_apply_ms = 0.0;
+thread_local int32_t t_prof_build_n = 0, t_prof_apply_n = 0;
+thread_local int64_t t_prof_matrices = 0, t_prof_squarings = 0;
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_err, sizeof(t_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(LMEP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int scheme_p(int scheme) { return scheme == LMEP_ETD2RK ? 2 : (scheme == LMEP_ETD1 ? 1 : 0); }
+bool frozen(const lmep_problem& q) { return q.nonlin == LMEP_NL_BURGERS_FROZEN; }
+
+int64_t weight_count(const lmep_problem& q) {
+    const int64_t kinds = 1 + scheme_p(q.scheme);
+    return frozen(q) ? kinds * q.n * q.N : kinds * q.n * q.n;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+// Checks of one instance (ERR_ARG for malformed input, ERR_UNSUPPORTED for a
+// well-formed combination the kernels do not implement).
+int check_problem(const lmep_problem& q, int k) {
+    if (q.n < 3 || q.n > kMaxN || (q.n % 2) == 0)
+        return fail(LMEP_ERR_ARG, "instance %d: stencil size n=%d must be odd, 3..%d", k, q.n, kMaxN);
+    if (q.N < q.n) return fail(LMEP_ERR_ARG, "instance %d: N=%lld < n=%d", k, (long long)q.N, q.n);
+    if (!(q.h > 0) || !finite(q.h)) return fail(LMEP_ERR_ARG, "instance %d: grid spacing h must be > 0", k);
+    if (!(q.dt > 0) || !finite(q.dt)) return fail(LMEP_ERR_ARG, "instance %d: dt must be > 0", k);
+    if (!finite(q.c) || !finite(q.nu) || !finite(q.delta) || !finite(q.react) || !finite(q.nl_coef) ||
+        !finite(q.bc_left) || !finite(q.bc_right))
+        return fail(LMEP_ERR_ARG, "instance %d: non-finite coefficient", k);
+    if (q.bc < 0 || q.bc > 2) return fail(LMEP_ERR_ARG, "instance %d: unknown boundary type %d", k, q.bc);
+    if (q.scheme < 0 || q.scheme > 2) return fail(LMEP_ERR_ARG, "instance %d: unknown scheme %d", k, q.scheme);
+    if (q.nonlin < 0 || q.nonlin > 3) return fail(LMEP_ERR_ARG, "instance %d: unknown nonlinearity %d", k, q.nonlin);
+    if (q.scheme == LMEP_LINEAR && q.nonlin != LMEP_NL_NONE)
+        return fail(LMEP_ERR_ARG, "instance %d: LINEAR scheme with a nonlinear term", k);
+    if (q.state_off < 0 || q.weight_off < 0) return fail(LMEP_ERR_ARG, "instance %d: negative offset", k);
+    if (q.n + scheme_p(q.scheme) > kMaxM)
+        return fail(LMEP_ERR_UNSUPPORTED, "instance %d: n + p = %d exceeds %d", k, q.n + scheme_p(q.scheme), kMaxM);
+    if (frozen(q) && q.scheme != LMEP_ETD1)
+        return fail(LMEP_ERR_UNSUPPORTED, "instance %d: frozen-velocity Burgers needs ETD1", k);
+    return LMEP_OK;
+}
+
+// Ranges [off, off + len) of distinct instances must not overlap.
+int check_disjoint(std::vector<std::pair<int64_t, int64_t>> r, const char* what) {
+    std::sort(r.begin(), r.end());
+    for (size_t k = 1; k < r.size(); ++k)
+        if (r[k].first < r[k - 1].first + r[k - 1].second)
+            return fail(LMEP_ERR_ARG, "%s ranges of two instances overlap", what);
+    return LMEP_OK;
+}
+
+int check_all(const lmep_problem* prob, int32_t count, bool weights_used) {
+    if (!prob || count <= 0) return fail(LMEP_ERR_ARG, "need count >= 1 problems");
+    std::vector<std::pair<int64_t, int64_t>> s, w;
+    for (int k = 0; k < count; ++k) {
+        int rc = check_problem(prob[k], k);
+        if (rc) return rc;
+        s.emplace_back(prob[k].state_off, prob[k].N);
+        w.emplace_back(prob[k].weight_off, weight_count(prob[k]));
+    }
+    int rc = check_disjoint(s, "state");
+    if (rc) return rc;
+    return weights_used ? check_disjoint(w, "weight") : LMEP_OK;
+}
+
+int64_t state_extent(const lmep_problem* prob, int32_t count) {
+    int64_t e = 0;
+    for (int k = 0; k < count; ++k) e = std::max(e, prob[k].state_off + prob[k].N);
+    return e;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Scratch layout.
+struct Layout {
+    size_t build_tab = 0, apply_tab = 0, state = 0, stage = 0, flag = 0, total = 0;
+};
+
+Layout layout(const lmep_problem* prob, int32_t count, int op) {
+    Layout L;
+    size_t off = 0;
+    const size_t tab = align256(sizeof(DevProb) * (size_t)count);
+    L.build_tab = off;
+    off += tab;
+    L.apply_tab = off;
+    off += tab;
+    if (op == 1) {
+        const size_t st = align256(sizeof(double) * (size_t)state_extent(prob, count));
+        L.state = off;
+        off += st;
+        bool rk2 = false;
+        for (int k = 0; k < count; ++k) rk2 |= prob[k].scheme == LMEP_ETD2RK;
+        L.stage = off;
+        if (rk2) off += st;
+    }
+    L.flag = off;
+    off += 256;
+    L.total = off;
+    return L;
+}
+
+DevProb to_dev(const lmep_problem& q, int index) {
+    DevProb d;
+    std::memset(&d, 0, sizeof(d));
+    d.N = q.N;
+    d.state_off = q.state_off;
+    d.weight_off = q.weight_off;
+    d.n = q.n;
+    d.bc = q.bc;
+    d.scheme = q.scheme;
+    d.nonlin = q.nonlin;
+    d.p = scheme_p(q.scheme);
+    d.frozen = frozen(q) ? 1 : 0;
+    d.index = index;
+    d.h = q.h;
+    d.dt = q.dt;
+    d.c = q.c;
+    d.nu = q.nu;
+    d.delta = q.delta;
+    d.react = q.react;
+    d.nl_coef = q.nl_coef;
+    d.bc_left = q.bc_left;
+    d.bc_right = q.bc_right;
+    return d;
+}
+
+// A launch group: a contiguous slice of a device table whose instances share
+// one kernel variant.
+struct Group {
+    int n = 0, p = 0, scheme = 0, nonlin = 0;
+    bool pernode = false;
+    int first = 0, count = 0;  // slice of the table
+    int64_t items = 0;         // matrices (build) or tiles (apply)
+};
+
+// Build groups: keyed by (n, p).  Instances selected by `want`.
+template <class Want>
+std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want, std::vector<DevProb>& tab) {
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (int k = 0; k < count; ++k)
+        if (want(prob[k])) by[{prob[k].n, scheme_p(prob[k].scheme)}].push_back(k);
+    std::vector<Group> groups;
+    for (auto& kv : by) {
+        Group g;
+        g.n = kv.first.first;
+        g.p = kv.first.second;
+        g.first = (int)tab.size();
+        int64_t items = 0;
+        for (int k : kv.second) {
+            DevProb d = to_dev(prob[k], k);
+            d.item_begin = items;
+            items += frozen(prob[k]) ? prob[k].N : prob[k].n;
+            tab.push_back(d);
+        }
+        g.count = (int)kv.second.size();
+        g.items = items;
+        groups.push_back(g);
+    }
+    return groups;
+}
+
+std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab) {
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
+    for (int k = 0; k < count; ++k)
+        by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : 0}].push_back(k);
+    std::vector<Group> groups;
+    for (auto& kv : by) {
+        Group g;
+        std::tie(g.n, g.scheme, g.nonlin, std::ignore) = kv.first;
+        g.pernode = std::get<3>(kv.first) != 0;
+        g.first = (int)tab.size();
+        int64_t tiles = 0;
+        for (int k : kv.second) {
+            DevProb d = to_dev(prob[k], k);
+            d.item_begin = tiles;
+            tiles += (prob[k].N + kApplyTile - 1) / kApplyTile;
+            tab.push_back(d);
+        }
+        g.count = (int)kv.second.size();
+        g.items = tiles;
+        groups.push_back(g);
+    }
+    return groups;
+}
+
+// Host staging for the device tables: pinned memory owned by the calling
+// thread, reused across calls; an event guards reuse until the previous copy
+// has been consumed.
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    ~Staging() {
+        if (pending && done) hipEventSynchronize(done);
+        if (host) hipHostFree(host);
+        if (done) hipEventDestroy(done);
+    }
+};
+thread_local Staging t_stage;
+
+int upload(const std::vector<DevProb>& a, const std::vector<DevProb>& b, void* d_a, void* d_b, hipStream_t s) {
+    const size_t na = a.size() * sizeof(DevProb), nb = b.size() * sizeof(DevProb);
+    Staging& st = t_stage;
+    if (!st.done) HIP_TRY(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
+    if (st.pending) {
+        HIP_TRY(hipEventSynchronize(st.done));
+        st.pending = false;
+    }
+    if (st.cap < na + nb) {
+        if (st.host) HIP_TRY(hipHostFree(st.host));
+        st.host = nullptr;
+        st.cap = 0;
+        const size_t cap = std::max<size_t>(na + nb, 1 << 16);
+        HIP_TRY(hipHostMalloc(&st.host, cap, hipHostMallocDefault));
+        st.cap = cap;
+    }
+    char* h = (char*)st.host;
+    if (na) std::memcpy(h, a.data(), na);
+    if (nb) std::memcpy(h + na, b.data(), nb);
+    if (na) HIP_TRY(hipMemcpyAsync(d_a, h, na, hipMemcpyHostToDevice, s));
+    if (nb) HIP_TRY(hipMemcpyAsync(d_b, h + na, nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(st.done, s));
+    st.pending = true;
+    return LMEP_OK;
+}
+
+// Scratch checks first (host only), then pick up any pending device error.
+int entry_checks(void* d_scratch, size_t scratch_bytes, size_t need) {
+    if (!d_scratch || scratch_bytes < need)
+        return fail(LMEP_ERR_SCRATCH, "scratch of %zu bytes needed, %zu given", need, d_scratch ? scratch_bytes : 0);
+    if (((uintptr_t)d_scratch) % 256 != 0) return fail(LMEP_ERR_ARG, "scratch must be 256-byte aligned");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "earlier device error: %s", hipGetErrorString(e));
+    return LMEP_OK;
+}
+
+// HIP events bracketing every build and apply launch (LMEP_F_PROFILE).  All
+// events are created before the first launch so that recording them costs
+// the host little and the host stays ahead of the device.
+struct Timer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> build, apply;
+    size_t nb = 0, na = 0;
+    ~Timer() {
+        for (auto& v : {&build, &apply})
+            for (auto& ev : *v) {
+                if (ev.first) hipEventDestroy(ev.first);
+                if (ev.second) hipEventDestroy(ev.second);
+            }
+    }
+    hipError_t reserve(size_t builds, size_t applies) {
+        if (!on) return hipSuccess;
+        build.assign(builds, {nullptr, nullptr});
+        apply.assign(applies, {nullptr, nullptr});
+        hipError_t e;
+        for (auto& v : {&build, &apply})
+            for (auto& ev : *v) {
+                if ((e = hipEventCreate(&ev.first)) != hipSuccess) return e;
+                if ((e = hipEventCreate(&ev.second)) != hipSuccess) return e;
+            }
+        return hipSuccess;
+    }
+    hipError_t mark(bool is_build, hipStream_t s, bool begin) {
+        if (!on) return hipSuccess;
+        auto& v = is_build ? build : apply;
+        size_t& k = is_build ? nb : na;
+        if (k >= v.size()) return hipErrorInvalidValue;
+        if (begin) return hipEventRecord(v[k].first, s);
+        return hipEventRecord(v[k++].second, s);
+    }
+};
+
+// Stream on which step loops are captured into a graph (the legacy default
+// stream cannot be captured); the graph itself is launched on the caller's
+// stream.  One per thread, default priority.
+struct CaptureStream {
+    hipStream_t s = nullptr;
+    ~CaptureStream() {
+        if (s) hipStreamDestroy(s);
+    }
+};
+thread_local CaptureStream t_capture;
+
+}  // namespace
+
+extern "C" {
+
+int64_t lmep_weight_count(const lmep_problem* prob) {
+    if (!prob || check_problem(*prob, 0)) return -1;
+    return weight_count(*prob);
+}
+
+size_t lmep_scratch_bytes(const lmep_problem* prob, int32_t count, int32_t op) {
+    if (op < 0 || op > 2 || check_all(prob, count, false)) return 0;
+    return layout(prob, count, op).total;
+}
+
+const char* lmep_last_error(void) { return t_err; }
+
+int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_ms, int32_t* apply_launches,
+                      int64_t* matrices, int64_t* squarings) {
+    if (build_ms) *build_ms = t_prof_build_ms;
+    if (build_launches) *build_launches = t_prof_build_n;
+    if (apply_ms) *apply_ms = t_prof_apply_ms;
+    if (apply_launches) *apply_launches = t_prof_apply_n;
+    if (matrices) *matrices = t_prof_matrices;
+    if (squarings) *squarings = t_prof_squarings;
+    return LMEP_OK;
+}
+
+int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_u, double* d_w, void* d_scratch,
+                       size_t scratch_bytes, void* hip_stream) {
+    int rc = check_all(prob, count, true);
+    if (rc) return rc;
+    if (!d_w) return fail(LMEP_ERR_ARG, "d_w is NULL");
+    for (int k = 0; k < count; ++k)
+        if (frozen(prob[k]) && !d_u) return fail(LMEP_ERR_ARG, "instance %d needs d_u (frozen velocity)", k);
+    const Layout L = layout(prob, count, 0);
+    if ((rc = entry_checks(d_scratch, scratch_bytes, L.total))) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double* fd = nullptr;
+    HIP_TRY(fd_table_init(&fd));
+    std::vector<DevProb> btab, none;
+    auto groups = plan_build(prob, count, [](const lmep_problem&) { return true; }, btab);
+    char* base = (char*)d_scratch;
+    if ((rc = upload(btab, none, base + L.build_tab, nullptr, s))) return rc;
+    const DevProb* dtab = (const DevProb*)(base + L.build_tab);
+    for (auto& g : groups)
+        HIP_TRY(launch_build(g.n, g.p, dtab + g.first, g.count, g.items, fd, d_u, d_w, nullptr, s));
+    return LMEP_OK;
+}
+
+int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
+              int32_t n_steps, uint32_t flags, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
+    int rc = check_all(prob, count, true);
+    if (rc) return rc;
+    if (!d_w || !d_u_in || !d_u_out) return fail(LMEP_ERR_ARG, "NULL weight or state pointer");
+    if (n_steps < 1) return fail(LMEP_ERR_ARG, "n_steps must be >= 1");
+    if (flags & ~(LMEP_F_GRAPH | LMEP_F_PERSISTENT | LMEP_F_CHECK_FINITE | LMEP_F_PROFILE | LMEP_F_COUNT))
+        return fail(LMEP_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if (flags & LMEP_F_PERSISTENT) return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT is not available");
+    if ((flags & LMEP_F_GRAPH) && (flags & (LMEP_F_PROFILE | LMEP_F_COUNT)))
+        return fail(LMEP_ERR_ARG, "LMEP_F_PROFILE / LMEP_F_COUNT cannot be combined with LMEP_F_GRAPH");
+    const int64_t ext = state_extent(prob, count);
+    {
+        const char *a = (const char*)d_u_in, *b = (const char*)d_u_out;
+        const size_t bytes = sizeof(double) * (size_t)ext;
+        if (a < b + bytes && b < a + bytes) return fail(LMEP_ERR_ARG, "d_u_in and d_u_out overlap");
+    }
+    const Layout L = layout(prob, count, 1);
+    if ((rc = entry_checks(d_scratch, scratch_bytes, L.total))) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double* fd = nullptr;
+    HIP_TRY(fd_table_init(&fd));
+
+    std::vector<DevProb> btab, atab;
+    auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab);
+    auto agroups = plan_apply(prob, count, atab);
+    char* base = (char*)d_scratch;
+    if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s))) return rc;
+    const DevProb* dbt = (const DevProb*)(base + L.build_tab);
+    const DevProb* dat = (const DevProb*)(base + L.apply_tab);
+    double* bufA = (double*)(base + L.state);
+    double* stage = (double*)(base + L.stage);
+
+    Timer timer;
+    timer.on = (flags & LMEP_F_PROFILE) != 0;
+    HIP_TRY(timer.reserve(bgroups.empty() ? 0 : (size_t)n_steps, (size_t)n_steps));
+    unsigned long long* counters = (flags & LMEP_F_COUNT) ? (unsigned long long*)(base + L.flag + 64) : nullptr;
+    if (counters) HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(unsigned long long), s));
+    const bool graph = (flags & LMEP_F_GRAPH) != 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipStream_t launch_stream = s;
+    if (graph) {
+        if (!t_capture.s) HIP_TRY(hipStreamCreateWithFlags(&t_capture.s, hipStreamNonBlocking));
+        s = t_capture.s;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    }
+
+    auto enqueue = [&]() -> int {
+        // destinations alternate between the scratch state and d_u_out so that
+        // the last step lands in d_u_out and no step works in place
+        for (int st = 0; st < n_steps; ++st) {
+            const double* src = (st == 0) ? d_u_in : (((n_steps - st) % 2 == 0) ? d_u_out : bufA);
+            double* dst = ((n_steps - 1 - st) % 2 == 0) ? d_u_out : bufA;
+            if (!bgroups.empty()) {
+                HIP_TRY(timer.mark(true, s, true));
+                for (auto& gr : bgroups)
+                    HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters, s));
+                HIP_TRY(timer.mark(true, s, false));
+            }
+            HIP_TRY(timer.mark(false, s, true));
+            for (auto& gr : agroups) {
+                if (gr.scheme == LMEP_ETD2RK) {
+                    HIP_TRY(launch_apply(gr.n, gr.scheme, gr.nonlin, gr.pernode, 0, dat + gr.first, gr.count, gr.items,
+                                         fd, d_w, src, nullptr, stage, s));
+                    HIP_TRY(launch_apply(gr.n, gr.scheme, gr.nonlin, gr.pernode, 1, dat + gr.first, gr.count, gr.items,
+                                         fd, d_w, src, stage, dst, s));
+                } else {
+                    HIP_TRY(launch_apply(gr.n, gr.scheme, gr.nonlin, gr.pernode, 0, dat + gr.first, gr.count, gr.items,
+                                         fd, d_w, src, nullptr, dst, s));
+                }
+            }
+            HIP_TRY(timer.mark(false, s, false));
+        }
+        return LMEP_OK;
+    };
+    rc = enqueue();
+    if (graph) {
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        s = launch_stream;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(ge, s);
+        if (ge) hipGraphExecDestroy(ge);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "graph launch: %s", hipGetErrorString(e));
+    } else if (rc) {
+        return rc;
+    }
+
+    if (timer.on) {
+        HIP_TRY(hipStreamSynchronize(s));
+        double bms = 0.0, ams = 0.0;
+        for (auto& ev : timer.build) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
+            bms += ms;
+        }
+        for (auto& ev : timer.apply) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
+            ams += ms;
+        }
+        t_prof_build_ms = bms;
+        t_prof_apply_ms = ams;
+        t_prof_build_n = (int32_t)timer.build.size();
+        t_prof_apply_n = (int32_t)timer.apply.size();
+    }
+    if (counters) {
+        unsigned long long hc[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        t_prof_matrices = (int64_t)hc[0];
+        t_prof_squarings = (int64_t)hc[1];
+    }
+
+    if (flags & LMEP_F_CHECK_FINITE) {
+        int* dflag = (int*)(base + L.flag);
+        HIP_TRY(hipMemsetAsync(dflag, 0, sizeof(int), s));
+        for (int k = 0; k < count; ++k)
+            HIP_TRY(launch_check_finite(d_u_out + prob[k].state_off, prob[k].N, dflag, s));
+        int hflag = 0;
+        HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hflag) return fail(LMEP_ERR_NONFINITE, "non-finite value in the result");
+    }
+    return LMEP_OK;
+}
+
+int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u_k, const double* d_lambda_next,
+                      double* d_lambda_k, double* d_grad, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
+    (void)prob; (void)count; (void)d_u_k; (void)d_lambda_next; (void)d_lambda_k; (void)d_grad;
+    (void)d_scratch; (void)scratch_bytes; (void)hip_stream;
+    return fail(LMEP_ERR_UNSUPPORTED, "lmep_adjoint_step is not available in this build");
+}
+
+}  // extern "C"

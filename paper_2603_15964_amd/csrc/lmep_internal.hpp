@@ -1,0 +1,68 @@
+// Internal declarations of liblmep: the device-side problem record, the
+// scratch layout, and the launchers each kernel file provides to the C-ABI
+// layer (lmep_abi.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lmep {
+
+constexpr int kMaxN = 15;     // largest stencil
+constexpr int kMaxM = 16;     // largest local matrix n + p (one 16-lane DPP row)
+constexpr int kNumN = 7;      // stencil sizes 3, 5, ..., 15
+constexpr int kFdDerivs = 3;  // first, second and third derivative tables
+
+// Device-side record of one instance, filled by the host from lmep_problem.
+// `item_begin` is the prefix sum of work items (matrices or tiles) over the
+// instances of one launch group, so a block finds its instance by a binary
+// search.  Kept at 128 bytes.
+struct DevProb {
+    int64_t N;
+    int64_t state_off;
+    int64_t weight_off;
+    int64_t item_begin;
+    int32_t n, bc, scheme, nonlin;
+    int32_t p, frozen, index, pad;
+    double h, dt, c, nu, delta, react, nl_coef, bc_left, bc_right;
+    double pad2[3];
+};
+static_assert(sizeof(DevProb) == 160, "DevProb layout");
+
+enum : int { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
+enum : int { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2 };
+enum : int { NL_NONE = 0, NL_BURGERS = 1, NL_KDV = 2, NL_AC = 3 };
+
+// Table of finite-difference weights on the centred integer stencil
+// x_k = k - (n-1)/2: fd[(n-3)/2][d][a][k] is the weight of node k for the
+// (d+1)-th derivative at node a.  Lives in a static device array per device.
+constexpr int kFdTableDoubles = kNumN * kFdDerivs * kMaxN * kMaxN;
+__host__ __device__ inline int fd_index(int n, int d, int a, int k) {
+    return ((((n - 3) / 2) * kFdDerivs + d) * kMaxN + a) * kMaxN + k;
+}
+
+// ---------------------------------------------------------------- launchers
+// Fill the per-device stencil table (blocking; once per device).
+hipError_t fd_table_init(const double** d_table_out);
+
+// Build weights for one group of instances sharing (n, p).  items = total
+// matrices of the group.  stats (nullable, profiling): stats[0] += matrices
+// built, stats[1] += squarings performed.
+hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t items,
+                        const double* fd, const double* d_u, double* d_w, unsigned long long* stats,
+                        hipStream_t stream);
+
+// One step stage over a group of instances sharing (n, scheme, nonlin, per-node).
+//   stage 0: LINEAR / ETD1 full step, or ETD2RK first stage (writes u_out = a)
+//   stage 1: ETD2RK second stage (reads u_in = u^k and u_stage = a)
+hipError_t launch_apply(int n, int scheme, int nonlin, bool pernode, int stage, const DevProb* d_probs,
+                        int nprob, int64_t tiles, const double* fd, const double* d_w, const double* d_u_in,
+                        const double* d_u_stage, double* d_u_out, hipStream_t stream);
+
+constexpr int kApplyTile = 256;  // nodes per apply block
+
+// Finite check: writes 1 into *d_flag if any of the count doubles is not finite.
+hipError_t launch_check_finite(const double* d_x, int64_t count, int* d_flag, hipStream_t stream);
+
+}  // namespace lmep

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/lmep.h declares, and rejects invalid arguments
+before touching the device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2603_15964_amd as lmep
+import workloads
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lmep.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lmep_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_are_exported():
+    lib = ctypes.CDLL(lmep.LIB_PATH)
+    names = _declared()
+    assert {"lmep_build_weights", "lmep_step", "lmep_adjoint_step"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(lmep.EXPORTED)
+
+
+def _structs(**over):
+    p, _ = workloads.burgers(N=64, n=7)
+    p.update(over)
+    return lmep.problem_array([p])
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(n=4), lmep.LMEP_ERR_ARG),
+    (dict(n=1), lmep.LMEP_ERR_ARG),
+    (dict(n=17), lmep.LMEP_ERR_ARG),
+    (dict(N=5), lmep.LMEP_ERR_ARG),
+    (dict(h=0.0), lmep.LMEP_ERR_ARG),
+    (dict(dt=-1.0), lmep.LMEP_ERR_ARG),
+    (dict(dt=float("nan")), lmep.LMEP_ERR_ARG),
+    (dict(nu=float("inf")), lmep.LMEP_ERR_ARG),
+    (dict(scheme="etd2rk"), lmep.LMEP_ERR_UNSUPPORTED),   # frozen velocity needs ETD1
+    (dict(n=15, nonlin="kdv", scheme="etd2rk"), lmep.LMEP_ERR_UNSUPPORTED),  # n + p = 17
+])
+def test_invalid_problems_rejected_before_any_device_work(over, code):
+    s = _structs(**over)
+    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 1, 0,
+                                  ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == code, lmep.lmep_last_error()
+    assert lmep.lmep_last_error()
+
+
+def test_bad_enums_and_flags():
+    s = _structs()
+    s[0].bc = 7
+    assert lmep.library().lmep_build_weights(s, 1, None, ctypes.c_void_p(8), None, 0, None) == lmep.LMEP_ERR_ARG
+    s = _structs()
+    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), 1, 0x100,
+                                  ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_ARG and "flag" in lmep.lmep_last_error()
+    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), 0, 0,
+                                  ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_ARG
+
+
+def test_scratch_and_overlap_checks():
+    s = _structs()
+    need = lmep.lmep_scratch_bytes(s, 1, lmep.OP_STEP)
+    assert need > 0
+    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24), 1, 0,
+                                  ctypes.c_void_p(256), need - 1, None)
+    assert rc == lmep.LMEP_ERR_SCRATCH
+    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 20), 1, 0,
+                                  ctypes.c_void_p(256), need, None)
+    assert rc == lmep.LMEP_ERR_ARG and "overlap" in lmep.lmep_last_error()
+    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24), 1, 0,
+                                  ctypes.c_void_p(260), need, None)
+    assert rc == lmep.LMEP_ERR_ARG and "aligned" in lmep.lmep_last_error()
+    # two instances whose states overlap
+    p, _ = workloads.burgers(N=64, n=7)
+    a = lmep.problem_array([lmep.to_struct(p, 0, 0), lmep.to_struct(p, 10, 5000)])
+    rc = lmep.library().lmep_build_weights(a, 2, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(256),
+                                           1 << 30, None)
+    assert rc == lmep.LMEP_ERR_ARG and "overlap" in lmep.lmep_last_error()
+
+
+def test_weight_counts_and_batch_packing():
+    p, _ = workloads.burgers(N=100, n=7)
+    assert lmep.lmep_weight_count(lmep.to_struct(p)) == 2 * 7 * 100
+    q, _ = workloads.kdv(N=64, n=9)
+    assert lmep.lmep_weight_count(lmep.to_struct(q)) == 3 * 9 * 9
+    probs, _ = workloads.allen_cahn_batch(count=5, n_min=20, n_max=40)
+    b = lmep.Batch(probs, device="cpu")
+    assert b.state_size == sum(x["N"] for x in probs)
+    assert all(o % 32 == 0 for o in b.weight_off)
+    assert lmep.lmep_scratch_bytes(b.structs, b.count, lmep.OP_BUILD) > 0

@@ -1,0 +1,235 @@
+"""GPU parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (FP64): weights 1e-12 relative per harvested row (infinity norm),
+one step 1e-13 and final states 1e-10 relative to the state's max norm, on
+readings whose step does not amplify rounding (see test_stability_readings).
+Batched vs single-instance launches and graph replay vs eager launches must
+agree bitwise (same kernels, same summation order).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_15964_amd as lmep
+import workloads
+from workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _print_case(*a):
+    print("case:", *a, flush=True)
+
+
+def row_rel_err(got, want):
+    """max over rows of ||got - want||_inf / ||want||_inf (rows = last axis)."""
+    num = np.max(np.abs(got - want), axis=-1)
+    den = np.max(np.abs(want), axis=-1)
+    return float(np.max(num / den))
+
+
+def state_rel_err(got, want):
+    return float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+
+
+def gpu_weights(p, u=None):
+    b = lmep.Batch([p], device=DEV)
+    w = b.empty_weights()
+    b.build_weights(w, b.pack(u) if u is not None else None)
+    torch.cuda.synchronize()
+    return b.unpack_weights(w)[0]
+
+
+def gpu_run(problems, states, steps, flags=0):
+    b = lmep.Batch(problems, device=DEV)
+    w = b.empty_weights()
+    u0 = b.pack(states)
+    if any(p.get("nonlin") != "burgers_frozen" for p in problems):
+        b.build_weights(w, u0)
+    out = b.step(w, u0, steps, flags)
+    torch.cuda.synchronize()
+    return b.unpack(out)
+
+
+def oracle_rows(p):
+    """Oracle harvest of every stencil row r: shape [kinds, r, k] (a Dirichlet
+    grid of exactly n nodes harvests row r at node r)."""
+    q = dict(p, N=p["n"], bc="dirichlet", nonlin="none" if p.get("nonlin") == "burgers_frozen" else p["nonlin"])
+    w = oracle.build_weights(q)  # [node, kind, k]
+    return np.transpose(w, (1, 0, 2))
+
+
+# ------------------------------------------------------------ weights ----
+STATIONARY = []
+for n in (3, 5, 7, 9, 11, 13, 15):
+    for scheme in ("linear", "etd1", "etd2rk"):
+        if n + workloads.stencil_p(scheme) > 16:
+            continue
+        STATIONARY.append((n, scheme))
+
+
+@pytest.mark.parametrize("n,scheme", STATIONARY)
+def test_stationary_weights_all_rows(n, scheme):
+    _print_case("stationary weights", n, scheme)
+    h = 0.3
+    for (cfl, mu, tau) in ((0.8, 0.2, 0.02), (-1.3, 0.05, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.05)):
+        dt = 0.01
+        p = make_problem(N=max(64, n), n=n, bc="dirichlet", h=h, dt=dt, c=cfl * h / dt, nu=mu * h * h / dt,
+                         delta=tau * h ** 3 / dt, scheme=scheme, nonlin="none")
+        got = gpu_weights(p)
+        want = oracle_rows(p)
+        assert got.shape == want.shape
+        err = row_rel_err(got, want)
+        assert err <= 1e-12, (cfl, mu, tau, err)
+
+
+def test_workload_operators_weights():
+    cases = [workloads.advection_diffusion(N=256, cfl=2.0)[0], workloads.advection_diffusion(N=256, cfl=1.0)[0],
+             workloads.kdv(N=4096)[0], workloads.kdv(N=4096, tau=0.05)[0]]
+    probs, _ = workloads.allen_cahn_batch(count=16, n_min=512, n_max=65536)
+    seen = set()
+    for q in probs:
+        if (q["n"], q["bc"]) not in seen:
+            seen.add((q["n"], q["bc"]))
+            cases.append(q)
+    for p in cases:
+        _print_case("workload weights", p["n"], p["scheme"], p["bc"])
+        err = row_rel_err(gpu_weights(p), oracle_rows(p))
+        assert err <= 1e-12, (p["n"], p["scheme"], err)
+
+
+@pytest.mark.parametrize("N,n,bc", [(300, 7, "dirichlet"), (257, 9, "dirichlet"), (64, 5, "periodic"),
+                                    (100, 15, "dirichlet"), (50, 7, "neumann")])
+def test_per_node_weights(N, n, bc):
+    _print_case("per-node weights", N, n, bc)
+    if bc == "dirichlet":
+        p, u = workloads.burgers(N=N, n=n)
+    else:
+        p, u = workloads.burgers(N=N, n=n)
+        p = dict(p, bc=bc)
+        u = 0.5 * np.sin(np.linspace(0, 2 * np.pi, N, endpoint=False)) + 0.3
+    got = gpu_weights(p, u)                       # [kind, k, N]
+    want = np.transpose(oracle.build_weights(p, u), (1, 2, 0))
+    err = row_rel_err(np.transpose(got, (0, 2, 1)), np.transpose(want, (0, 2, 1)))
+    assert err <= 1e-12, err
+
+
+# ----------------------------------------------------------- one step ----
+ONE_STEP = [
+    ("adv-diff periodic CFL2 (literal)", lambda: workloads.advection_diffusion(cfl=2.0)),
+    ("adv-diff periodic CFL1", lambda: workloads.advection_diffusion(cfl=1.0)),
+    ("adv-diff dirichlet", lambda: (make_problem(N=300, n=7, bc="dirichlet", h=0.1, dt=0.05, c=0.8, nu=0.02,
+                                                 scheme="linear", bc_left=0.2, bc_right=-0.1),
+                                    np.cos(np.linspace(0, 3, 300)))),
+    ("burgers dirichlet n7", lambda: workloads.burgers(N=1000, n=7)),
+    ("burgers dirichlet n9", lambda: workloads.burgers(N=777, n=9, nu=5e-3)),
+    ("burgers periodic n5", lambda: (dict(workloads.burgers(N=512, n=5)[0], bc="periodic"),
+                                     np.sin(np.linspace(0, 2 * np.pi, 512, endpoint=False)))),
+    ("kdv periodic etd2rk", lambda: workloads.kdv(N=2048, tau=0.05)),
+    ("kdv periodic etd1", lambda: (dict(workloads.kdv(N=2048, tau=0.05)[0], scheme="etd1"),
+                                   workloads.kdv(N=2048, tau=0.05)[1])),
+    ("allen-cahn periodic", lambda: (workloads.allen_cahn_batch(count=1, n_min=700, n_max=700)[0][0],
+                                     workloads.allen_cahn_batch(count=1, n_min=700, n_max=700)[1][0])),
+    ("allen-cahn neumann etd2rk", lambda: (dict(make_problem(N=500, n=9, bc="neumann", h=2 / 499, nu=1e-4,
+                                                             dt=0.5 * (2 / 499) ** 2 / 1e-4, scheme="etd2rk",
+                                                             nonlin="allen_cahn", nl_coef=1.0)),
+                                           np.random.default_rng(3).uniform(-0.1, 0.1, 500))),
+    ("diffusion dirichlet etd1 react", lambda: (make_problem(N=260, n=11, bc="dirichlet", h=0.05, dt=0.001, nu=0.5,
+                                                             react=-0.7, scheme="etd1", nonlin="allen_cahn",
+                                                             nl_coef=0.3, bc_left=1.0, bc_right=-1.0),
+                                                np.tanh(np.linspace(-3, 3, 260)))),
+]
+
+
+@pytest.mark.parametrize("name,make", ONE_STEP, ids=[c[0] for c in ONE_STEP])
+def test_one_step(name, make):
+    _print_case("one step", name)
+    p, u0 = make()
+    got = gpu_run([p], [u0], 1)[0]
+    want = oracle.run(p, u0, 1)
+    assert state_rel_err(got, want) <= 1e-13
+
+
+# -------------------------------------------------------- multi step ----
+def _ac_subset(k, nmax=3000, seed=workloads.BASE_SEED + 3):
+    probs, states = workloads.allen_cahn_batch(count=k, n_min=512, n_max=nmax, seed=seed)
+    return probs, states
+
+
+MULTI = [
+    ("advection-diffusion CFL1 N256 100 steps", lambda: ([workloads.advection_diffusion(cfl=1.0)[0]],
+                                                         [workloads.advection_diffusion(cfl=1.0)[1]], 100)),
+    ("advection CFL2 nu=0 exact shift 100 steps", lambda: ([dict(workloads.advection_diffusion(cfl=2.0)[0], nu=0.0)],
+                                                           [workloads.advection_diffusion(cfl=2.0)[1]], 100)),
+    ("burgers N4096 n7 100 steps", lambda: ([workloads.burgers(N=4096)[0]], [workloads.burgers(N=4096)[1]], 100)),
+    ("kdv N2048 tau0.05 200 steps", lambda: ([workloads.kdv(N=2048, tau=0.05)[0]],
+                                             [workloads.kdv(N=2048, tau=0.05)[1]], 200)),
+    ("allen-cahn batch of 6, 60 steps", lambda: (*_ac_subset(6), 60)),
+    ("burgers n9 nu5e-3 N3000 60 steps", lambda: ([workloads.burgers(N=3000, n=9, nu=5e-3)[0]],
+                                                  [workloads.burgers(N=3000, n=9, nu=5e-3)[1]], 60)),
+]
+
+
+@pytest.mark.parametrize("name,make", MULTI, ids=[c[0] for c in MULTI])
+def test_multi_step(name, make):
+    _print_case("multi step", name)
+    probs, states, steps = make()
+    got = gpu_run(probs, states, steps)
+    for p, u0, g in zip(probs, states, got):
+        want = oracle.run(p, u0, steps)
+        assert state_rel_err(g, want) <= 1e-10, (p["n"], p["N"])
+
+
+def test_batched_equals_single_and_graph_equals_eager():
+    _print_case("batched vs single, graph vs eager")
+    probs, states = _ac_subset(5, nmax=2000)
+    probs.append(workloads.burgers(N=1500)[0])
+    states.append(workloads.burgers(N=1500)[1])
+    steps = 7
+    batched = gpu_run(probs, states, steps)
+    graphed = gpu_run(probs, states, steps, flags=lmep.LMEP_F_GRAPH)
+    for k, (p, u0) in enumerate(zip(probs, states)):
+        single = gpu_run([p], [u0], steps)[0]
+        assert np.array_equal(single, batched[k])
+        assert np.array_equal(graphed[k], batched[k])
+
+
+def test_check_finite_flag():
+    _print_case("check finite")
+    p, u0 = workloads.burgers(N=512)
+    u0 = u0.copy()
+    u0[100] = np.nan
+    with pytest.raises(lmep.LmepError) as e:
+        gpu_run([p], [u0], 2, flags=lmep.LMEP_F_CHECK_FINITE)
+    assert e.value.code == lmep.LMEP_ERR_NONFINITE
+    p, u0 = workloads.burgers(N=512)
+    gpu_run([p], [u0], 2, flags=lmep.LMEP_F_CHECK_FINITE)
+
+
+# ---------------------------------------------------------- full size ----
+def test_full_size_burgers_65536():
+    """The Burgers workload at its full size, in the launch configuration the
+    benchmark times (one instance, weights rebuilt every step), for 20 steps."""
+    _print_case("full size burgers N=65536 n=7")
+    p, u0 = workloads.burgers()
+    steps = 20
+    got = gpu_run([p], [u0], steps, flags=lmep.LMEP_F_GRAPH)[0]
+    want = oracle.run(p, u0, steps)
+    assert state_rel_err(got, want) <= 1e-10
+
+
+def test_full_size_kdv_conservation_and_sample():
+    """KdV at N = 2^20: a few steps against the oracle, and the periodic
+    conservative form keeps sum(u) to rounding over 50 steps."""
+    _print_case("full size kdv N=2^20")
+    p, u0 = workloads.kdv()
+    got = gpu_run([p], [u0], 3)[0]
+    assert state_rel_err(got, oracle.run(p, u0, 3)) <= 1e-12
+    got50 = gpu_run([p], [u0], 50)[0]
+    assert abs(got50.sum() - u0.sum()) <= 1e-11 * np.sum(np.abs(u0))
