@@ -40,37 +40,61 @@ __device__ __forceinline__ void add_identity(double (&X)[M], double a, int lane)
     for (int j = 0; j < M; ++j) X[j] += (j == lane) ? a : 0.0;
 }
 
-// P = V + U, Q = V - U for the degree-13 approximant of A (row matrices).
+// P = V + U, Q = V - U for the degree-13 approximant of A (row matrices):
+//   U = A (A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I)
+//   V =    A6 (c12 A6 + c10 A4 + c8 A2) + c6 A6 + c4 A4 + c2 A2 + c0 I
+// The inner products accumulate into the linear combination they are added to.
 template <int M, int NB>
 __device__ __forceinline__ void pade13(const double (&A)[M], double (&P)[M], double (&Q)[M], int lane) {
     constexpr double c[14] = {pade13c(0), pade13c(1), pade13c(2),  pade13c(3),  pade13c(4),
                               pade13c(5), pade13c(6), pade13c(7),  pade13c(8),  pade13c(9),
                               pade13c(10), pade13c(11), pade13c(12), pade13c(13)};
-    double A2[M], A4[M], A6[M], T[M];
+    double A2[M], A4[M], A6[M], T[M], W[M];
     mul<M, NB>(A, A, A2);
     mul<M, NB>(A2, A2, A4);
     mul<M, NB>(A4, A2, A6);
-    // U = A (A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I)
-#pragma unroll
-    for (int j = 0; j < M; ++j) T[j] = c[13] * A6[j] + c[11] * A4[j] + c[9] * A2[j];
-    mul<M, NB>(A6, T, P);  // P used as scratch for the inner sum
-#pragma unroll
-    for (int j = 0; j < M; ++j) P[j] += c[7] * A6[j] + c[5] * A4[j] + c[3] * A2[j];
-    add_identity(P, c[1], lane);
-    mul<M, NB>(A, P, T);  // T = U
-    // V = A6 (c12 A6 + c10 A4 + c8 A2) + c6 A6 + c4 A4 + c2 A2 + c0 I
-#pragma unroll
-    for (int j = 0; j < M; ++j) P[j] = c[12] * A6[j] + c[10] * A4[j] + c[8] * A2[j];
-#pragma unroll
-    for (int j = 0; j < M; ++j) Q[j] = c[6] * A6[j] + c[4] * A4[j] + c[2] * A2[j];
-    add_identity(Q, c[0], lane);
-    mul_acc<M, NB>(A6, P, Q);  // Q = V
 #pragma unroll
     for (int j = 0; j < M; ++j) {
+        T[j] = c[13] * A6[j] + c[11] * A4[j] + c[9] * A2[j];
+        W[j] = c[7] * A6[j] + c[5] * A4[j] + c[3] * A2[j];
+    }
+    add_identity(W, c[1], lane);
+    mul_acc<M, NB>(A6, T, W);  // W = inner factor of U
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        T[j] = c[12] * A6[j] + c[10] * A4[j] + c[8] * A2[j];
+        Q[j] = c[6] * A6[j] + c[4] * A4[j] + c[2] * A2[j];
+    }
+    add_identity(Q, c[0], lane);
+    mul_acc<M, NB>(A6, T, Q);  // Q = V
+    mul<M, NB>(A, W, T);  // T = U
+#pragma unroll
+    for (int j = 0; j < M; ++j) {  // V and U are formed separately: V - U may cancel
         const double v = Q[j], u = T[j];
         P[j] = v + u;
         Q[j] = v - u;
     }
+}
+
+// Column `col` of the row matrix X, one entry per lane (lane i gets X[i][col]).
+template <int M>
+__device__ __forceinline__ double column(const double (&X)[M], int col) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) v = (k == col) ? X[k] : v;
+    return v;
+}
+
+// (X * X)[:, col] given the column v = X[:, col] distributed over the lanes.
+template <int M>
+__device__ __forceinline__ double square_column(const double (&X)[M], double v) {
+    double c = 0.0;
+    exec_guard();
+    sfor<M>([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        fmac_b1<K>(c, v, X[K]);
+    });
+    return c;
 }
 
 template <int NN, int PP>
@@ -125,18 +149,27 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
 
     double X[M], Q[M];
     pade13<M, NN>(A, X, Q, lane);
-    solve_inplace<M>(Q, X, lane);
-    // s squarings, alternating between X and A
+    solve_inplace<M, NN>(Q, X, lane);
+    // s squarings, alternating between X and A; only the harvested columns
+    // (r and the augmented ones) of the last square are formed
     int q = s;
-    while (q >= 2) {
+    while (q >= 3) {
         mul<M, NN>(X, X, A);
         mul<M, NN>(A, A, X);
         q -= 2;
     }
-    if (q == 1) {
+    if (q == 2) {
         mul<M, NN>(X, X, A);
 #pragma unroll
         for (int j = 0; j < M; ++j) X[j] = A[j];
+    }
+    double w0 = column(X, r), w1 = 0.0, w2 = 0.0;
+    if constexpr (PP >= 1) w1 = X[NN];
+    if constexpr (PP == 2) w2 = X[NN + 1];
+    if (q >= 1) {
+        w0 = square_column(X, w0);
+        if constexpr (PP >= 1) w1 = square_column(X, w1);
+        if constexpr (PP == 2) w2 = square_column(X, w2);
     }
 
     if (stats && lane == 0) {  // profiling only: matrices built and squarings done
@@ -144,19 +177,16 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
         atomicAdd(stats + 1, (unsigned long long)s);
     }
     if (lane >= NN) return;
-    double w0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < NN; ++k) w0 = (k == r) ? X[k] : w0;
     double* __restrict__ wb = w + P.weight_off;
     if (frozen) {
         const int64_t N = P.N;
         wb[(int64_t)lane * N + node] = w0;
-        if constexpr (PP >= 1) wb[(int64_t)(NN + lane) * N + node] = X[NN];
-        if constexpr (PP == 2) wb[(int64_t)(2 * NN + lane) * N + node] = X[NN + 1] / dt;
+        if constexpr (PP >= 1) wb[(int64_t)(NN + lane) * N + node] = w1;
+        if constexpr (PP == 2) wb[(int64_t)(2 * NN + lane) * N + node] = w2 / dt;
     } else {
         wb[r * NN + lane] = w0;
-        if constexpr (PP >= 1) wb[(NN + r) * NN + lane] = X[NN];
-        if constexpr (PP == 2) wb[(2 * NN + r) * NN + lane] = X[NN + 1] / dt;
+        if constexpr (PP >= 1) wb[(NN + r) * NN + lane] = w1;
+        if constexpr (PP == 2) wb[(2 * NN + r) * NN + lane] = w2 / dt;
     }
 }
 

@@ -169,25 +169,30 @@ __device__ __forceinline__ double recip(double x) {
 // denominators are well conditioned and, for these block-triangular local
 // matrices, elimination in natural order keeps growth near 1.  Rows are
 // eliminated downwards, then upwards with the unnormalised pivot rows, and
-// each lane divides its own row by its pivot once at the end.
-template <int M>
+// each lane divides its own row by its pivot once at the end.  Q and P are
+// block upper triangular with the augmented block (rows and columns >= NB)
+// upper triangular, so downward steps on augmented pivots and the left
+// columns of augmented pivot rows are skipped.
+template <int M, int NB>
 __device__ __forceinline__ void solve_inplace(double (&Q)[M], double (&P)[M], int lane) {
     exec_guard();
     double own_pivot = 1.0;
+    double rp[M];
     sfor<M>([&](auto kc) {
         constexpr int K = decltype(kc)::value;
         own_pivot = (lane == K) ? Q[K] : own_pivot;
-        const double rp = recip(bcast<K>(Q[K]));
-        const double l = (lane > K) ? -Q[K] * rp : 0.0;
-        fmac_cols<M, K, K + 1, M>(Q, Q, l);
-        fmac_cols<M, K, 0, M>(P, P, l);
+        rp[K] = recip(bcast<K>(Q[K]));
+        if constexpr (K < NB) {
+            const double l = (lane > K) ? -Q[K] * rp[K] : 0.0;
+            fmac_cols<M, K, K + 1, M>(Q, Q, l);
+            fmac_cols<M, K, 0, M>(P, P, l);
+        }
     });
     sfor<M>([&](auto kc) {
         constexpr int K = M - 1 - decltype(kc)::value;
         if constexpr (K > 0) {
-            const double rp = recip(bcast<K>(Q[K]));
-            const double l = (lane < K) ? -Q[K] * rp : 0.0;
-            fmac_cols<M, K, 0, M>(P, P, l);
+            const double l = (lane < K) ? -Q[K] * rp[K] : 0.0;
+            fmac_cols<M, K, (K < NB) ? 0 : NB, M>(P, P, l);
         }
     });
     const double inv = recip(own_pivot);
