@@ -108,7 +108,15 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Scratch layout.
 struct Layout {
     size_t build_tab = 0, apply_tab = 0, state = 0, stage = 0, flag = 0, total = 0;
+    size_t g = 0, ghat = 0, ws = 0, dparam = 0, part = 0;  // reverse step
+    int ws_stride = 0;
 };
+
+int64_t total_tiles(const lmep_problem* prob, int32_t count) {
+    int64_t t = 0;
+    for (int k = 0; k < count; ++k) t += (prob[k].N + kApplyTile - 1) / kApplyTile;
+    return t;
+}
 
 Layout layout(const lmep_problem* prob, int32_t count, int op) {
     Layout L;
@@ -126,6 +134,22 @@ Layout layout(const lmep_problem* prob, int32_t count, int op) {
         for (int k = 0; k < count; ++k) rk2 |= prob[k].scheme == LMEP_ETD2RK;
         L.stage = off;
         if (rk2) off += st;
+    }
+    if (op == 2) {
+        const size_t ext = (size_t)state_extent(prob, count);
+        int nmax = 3;
+        for (int k = 0; k < count; ++k) nmax = std::max(nmax, (int)prob[k].n);
+        L.ws_stride = 2 * nmax;
+        L.g = off;
+        off += align256(sizeof(double) * ext);
+        L.ghat = off;
+        off += align256(sizeof(double) * ext);
+        L.ws = off;
+        off += align256(sizeof(double) * ext * (size_t)L.ws_stride);
+        L.dparam = off;
+        off += align256(sizeof(double) * 3 * ext);
+        L.part = off;
+        off += align256(sizeof(double) * 3 * (size_t)total_tiles(prob, count));
     }
     L.flag = off;
     off += 256;
@@ -500,9 +524,81 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
 
 int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u_k, const double* d_lambda_next,
                       double* d_lambda_k, double* d_grad, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
-    (void)prob; (void)count; (void)d_u_k; (void)d_lambda_next; (void)d_lambda_k; (void)d_grad;
-    (void)d_scratch; (void)scratch_bytes; (void)hip_stream;
-    return fail(LMEP_ERR_UNSUPPORTED, "lmep_adjoint_step is not available in this build");
+    int rc = check_all(prob, count, false);
+    if (rc) return rc;
+    for (int k = 0; k < count; ++k) {
+        const lmep_problem& q = prob[k];
+        if (q.scheme == LMEP_ETD2RK || q.nonlin == LMEP_NL_KDV)
+            return fail(LMEP_ERR_UNSUPPORTED, "instance %d: the reverse step covers LINEAR and ETD1 without KdV", k);
+    }
+    if (!d_u_k || !d_lambda_next || !d_lambda_k || !d_grad) return fail(LMEP_ERR_ARG, "NULL pointer argument");
+    const int64_t ext = state_extent(prob, count);
+    {
+        const char *a = (const char*)d_lambda_next, *b = (const char*)d_lambda_k;
+        const size_t bytes = sizeof(double) * (size_t)ext;
+        if (a < b + bytes && b < a + bytes) return fail(LMEP_ERR_ARG, "d_lambda_next and d_lambda_k overlap");
+    }
+    const Layout L = layout(prob, count, 2);
+    if ((rc = entry_checks(d_scratch, scratch_bytes, L.total))) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double* fd = nullptr;
+    HIP_TRY(fd_table_init(&fd));
+
+    // groups by (n, p): a node table and a tile table with the same instance order
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (int k = 0; k < count; ++k) by[{prob[k].n, scheme_p(prob[k].scheme)}].push_back(k);
+    std::vector<DevProb> ntab, ttab;
+    struct G {
+        int n, p, first, cnt;
+        int64_t nodes, tiles;
+    };
+    std::vector<G> groups;
+    int64_t tile_base = 0;
+    for (auto& kv : by) {
+        G g{kv.first.first, kv.first.second, (int)ntab.size(), (int)kv.second.size(), 0, 0};
+        for (int k : kv.second) {
+            DevProb d = to_dev(prob[k], k);
+            d.item_begin = g.nodes;
+            ntab.push_back(d);
+            d.item_begin = tile_base + g.tiles;  // global tile index: rows of the partial-sum array
+            ttab.push_back(d);
+            g.nodes += prob[k].N;
+            g.tiles += (prob[k].N + kApplyTile - 1) / kApplyTile;
+        }
+        // tile tables are searched from the group's first tile
+        for (int q = g.first; q < g.first + g.cnt; ++q) ttab[q].item_begin -= tile_base;
+        groups.push_back(g);
+        tile_base += g.tiles;
+    }
+    char* base = (char*)d_scratch;
+    if ((rc = upload(ntab, ttab, base + L.build_tab, base + L.apply_tab, s))) return rc;
+    const DevProb* dn = (const DevProb*)(base + L.build_tab);
+    const DevProb* dtt = (const DevProb*)(base + L.apply_tab);
+    int64_t part_base = 0;
+    for (auto& g : groups) {
+        AdjointLaunch a;
+        a.n = g.n;
+        a.p = g.p;
+        a.node_probs = dn + g.first;
+        a.tile_probs = dtt + g.first;
+        a.nprob = g.cnt;
+        a.tiles = g.tiles;
+        a.nodes = g.nodes;
+        a.fd = fd;
+        a.u = d_u_k;
+        a.lam = d_lambda_next;
+        a.lam_out = d_lambda_k;
+        a.grad = d_grad;
+        a.g = (double*)(base + L.g);
+        a.ghat = (double*)(base + L.ghat);
+        a.ws = (double*)(base + L.ws);
+        a.ws_stride = L.ws_stride;
+        a.dparam = (double*)(base + L.dparam);
+        a.part = (double*)(base + L.part) + 3 * part_base;
+        HIP_TRY(launch_adjoint(a, s));
+        part_base += g.tiles;
+    }
+    return LMEP_OK;
 }
 
 }  // extern "C"

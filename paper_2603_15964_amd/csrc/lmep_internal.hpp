@@ -62,6 +62,30 @@ hipError_t launch_apply(int n, int scheme, int nonlin, bool pernode, int stage, 
 
 constexpr int kApplyTile = 256;  // nodes per apply block
 
+// One group (same n and p) of a reverse step.  tile_probs: item_begin =
+// prefix of 256-node tiles; node_probs: the same instances with item_begin =
+// prefix of nodes.  Scratch arrays are indexed by state_off (ws by
+// state_off * ws_stride, dparam by 3 * state_off, part by 3 * tile).
+struct AdjointLaunch {
+    int n = 0, p = 0;
+    const DevProb* tile_probs = nullptr;
+    const DevProb* node_probs = nullptr;
+    int nprob = 0;
+    int64_t tiles = 0, nodes = 0;
+    const double* fd = nullptr;
+    const double* u = nullptr;
+    const double* lam = nullptr;
+    double* lam_out = nullptr;
+    double* grad = nullptr;
+    double* g = nullptr;
+    double* ghat = nullptr;
+    double* ws = nullptr;
+    int ws_stride = 0;
+    double* dparam = nullptr;
+    double* part = nullptr;
+};
+hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t stream);
+
 // Finite check: writes 1 into *d_flag if any of the count doubles is not finite.
 hipError_t launch_check_finite(const double* d_x, int64_t count, int* d_flag, hipStream_t stream);
 
