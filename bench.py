@@ -48,7 +48,30 @@ def make_workload(name: str):
     if name == "advection_diffusion":
         p, u0 = workloads.advection_diffusion()
         return [p], [u0], "periodic advection-diffusion N=256 n=5 CFL 2, LINEAR"
+    if name == "burgers_adjoint":
+        p, pt, u0s = workloads.burgers_adjoint_batch()
+        return ([p] * len(u0s), u0s,
+                "adjoint: 64 Burgers trajectories N=262144 n=9, ETD1 frozen velocity, forward + checkpointed reverse")
     raise SystemExit(f"unknown workload {name}")
+
+
+def bench_adjoint(problems, states, steps, every=50):
+    """Forward with checkpoints + reverse through lmep_adjoint_step; returns
+    (seconds, node-steps) with node-steps = nodes x steps."""
+    import torch
+    import paper_2603_15964_amd as lmep
+    from paper_2603_15964_amd import autograd as lad
+    batch = lmep.Batch(problems, device="cuda:0")
+    u0 = batch.pack(states).requires_grad_(True)
+    nu = torch.tensor([p["nu"] for p in problems], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    target = torch.zeros_like(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uT = lad.solve(batch, u0, steps, nu=nu, checkpoint_every=every)
+    loss = 0.5 * torch.sum((uT - target) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, batch.state_size * steps
 
 
 def cpu_baseline(problem, u0, budget_s: float = 15.0):
@@ -86,6 +109,18 @@ def main():
 
     problems, states, desc = make_workload(args.workload)
     dev = "cuda:0"
+    if args.workload == "burgers_adjoint":
+        bench_adjoint(problems, states, max(1, args.warmup), every=max(1, args.warmup))  # warm-up
+        secs, node_steps = bench_adjoint(problems, states, args.steps)
+        out = {"metric": "node-steps/s (weight build+apply, FP64), adjoint: forward + checkpointed reverse",
+               "value": node_steps / secs, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": secs * 1e3 / args.steps, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": desc, "instances": len(problems), "nodes": sum(p["N"] for p in problems),
+                          "checkpoint_every": 50},
+               "roofline": None}
+        print(json.dumps(out), flush=True)
+        return
     batch = lmep.Batch(problems, device=dev)
     w = batch.empty_weights()
     u0 = batch.pack(states)
