@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--workload", default="burgers")
     ap.add_argument("--graph", action="store_true", help="replay the step loop from a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (calibrates byte counters)")
     ap.add_argument("--skip-count", action="store_true",
                     help="skip the squaring-count pass (its atomics would show up in a kernel trace)")
     args = ap.parse_args()
@@ -106,6 +108,15 @@ def main():
 
     import torch
     import paper_2603_15964_amd as lmep
+
+    if args.copy_probe:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 8, "copies": 3}), flush=True)
+        return
 
     problems, states, desc = make_workload(args.workload)
     dev = "cuda:0"
@@ -155,7 +166,7 @@ def main():
     prof = lmep.lmep_profile_last()
     roof = None
     extra = {"gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3}
-    apply_bytes = {"burgers": 128.0, "kdv": 40.0, "allen_cahn_batch": 16.0, "advection_diffusion": 16.0}
+    apply_bytes = {"burgers": 128.0, "kdv": 16.0, "allen_cahn_batch": 16.0, "advection_diffusion": 16.0}
     if frozen and prof["build_launches"] > 0 and prof["matrices"] > 0:
         p0 = problems[0]
         m = p0["n"] + {"linear": 0, "etd1": 1, "etd2rk": 2}[p0["scheme"]]

@@ -33,7 +33,7 @@ namespace lmep {
 namespace {
 
 constexpr double kTheta13 = 5.371920351148152;  // Higham 2005, Table 2.3
-constexpr int T = 256;
+constexpr int T = kAdjTile;
 
 constexpr double pade13c(int j) {
     double c = 1.0;

@@ -2,205 +2,242 @@
 // integrator, node by node, with the harvested weights (Sec. 3.1 step 3):
 //   LINEAR : u+_i = W0_i . u_S
 //   ETD1   : u+_i = W0_i . u_S + W1_i . N_S
-//   ETD2RK : a_i  = W0_i . u_S + W1_i . N(u)_S                    (stage 0)
-//            u+_i = a_i + W2_i . (N(a) - N(u))_S                  (stage 1)
+//   ETD2RK : a_i  = W0_i . u_S + W1_i . N(u)_S
+//            u+_i = a_i + W2_i . (N(a) - N(u))_S          (both stages fused)
 // with the nonlinear terms
 //   frozen-velocity Burgers : N^(i)_j = -g (u_j - u_i) (du/dx)_j
 //   KdV                     : N_j = -(g/2) (d/dx u^2)_j
 //   Allen-Cahn              : N_j = g (u_j - u_j^3)
 // where d/dx at node j uses row r_j of D1 on j's own stencil.
 //
-// One block covers a tile of kApplyTile consecutive nodes of one instance.
-// A node's stencil lies within 2R of it (R = (n-1)/2; one-sided stencils next
-// to Dirichlet ends reach 2R to one side), so N is needed over the tile plus a
-// halo of 2R, and the state (and the stage value a) is staged in LDS over a
-// halo of 4R when N needs a derivative, 2R otherwise.  Every global read of
-// the state is coalesced and happens once per block.  N is
-// evaluated once per position into LDS.  Per-node weights (structure of
-// arrays, [kind][k][node]) are read coalesced straight from HBM; stationary
-// weights ([kind][r][k], a few KB) are staged in LDS.  Dirichlet end nodes
-// hold their boundary values.
+// One block covers a tile of kApplyTile consecutive nodes of one instance
+// (block -> instance through a host-built table).  A node's stencil lies
+// within 2R of it (R = (n-1)/2; one-sided stencils next to Dirichlet ends
+// reach 2R to one side) and a derivative adds another 2R, so the state is
+// staged in LDS over the tile plus a halo covering every value the tile's
+// outputs depend on: 2R (LINEAR, pointwise N), 4R (derivative N), and for the
+// fused ETD2RK 4R (pointwise) or 8R (derivative) since a and N(a) are formed
+// in LDS around the tile.  Each global value of the state is read once per
+// block, coalesced; per-node weights (structure of arrays [kind][k][node]) are
+// read coalesced from HBM; stationary weights ([kind][r][k]) sit in LDS.
+// Dirichlet end nodes hold their boundary values.
 #include "lmep_device.hpp"
 
 namespace lmep {
 namespace {
 
-constexpr int T = kApplyTile;
+constexpr int NT = 256;  // threads per block
 
-template <int NN, int SCH, int NL, bool PERNODE, int STAGE>
-__global__ __launch_bounds__(T) void apply_kernel(const DevProb* __restrict__ probs, int nprob,
-                                                  const double* __restrict__ fd, const double* __restrict__ w,
-                                                  const double* __restrict__ u_in,
-                                                  const double* __restrict__ u_stage, double* __restrict__ u_out) {
+template <int NN, int NL>
+struct Halo {
+    static constexpr int R = (NN - 1) / 2;
+    static constexpr bool DERIV = (NL == NL_BURGERS) || (NL == NL_KDV);
+    static constexpr int STEN = 2 * R;            // reach of a stencil (edge rows included)
+    static constexpr int NR = DERIV ? 2 * R : 0;  // extra reach of N
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Position whose neighbourhood in the staged arrays stands for unwrapped
+// position j: j itself on periodic grids (translation invariance) and inside a
+// Dirichlet grid; the reflected node on Neumann grids, since every nodal
+// quantity at a reflected position is the reflected node's own value.
+__device__ __forceinline__ int64_t source_position(int64_t j, int64_t N, int bc) {
+    return bc == BC_NEUMANN ? map_index(j, N, bc) : j;
+}
+
+// N at unwrapped position j, from the LDS array v that starts at unwrapped
+// position base.  KdV and the frozen-velocity du/dx use j's own stencil.
+template <int NN, int NL>
+__device__ __forceinline__ double nonlinear_at(const double* __restrict__ v, int len, int64_t base, int64_t j,
+                                               int64_t N, int bc, const double* __restrict__ sD1, double g) {
     constexpr int R = (NN - 1) / 2;
-    constexpr bool DERIV = (NL == NL_BURGERS) || (NL == NL_KDV);
-    constexpr int HN = 2 * R;               // halo of the N (or du/dx) positions
-    constexpr int H = DERIV ? 4 * R : 2 * R; // halo of the staged state
-    constexpr int LU = T + 2 * H;          // staged state positions
-    constexpr int LN = T + 2 * HN;         // positions where N (or du/dx) is needed
+    if constexpr (NL == NL_AC) {
+        const double x = v[clampi((int)(j - base), 0, len - 1)];
+        return g * (x - x * x * x);
+    } else {
+        int64_t jj = source_position(j, N, bc);
+        if (bc == BC_DIRICHLET) jj = jj < 0 ? 0 : (jj > N - 1 ? N - 1 : jj);
+        const int64_t o = (bc == BC_DIRICHLET) ? window_offset(jj, N, NN, bc) : -(int64_t)R;
+        const int rr = (int)(-o);
+        const int b = clampi((int)(jj + o - base), 0, len - NN);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < NN; ++k) {
+            const double x = v[b + k];
+            if constexpr (NL == NL_KDV) acc += sD1[rr * NN + k] * x * x;
+            else acc += sD1[rr * NN + k] * x;
+        }
+        if constexpr (NL == NL_KDV) return -0.5 * g * acc;
+        else return acc;  // du/dx (frozen-velocity remainder)
+    }
+}
+
+template <int NN, int SCH, int NL, bool PERNODE, int TILE>
+__global__ __launch_bounds__(NT) void apply_kernel(const DevProb* __restrict__ probs, const int* __restrict__ tile_inst,
+                                                   const double* __restrict__ fd, const double* __restrict__ w,
+                                                   const double* __restrict__ u_in, double* __restrict__ u_out) {
+    using Hh = Halo<NN, NL>;
     constexpr int PP = (SCH == SCH_ETD2RK) ? 2 : (SCH == SCH_ETD1 ? 1 : 0);
-    constexpr bool TWO = (STAGE == 1);     // ETD2RK second stage: needs u and a
+    constexpr bool HAS_N = (PP > 0) && (NL != NL_NONE);
+    constexpr bool RK2 = (SCH == SCH_ETD2RK);
+    // reach of each stage around the tile (in nodes)
+    constexpr int A_REACH = RK2 ? Hh::STEN + (HAS_N ? Hh::NR : 0) : 0;  // a and N(a) region halo
+    constexpr int AR = A_REACH;                                          // a region halo
+    constexpr int NU_REACH = AR + Hh::STEN;                              // N(u) region halo
+    constexpr int U_REACH = NU_REACH + (HAS_N ? Hh::NR : 0);             // staged state halo
+    constexpr int LU = TILE + 2 * U_REACH;
+    constexpr int LNU = TILE + 2 * NU_REACH;
+    constexpr int LA = TILE + 2 * AR;
 
     __shared__ double su[LU];
-    __shared__ double sa[TWO ? LU : 1];
-    __shared__ double sN[(PP > 0) ? LN : 1];
-    __shared__ double sNa[TWO ? LN : 1];
-    __shared__ double sD1[DERIV ? NN * NN : 1];
+    __shared__ double sNu[HAS_N ? LNU : 1];
+    __shared__ double sa[RK2 ? LA : 1];
+    __shared__ double sNa[(RK2 && HAS_N) ? LA : 1];
+    __shared__ double sD1[Hh::DERIV ? NN * NN : 1];
     __shared__ double sw[PERNODE ? 1 : (PP + 1) * NN * NN];
 
     const int tid = threadIdx.x;
-    const int64_t tile = blockIdx.x;
-    const DevProb& P = probs[find_instance(probs, nprob, tile)];
+    const DevProb& P = probs[tile_inst[blockIdx.x]];
     const int64_t N = P.N;
     const int bc = P.bc;
-    const int64_t t0 = (tile - P.item_begin) * T;
+    const int64_t t0 = ((int64_t)blockIdx.x - P.item_begin) * TILE;
     const double* __restrict__ u = u_in + P.state_off;
-    const double* __restrict__ a = u_stage + P.state_off;
     const double g = P.nl_coef;
+    const int64_t ubase = t0 - U_REACH;
 
-    // stage the state over [t0 - H, t0 + T + H); positions no valid node needs
-    // are clamped into the grid so that no read leaves the instance.
-    for (int q = tid; q < LU; q += T) {
-        int64_t j = map_index(t0 - H + q, N, bc);
-        j = j < 0 ? 0 : (j > N - 1 ? N - 1 : j);
-        su[q] = u[j];
-        if constexpr (TWO) sa[q] = a[j];
+    {  // all loads of the staged state in flight before the LDS stores
+        constexpr int ITER = (LU + NT - 1) / NT;
+        double v[ITER];
+#pragma unroll
+        for (int t = 0; t < ITER; ++t) {
+            const int q = tid + t * NT;
+            int64_t j = map_index(ubase + q, N, bc);
+            j = j < 0 ? 0 : (j > N - 1 ? N - 1 : j);
+            v[t] = (q < LU) ? u[j] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < ITER; ++t)
+            if (tid + t * NT < LU) su[tid + t * NT] = v[t];
     }
-    if constexpr (DERIV) {
+    if constexpr (Hh::DERIV) {
         const double ih = 1.0 / P.h;
-        for (int q = tid; q < NN * NN; q += T) sD1[q] = fd[fd_index(NN, 0, q / NN, q % NN)] * ih;
+        for (int q = tid; q < NN * NN; q += NT) sD1[q] = fd[fd_index(NN, 0, q / NN, q % NN)] * ih;
     }
     if constexpr (!PERNODE) {
-        for (int q = tid; q < (PP + 1) * NN * NN; q += T) sw[q] = w[P.weight_off + q];
+        for (int q = tid; q < (PP + 1) * NN * NN; q += NT) sw[q] = w[P.weight_off + q];
     }
     __syncthreads();
 
-    // nonlinear term (or du/dx for the frozen-velocity case) over [t0 - HN, t0 + T + HN)
-    if constexpr (PP > 0 && NL != NL_NONE) {
-        for (int q = tid; q < LN; q += T) {
-            const int64_t j = t0 - HN + q;  // unwrapped position
-            double vN = 0.0, vNa = 0.0;
-            if constexpr (NL == NL_AC) {
-                const double x = su[q + H - HN];
-                vN = g * (x - x * x * x);
-                if constexpr (TWO) {
-                    const double y = sa[q + H - HN];
-                    vNa = g * (y - y * y * y);
-                }
-            } else {
-                // derivative at position j from j's own stencil (row r_j of D1)
-                int64_t jj = j;
-                if (bc == BC_DIRICHLET) jj = jj < 0 ? 0 : (jj > N - 1 ? N - 1 : jj);
-                const int64_t o = (bc == BC_DIRICHLET) ? window_offset(jj, N, NN, bc) : -(int64_t)R;
-                const int rr = (int)(-o);
-                int base = (int)(jj + o - (t0 - H));
-                base = base < 0 ? 0 : (base > LU - NN ? LU - NN : base);
-                double acc = 0.0, acca = 0.0;
-#pragma unroll
-                for (int k = 0; k < NN; ++k) {
-                    const double d = sD1[rr * NN + k];
-                    const double x = su[base + k];
-                    if constexpr (NL == NL_KDV) {
-                        acc += d * x * x;
-                        if constexpr (TWO) acca += d * sa[base + k] * sa[base + k];
-                    } else {
-                        acc += d * x;
-                    }
-                }
-                if constexpr (NL == NL_KDV) {
-                    vN = -0.5 * g * acc;
-                    vNa = -0.5 * g * acca;
-                } else {
-                    vN = acc;  // du/dx for the frozen-velocity remainder
-                }
-            }
-            sN[q] = vN;
-            if constexpr (TWO) sNa[q] = vNa;
-        }
+    const int64_t nubase = t0 - NU_REACH;
+    if constexpr (HAS_N) {
+        for (int q = tid; q < LNU; q += NT) sNu[q] = nonlinear_at<NN, NL>(su, LU, ubase, nubase + q, N, bc, sD1, g);
         __syncthreads();
     }
 
-    const int64_t i = t0 + tid;
-    if (i >= N) return;
-    double* __restrict__ out = u_out + P.state_off;
-    if (bc == BC_DIRICHLET && (i == 0 || i == N - 1)) {
-        out[i] = (i == 0) ? P.bc_left : P.bc_right;
-        return;
-    }
-    const int64_t o = window_offset(i, N, NN, bc);
-    const int r = (int)(-o);
-    int bu = (int)(i + o - (t0 - H));   // first stencil position in su
-    int bn = (int)(i + o - (t0 - HN));  // first stencil position in sN
-    bu = bu < 0 ? 0 : (bu > LU - NN ? LU - NN : bu);
-    bn = bn < 0 ? 0 : (bn > LN - NN ? LN - NN : bn);
     const double* __restrict__ wn = w + P.weight_off;
-
-    auto weight = [&](int kind, int k) -> double {
+    auto weight = [&](int kind, int r, int k, int64_t i) -> double {
         if constexpr (PERNODE) return wn[(int64_t)(kind * NN + k) * N + i];
         else return sw[(kind * NN + r) * NN + k];
     };
-
-    double acc;
-    if constexpr (!TWO) {
-        acc = 0.0;
-        const double ui = su[tid + H];
+    // first stage (or the whole LINEAR / ETD1 step) at unwrapped position i
+    auto stage_a = [&](int64_t i) -> double {
+        int64_t ii = i;
+        if (bc == BC_DIRICHLET) {
+            if (ii <= 0) return P.bc_left;
+            if (ii >= N - 1) return P.bc_right;
+        } else {
+            ii = map_index(i, N, bc);
+        }
+        const int64_t c = source_position(i, N, bc);  // where the stencil of node ii is read
+        const int64_t o = window_offset(ii, N, NN, bc);
+        const int r = (int)(-o);
+        const int bu = clampi((int)(c + o - ubase), 0, LU - NN);
+        const int bn = clampi((int)(c + o - nubase), 0, (HAS_N ? LNU : NN) - NN);
+        const double ui = su[clampi((int)(c - ubase), 0, LU - 1)];
+        double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < NN; ++k) {
-            acc += weight(0, k) * su[bu + k];
-            if constexpr (PP > 0 && NL != NL_NONE) {
-                if constexpr (NL == NL_BURGERS) acc += weight(1, k) * (-g * (su[bu + k] - ui) * sN[bn + k]);
-                else acc += weight(1, k) * sN[bn + k];
+            acc += weight(0, r, k, ii) * su[bu + k];
+            if constexpr (HAS_N) {
+                if constexpr (NL == NL_BURGERS) acc += weight(1, r, k, ii) * (-g * (su[bu + k] - ui) * sNu[bn + k]);
+                else acc += weight(1, r, k, ii) * sNu[bn + k];
             }
         }
+        return acc;
+    };
+
+    double* __restrict__ out = u_out + P.state_off;
+    if constexpr (!RK2) {
+        for (int q = tid; q < TILE; q += NT) {
+            const int64_t i = t0 + q;
+            if (i < N) out[i] = stage_a(i);
+        }
     } else {
-        acc = sa[tid + H];
-        if constexpr (NL != NL_NONE) {
+        const int64_t abase = t0 - AR;
+        for (int q = tid; q < LA; q += NT) sa[q] = stage_a(abase + q);
+        __syncthreads();
+        if constexpr (HAS_N) {
+            for (int q = tid; q < LA; q += NT) sNa[q] = nonlinear_at<NN, NL>(sa, LA, abase, abase + q, N, bc, sD1, g);
+            __syncthreads();
+        }
+        for (int q = tid; q < TILE; q += NT) {
+            const int64_t i = t0 + q;
+            if (i >= N) continue;
+            double acc = sa[q + AR];
+            if (bc == BC_DIRICHLET && (i == 0 || i == N - 1)) {
+                out[i] = acc;
+                continue;
+            }
+            if constexpr (HAS_N) {
+                const int64_t o = window_offset(i, N, NN, bc);
+                const int r = (int)(-o);
+                const int ba = clampi((int)(i + o - abase), 0, LA - NN);
+                const int bn = clampi((int)(i + o - nubase), 0, LNU - NN);
 #pragma unroll
-            for (int k = 0; k < NN; ++k) acc += weight(2, k) * (sNa[bn + k] - sN[bn + k]);
+                for (int k = 0; k < NN; ++k) acc += weight(2, r, k, i) * (sNa[ba + k] - sNu[bn + k]);
+            }
+            out[i] = acc;
         }
     }
-    out[i] = acc;
 }
 
-template <int NN, int SCH, int NL, bool PN, int ST>
-hipError_t go(const DevProb* p, int np, int64_t tiles, const double* fd, const double* w, const double* ui,
-              const double* us, double* uo, hipStream_t s) {
-    hipLaunchKernelGGL((apply_kernel<NN, SCH, NL, PN, ST>), dim3((unsigned)tiles), dim3(T), 0, s, p, np, fd, w, ui, us,
-                       uo);
+template <int NN, int SCH, int NL, bool PN>
+hipError_t go(int tile, const DevProb* p, const int* ti, int64_t tiles, const double* fd, const double* w,
+              const double* ui, double* uo, hipStream_t s) {
+    if (tile == 256)
+        hipLaunchKernelGGL((apply_kernel<NN, SCH, NL, PN, 256>), dim3((unsigned)tiles), dim3(NT), 0, s, p, ti, fd, w,
+                           ui, uo);
+    else if (tile == 1024)
+        hipLaunchKernelGGL((apply_kernel<NN, SCH, NL, PN, 1024>), dim3((unsigned)tiles), dim3(NT), 0, s, p, ti, fd, w,
+                           ui, uo);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 // Supported (scheme, nonlinearity, weights) combinations.
 template <int NN>
-hipError_t dispatch(int scheme, int nonlin, bool pernode, int stage, const DevProb* p, int np, int64_t tiles,
-                    const double* fd, const double* w, const double* ui, const double* us, double* uo,
-                    hipStream_t s) {
-    if (scheme == SCH_LINEAR && !pernode) return go<NN, SCH_LINEAR, NL_NONE, false, 0>(p, np, tiles, fd, w, ui, us, uo, s);
-    if (scheme == SCH_ETD1 && !pernode) {
-        switch (nonlin) {
-            case NL_NONE: return go<NN, SCH_ETD1, NL_NONE, false, 0>(p, np, tiles, fd, w, ui, us, uo, s);
-            case NL_AC: return go<NN, SCH_ETD1, NL_AC, false, 0>(p, np, tiles, fd, w, ui, us, uo, s);
-            case NL_KDV: return go<NN, SCH_ETD1, NL_KDV, false, 0>(p, np, tiles, fd, w, ui, us, uo, s);
-            default: return hipErrorInvalidValue;
-        }
+hipError_t dispatch(int tile, int scheme, int nonlin, bool pernode, const DevProb* p, const int* ti, int64_t tiles,
+                    const double* fd, const double* w, const double* ui, double* uo, hipStream_t s) {
+    if (pernode) {
+        if (scheme == SCH_ETD1 && nonlin == NL_BURGERS)
+            return go<NN, SCH_ETD1, NL_BURGERS, true>(tile, p, ti, tiles, fd, w, ui, uo, s);
+        return hipErrorInvalidValue;
     }
-    if (scheme == SCH_ETD1 && pernode && nonlin == NL_BURGERS)
-        return go<NN, SCH_ETD1, NL_BURGERS, true, 0>(p, np, tiles, fd, w, ui, us, uo, s);
-    if (scheme == SCH_ETD2RK && !pernode) {
-        switch (nonlin) {
-            case NL_NONE:
-                return stage == 0 ? go<NN, SCH_ETD2RK, NL_NONE, false, 0>(p, np, tiles, fd, w, ui, us, uo, s)
-                                  : go<NN, SCH_ETD2RK, NL_NONE, false, 1>(p, np, tiles, fd, w, ui, us, uo, s);
-            case NL_AC:
-                return stage == 0 ? go<NN, SCH_ETD2RK, NL_AC, false, 0>(p, np, tiles, fd, w, ui, us, uo, s)
-                                  : go<NN, SCH_ETD2RK, NL_AC, false, 1>(p, np, tiles, fd, w, ui, us, uo, s);
-            case NL_KDV:
-                return stage == 0 ? go<NN, SCH_ETD2RK, NL_KDV, false, 0>(p, np, tiles, fd, w, ui, us, uo, s)
-                                  : go<NN, SCH_ETD2RK, NL_KDV, false, 1>(p, np, tiles, fd, w, ui, us, uo, s);
-            default: return hipErrorInvalidValue;
-        }
+    if (scheme == SCH_LINEAR) return go<NN, SCH_LINEAR, NL_NONE, false>(tile, p, ti, tiles, fd, w, ui, uo, s);
+    switch (nonlin) {
+        case NL_NONE:
+            return scheme == SCH_ETD1 ? go<NN, SCH_ETD1, NL_NONE, false>(tile, p, ti, tiles, fd, w, ui, uo, s)
+                                      : go<NN, SCH_ETD2RK, NL_NONE, false>(tile, p, ti, tiles, fd, w, ui, uo, s);
+        case NL_AC:
+            return scheme == SCH_ETD1 ? go<NN, SCH_ETD1, NL_AC, false>(tile, p, ti, tiles, fd, w, ui, uo, s)
+                                      : go<NN, SCH_ETD2RK, NL_AC, false>(tile, p, ti, tiles, fd, w, ui, uo, s);
+        case NL_KDV:
+            return scheme == SCH_ETD1 ? go<NN, SCH_ETD1, NL_KDV, false>(tile, p, ti, tiles, fd, w, ui, uo, s)
+                                      : go<NN, SCH_ETD2RK, NL_KDV, false>(tile, p, ti, tiles, fd, w, ui, uo, s);
+        default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 __global__ void check_finite_kernel(const double* __restrict__ x, int64_t count, int* __restrict__ flag) {
@@ -212,18 +249,18 @@ __global__ void check_finite_kernel(const double* __restrict__ x, int64_t count,
 
 }  // namespace
 
-hipError_t launch_apply(int n, int scheme, int nonlin, bool pernode, int stage, const DevProb* d_probs, int nprob,
-                        int64_t tiles, const double* fd, const double* d_w, const double* d_u_in,
-                        const double* d_u_stage, double* d_u_out, hipStream_t stream) {
+hipError_t launch_apply(int n, int tile, int scheme, int nonlin, bool pernode, const DevProb* d_probs,
+                        const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                        const double* d_u_in, double* d_u_out, hipStream_t stream) {
     if (tiles <= 0) return hipSuccess;
     switch (n) {
-        case 3: return dispatch<3>(scheme, nonlin, pernode, stage, d_probs, nprob, tiles, fd, d_w, d_u_in, d_u_stage, d_u_out, stream);
-        case 5: return dispatch<5>(scheme, nonlin, pernode, stage, d_probs, nprob, tiles, fd, d_w, d_u_in, d_u_stage, d_u_out, stream);
-        case 7: return dispatch<7>(scheme, nonlin, pernode, stage, d_probs, nprob, tiles, fd, d_w, d_u_in, d_u_stage, d_u_out, stream);
-        case 9: return dispatch<9>(scheme, nonlin, pernode, stage, d_probs, nprob, tiles, fd, d_w, d_u_in, d_u_stage, d_u_out, stream);
-        case 11: return dispatch<11>(scheme, nonlin, pernode, stage, d_probs, nprob, tiles, fd, d_w, d_u_in, d_u_stage, d_u_out, stream);
-        case 13: return dispatch<13>(scheme, nonlin, pernode, stage, d_probs, nprob, tiles, fd, d_w, d_u_in, d_u_stage, d_u_out, stream);
-        case 15: return dispatch<15>(scheme, nonlin, pernode, stage, d_probs, nprob, tiles, fd, d_w, d_u_in, d_u_stage, d_u_out, stream);
+        case 3: return dispatch<3>(tile, scheme, nonlin, pernode, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 5: return dispatch<5>(tile, scheme, nonlin, pernode, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 7: return dispatch<7>(tile, scheme, nonlin, pernode, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 9: return dispatch<9>(tile, scheme, nonlin, pernode, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 11: return dispatch<11>(tile, scheme, nonlin, pernode, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 13: return dispatch<13>(tile, scheme, nonlin, pernode, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 15: return dispatch<15>(tile, scheme, nonlin, pernode, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -107,14 +107,14 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Scratch layout.
 struct Layout {
-    size_t build_tab = 0, apply_tab = 0, state = 0, stage = 0, flag = 0, total = 0;
+    size_t build_tab = 0, apply_tab = 0, tile_inst = 0, state = 0, flag = 0, total = 0;
     size_t g = 0, ghat = 0, ws = 0, dparam = 0, part = 0;  // reverse step
     int ws_stride = 0;
 };
 
-int64_t total_tiles(const lmep_problem* prob, int32_t count) {
+int64_t total_tiles(const lmep_problem* prob, int32_t count, int tile) {
     int64_t t = 0;
-    for (int k = 0; k < count; ++k) t += (prob[k].N + kApplyTile - 1) / kApplyTile;
+    for (int k = 0; k < count; ++k) t += (prob[k].N + tile - 1) / tile;
     return t;
 }
 
@@ -127,13 +127,10 @@ Layout layout(const lmep_problem* prob, int32_t count, int op) {
     L.apply_tab = off;
     off += tab;
     if (op == 1) {
-        const size_t st = align256(sizeof(double) * (size_t)state_extent(prob, count));
+        L.tile_inst = off;
+        off += align256(sizeof(int) * (size_t)total_tiles(prob, count, kApplyTileSmall));
         L.state = off;
-        off += st;
-        bool rk2 = false;
-        for (int k = 0; k < count; ++k) rk2 |= prob[k].scheme == LMEP_ETD2RK;
-        L.stage = off;
-        if (rk2) off += st;
+        off += align256(sizeof(double) * (size_t)state_extent(prob, count));
     }
     if (op == 2) {
         const size_t ext = (size_t)state_extent(prob, count);
@@ -149,7 +146,7 @@ Layout layout(const lmep_problem* prob, int32_t count, int op) {
         L.dparam = off;
         off += align256(sizeof(double) * 3 * ext);
         L.part = off;
-        off += align256(sizeof(double) * 3 * (size_t)total_tiles(prob, count));
+        off += align256(sizeof(double) * 3 * (size_t)total_tiles(prob, count, kAdjTile));
     }
     L.flag = off;
     off += 256;
@@ -185,7 +182,7 @@ DevProb to_dev(const lmep_problem& q, int index) {
 // A launch group: a contiguous slice of a device table whose instances share
 // one kernel variant.
 struct Group {
-    int n = 0, p = 0, scheme = 0, nonlin = 0;
+    int n = 0, p = 0, scheme = 0, nonlin = 0, tile = 0;
     bool pernode = false;
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
@@ -217,7 +214,9 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
     return groups;
 }
 
-std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab) {
+// Apply groups: keyed by kernel variant; also fills the block -> table-row map.
+std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab,
+                              std::vector<int>& tile_inst) {
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < count; ++k)
         by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : 0}].push_back(k);
@@ -227,11 +226,16 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         std::tie(g.n, g.scheme, g.nonlin, std::ignore) = kv.first;
         g.pernode = std::get<3>(kv.first) != 0;
         g.first = (int)tab.size();
+        int64_t nodes = 0;
+        for (int k : kv.second) nodes += prob[k].N;
+        g.tile = nodes < kSmallGroupNodes ? kApplyTileSmall : kApplyTile;
         int64_t tiles = 0;
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
             d.item_begin = tiles;
-            tiles += (prob[k].N + kApplyTile - 1) / kApplyTile;
+            const int64_t nt = (prob[k].N + g.tile - 1) / g.tile;
+            for (int64_t t = 0; t < nt; ++t) tile_inst.push_back((int)(tab.size() - g.first));
+            tiles += nt;
             tab.push_back(d);
         }
         g.count = (int)kv.second.size();
@@ -257,27 +261,31 @@ struct Staging {
 };
 thread_local Staging t_stage;
 
-int upload(const std::vector<DevProb>& a, const std::vector<DevProb>& b, void* d_a, void* d_b, hipStream_t s) {
+int upload(const std::vector<DevProb>& a, const std::vector<DevProb>& b, void* d_a, void* d_b, hipStream_t s,
+           const std::vector<int>* c = nullptr, void* d_c = nullptr) {
     const size_t na = a.size() * sizeof(DevProb), nb = b.size() * sizeof(DevProb);
+    const size_t nc = c ? c->size() * sizeof(int) : 0;
     Staging& st = t_stage;
     if (!st.done) HIP_TRY(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     if (st.pending) {
         HIP_TRY(hipEventSynchronize(st.done));
         st.pending = false;
     }
-    if (st.cap < na + nb) {
+    if (st.cap < na + nb + nc) {
         if (st.host) HIP_TRY(hipHostFree(st.host));
         st.host = nullptr;
         st.cap = 0;
-        const size_t cap = std::max<size_t>(na + nb, 1 << 16);
+        const size_t cap = std::max<size_t>(na + nb + nc, 1 << 16);
         HIP_TRY(hipHostMalloc(&st.host, cap, hipHostMallocDefault));
         st.cap = cap;
     }
     char* h = (char*)st.host;
     if (na) std::memcpy(h, a.data(), na);
     if (nb) std::memcpy(h + na, b.data(), nb);
+    if (nc) std::memcpy(h + na + nb, c->data(), nc);
     if (na) HIP_TRY(hipMemcpyAsync(d_a, h, na, hipMemcpyHostToDevice, s));
     if (nb) HIP_TRY(hipMemcpyAsync(d_b, h + na, nb, hipMemcpyHostToDevice, s));
+    if (nc) HIP_TRY(hipMemcpyAsync(d_c, h + na + nb, nc, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(st.done, s));
     st.pending = true;
     return LMEP_OK;
@@ -413,14 +421,16 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     HIP_TRY(fd_table_init(&fd));
 
     std::vector<DevProb> btab, atab;
+    std::vector<int> tile_inst;
     auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab);
-    auto agroups = plan_apply(prob, count, atab);
+    auto agroups = plan_apply(prob, count, atab, tile_inst);
     char* base = (char*)d_scratch;
-    if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s))) return rc;
+    if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s, &tile_inst, base + L.tile_inst)))
+        return rc;
     const DevProb* dbt = (const DevProb*)(base + L.build_tab);
     const DevProb* dat = (const DevProb*)(base + L.apply_tab);
+    const int* dti = (const int*)(base + L.tile_inst);
     double* bufA = (double*)(base + L.state);
-    double* stage = (double*)(base + L.stage);
 
     Timer timer;
     timer.on = (flags & LMEP_F_PROFILE) != 0;
@@ -450,16 +460,11 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
                 HIP_TRY(timer.mark(true, s, false));
             }
             HIP_TRY(timer.mark(false, s, true));
+            int64_t tile0 = 0;
             for (auto& gr : agroups) {
-                if (gr.scheme == LMEP_ETD2RK) {
-                    HIP_TRY(launch_apply(gr.n, gr.scheme, gr.nonlin, gr.pernode, 0, dat + gr.first, gr.count, gr.items,
-                                         fd, d_w, src, nullptr, stage, s));
-                    HIP_TRY(launch_apply(gr.n, gr.scheme, gr.nonlin, gr.pernode, 1, dat + gr.first, gr.count, gr.items,
-                                         fd, d_w, src, stage, dst, s));
-                } else {
-                    HIP_TRY(launch_apply(gr.n, gr.scheme, gr.nonlin, gr.pernode, 0, dat + gr.first, gr.count, gr.items,
-                                         fd, d_w, src, nullptr, dst, s));
-                }
+                HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first, dti + tile0,
+                                     gr.items, fd, d_w, src, dst, s));
+                tile0 += gr.items;
             }
             HIP_TRY(timer.mark(false, s, false));
         }
@@ -563,7 +568,7 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
             d.item_begin = tile_base + g.tiles;  // global tile index: rows of the partial-sum array
             ttab.push_back(d);
             g.nodes += prob[k].N;
-            g.tiles += (prob[k].N + kApplyTile - 1) / kApplyTile;
+            g.tiles += (prob[k].N + kAdjTile - 1) / kAdjTile;
         }
         // tile tables are searched from the group's first tile
         for (int q = g.first; q < g.first + g.cnt; ++q) ttab[q].item_begin -= tile_base;

@@ -37,7 +37,10 @@ __device__ __forceinline__ int64_t window_offset(int64_t i, int64_t N, int n, in
 // the end nodes (Neumann), identity (Dirichlet windows never leave the grid).
 __device__ __forceinline__ int64_t map_index(int64_t j, int64_t N, int bc) {
     if (bc == BC_PERIODIC) {
-        j = j % N;
+        if (j >= 0 && j < N) return j;
+        if (j < 0 && j >= -N) return j + N;
+        if (j >= N && j < 2 * N) return j - N;
+        j = j % N;  // halos wider than the grid (tiny instances)
         return j < 0 ? j + N : j;
     }
     if (bc == BC_NEUMANN) {

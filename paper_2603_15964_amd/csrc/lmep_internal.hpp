@@ -53,14 +53,18 @@ hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t
                         const double* fd, const double* d_u, double* d_w, unsigned long long* stats,
                         hipStream_t stream);
 
-// One step stage over a group of instances sharing (n, scheme, nonlin, per-node).
-//   stage 0: LINEAR / ETD1 full step, or ETD2RK first stage (writes u_out = a)
-//   stage 1: ETD2RK second stage (reads u_in = u^k and u_stage = a)
-hipError_t launch_apply(int n, int scheme, int nonlin, bool pernode, int stage, const DevProb* d_probs,
-                        int nprob, int64_t tiles, const double* fd, const double* d_w, const double* d_u_in,
-                        const double* d_u_stage, double* d_u_out, hipStream_t stream);
+// One time step over a group of instances sharing (n, scheme, nonlin,
+// per-node weights); ETD2RK's two stages run in one kernel.  d_tile_inst maps
+// each block (tile of `tile` nodes, 256 or 1024) to its instance in d_probs,
+// whose item_begin is the instance's first tile.
+hipError_t launch_apply(int n, int tile, int scheme, int nonlin, bool pernode, const DevProb* d_probs,
+                        const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                        const double* d_u_in, double* d_u_out, hipStream_t stream);
 
-constexpr int kApplyTile = 256;  // nodes per apply block
+constexpr int kApplyTileSmall = 256;   // nodes per apply block for groups with few nodes
+constexpr int kApplyTile = 1024;       // nodes per apply block otherwise
+constexpr int64_t kSmallGroupNodes = 1 << 20;  // groups below this many nodes use the small tile
+constexpr int kAdjTile = 256;     // nodes per block of the reverse-step gathers
 
 // One group (same n and p) of a reverse step.  tile_probs: item_begin =
 // prefix of 256-node tiles; node_probs: the same instances with item_begin =

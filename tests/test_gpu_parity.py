@@ -140,6 +140,16 @@ ONE_STEP = [
                                                              dt=0.5 * (2 / 499) ** 2 / 1e-4, scheme="etd2rk",
                                                              nonlin="allen_cahn", nl_coef=1.0)),
                                            np.random.default_rng(3).uniform(-0.1, 0.1, 500))),
+    ("burgers neumann n7", lambda: (dict(workloads.burgers(N=900, n=7)[0], bc="neumann", c=0.2),
+                                    0.6 * np.cos(np.linspace(0, 3 * np.pi, 900)) + 0.1)),
+    ("kdv neumann etd2rk", lambda: (dict(workloads.kdv(N=1024, tau=0.05)[0], bc="neumann"),
+                                    workloads.kdv(N=1024, tau=0.05)[1])),
+    ("advection-dispersion neumann etd2rk", lambda: (make_problem(N=700, n=9, bc="neumann", h=0.05, dt=0.01, c=0.7,
+                                                                  nu=0.01, delta=1e-5, scheme="etd2rk",
+                                                                  nonlin="allen_cahn", nl_coef=0.5),
+                                                     np.sin(np.linspace(0, 5, 700)))),
+    ("kdv dirichlet etd2rk", lambda: (dict(workloads.kdv(N=1500, tau=0.05)[0], bc="dirichlet", bc_left=0.1,
+                                           bc_right=0.0), workloads.kdv(N=1500, tau=0.05)[1])),
     ("diffusion dirichlet etd1 react", lambda: (make_problem(N=260, n=11, bc="dirichlet", h=0.05, dt=0.001, nu=0.5,
                                                              react=-0.7, scheme="etd1", nonlin="allen_cahn",
                                                              nl_coef=0.3, bc_left=1.0, bc_right=-1.0),
@@ -173,6 +183,13 @@ MULTI = [
     ("allen-cahn batch of 6, 60 steps", lambda: (*_ac_subset(6), 60)),
     ("burgers n9 nu5e-3 N3000 60 steps", lambda: ([workloads.burgers(N=3000, n=9, nu=5e-3)[0]],
                                                   [workloads.burgers(N=3000, n=9, nu=5e-3)[1]], 60)),
+    ("kdv neumann N3000 tau0.05 100 steps", lambda: ([dict(workloads.kdv(N=3000, tau=0.05)[0], bc="neumann")],
+                                                     [workloads.kdv(N=3000, tau=0.05)[1]], 100)),
+    ("mixed batch: tiles of 1024 straddling instances", lambda: (
+        [workloads.advection_diffusion(N=1500, cfl=1.0)[0], dict(workloads.kdv(N=2500, tau=0.05)[0]),
+         workloads.allen_cahn_batch(count=1, n_min=3000, n_max=3000)[0][0]],
+        [workloads.advection_diffusion(N=1500, cfl=1.0)[1], workloads.kdv(N=2500, tau=0.05)[1],
+         workloads.allen_cahn_batch(count=1, n_min=3000, n_max=3000)[1][0]], 40)),
 ]
 
 
