@@ -34,6 +34,24 @@ def pade_flops(m: int, matrices: int, squarings: int) -> float:
     return matrices * (2.0 * 6 * m ** 3 + 8.0 * m ** 3 / 3.0) + squarings * 2.0 * m ** 3
 
 
+def stationary_flops(p: dict) -> float:
+    """Algorithmic flops of one node-step of the banded apply with stationary
+    weights (multiply-add = 2): W0.u (+ W1.N) over the n-window, N itself
+    (Allen-Cahn g(u - u^3): 4; KdV -(g/2) D1.(u u): 3n + 2), and for ETD2RK with
+    a nonlinearity N(a) plus a + W2.(N(a) - N(u)) (2n + 1)."""
+    n = p["n"]
+    rk2 = p["scheme"] == "etd2rk"
+    nl = p.get("nonlin", "none")
+    has_n = p["scheme"] != "linear" and nl != "none"
+    n_cost = {"allen_cahn": 4.0, "kdv": 3.0 * n + 2.0}.get(nl, 0.0)
+    f = 2.0 * n
+    if has_n:
+        f += 2.0 * n + n_cost
+        if rk2:
+            f += n_cost + 2.0 * n + 1.0
+    return f
+
+
 def make_workload(name: str):
     import workloads
     if name == "burgers":
@@ -99,6 +117,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates byte counters)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="stationary weights: advance several steps per launch (LMEP_F_PERSISTENT)")
+    ap.add_argument("--steps-per-launch", type=int, default=8, choices=(1, 2, 4, 8))
     ap.add_argument("--skip-count", action="store_true",
                     help="skip the squaring-count pass (its atomics would show up in a kernel trace)")
     args = ap.parse_args()
@@ -140,6 +161,13 @@ def main():
     if not all(p.get("nonlin") == "burgers_frozen" for p in problems):
         batch.build_weights(w, u0)
     flags = lmep.LMEP_F_GRAPH if args.graph else 0
+    kb = 1
+    if args.persistent:
+        if frozen:
+            raise SystemExit("--persistent needs stationary weights (this workload rebuilds them every step)")
+        flags |= lmep.LMEP_F_PERSISTENT
+        kb = args.steps_per_launch
+        lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
 
     if args.warmup > 0:
         batch.step(w, u0, args.warmup, flags, u_out=ua)
@@ -160,7 +188,7 @@ def main():
     # profiled pass: HIP events around every build / apply launch, same K steps
     # from the same state; then an untimed pass over the same steps that counts
     # the squarings each local exponential took (for the algorithmic flops)
-    batch.step(w, ua, args.steps, lmep.LMEP_F_PROFILE, u_out=ub)
+    batch.step(w, ua, args.steps, lmep.LMEP_F_PROFILE | (flags & lmep.LMEP_F_PERSISTENT), u_out=ub)
     if frozen and not args.skip_count:
         batch.step(w, ua, args.steps, lmep.LMEP_F_COUNT, u_out=ub)
     prof = lmep.lmep_profile_last()
@@ -180,13 +208,25 @@ def main():
                 "flops_per_launch": flops / prof["build_launches"],
                 "mean_squarings": prof["squarings"] / max(1, prof["matrices"])}
     if prof["apply_launches"] > 0:
-        ab = apply_bytes.get(args.workload, 16.0) * node_steps
-        gbs = ab / (prof["apply_ms"] / 1e3) / 1e9
+        apply_s = prof["apply_ms"] / 1e3
+        avg_us = prof["apply_ms"] * 1e3 / prof["apply_launches"]
+        # algorithmic HBM bytes: per node and launch, u in + u out (16 B), plus
+        # the per-node weights of the frozen-velocity path (read every step)
+        ab = apply_bytes.get(args.workload, 16.0) * node_steps / kb
+        gbs = ab / apply_s / 1e9
         extra["apply"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                          "frac": gbs / PEAK_HBM_GBS,
-                          "avg_launch_us": prof["apply_ms"] * 1e3 / prof["apply_launches"]}
+                          "frac": gbs / PEAK_HBM_GBS, "avg_launch_us": avg_us, "steps_per_launch": kb,
+                          "bytes_per_launch": ab / prof["apply_launches"]}
+        if not frozen:
+            fl = sum(stationary_flops(p) * p["N"] for p in problems) * args.steps
+            tf = fl / apply_s / 1e12
+            extra["apply_alu"] = {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / PEAK_FP64_TFLOPS, "flops_per_launch": fl / prof["apply_launches"]}
         if roof is None:
-            roof = dict(extra["apply"], traffic=None)
+            # one step per launch: HBM-bound; several: the traffic is paid once
+            # per launch and the FP64 work of the steps bounds the kernel
+            roof = dict(extra["apply_alu"] if kb > 1 else extra["apply"], traffic=None,
+                        kernel=("stepk_kernel" if kb > 1 else "apply_kernel"), avg_launch_us=avg_us)
     out = {
         "metric": "node-steps/s (weight build+apply, FP64)",
         "value": value,
@@ -201,7 +241,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "instances": batch.count, "nodes": batch.state_size,
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "steps_per_launch": kb},
         "roofline": roof,
         "detail": extra,
     }

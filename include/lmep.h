@@ -70,7 +70,13 @@ enum { LMEP_NL_NONE = 0, LMEP_NL_BURGERS_FROZEN = 1, LMEP_NL_KDV = 2, LMEP_NL_AL
 
 /* lmep_step flags */
 #define LMEP_F_GRAPH        0x1u  /* capture the step loop in a hipGraph and replay it          */
-#define LMEP_F_PERSISTENT   0x2u  /* multi-step kernel that keeps each instance on chip          */
+#define LMEP_F_PERSISTENT   0x2u  /* multi-step launches: each block keeps its tile of nodes,    */
+                                  /* with a halo it recomputes, in LDS for up to 8 steps (see   */
+                                  /* LMEP_OPT_STEPS_PER_LAUNCH), so                             */
+                                  /* HBM is read and written once per launch instead of once    */
+                                  /* per step; same result bit for bit as the one-step path.    */
+                                  /* Stationary weights only (LMEP_ERR_UNSUPPORTED if any       */
+                                  /* instance is BURGERS_FROZEN).                               */
 #define LMEP_F_CHECK_FINITE 0x4u  /* scan the result; LMEP_ERR_NONFINITE if any entry is not    */
                                   /* finite (synchronises the stream)                            */
 #define LMEP_F_PROFILE      0x8u  /* time the weight-build and apply kernels with HIP events    */
@@ -153,6 +159,17 @@ int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_m
 
 /* Thread-local description of the last non-OK status. */
 const char* lmep_last_error(void);
+
+/* Process-wide tuning options (read at each lmep_step call).
+ *  LMEP_OPT_STEPS_PER_LAUNCH  steps advanced per launch under
+ *                             LMEP_F_PERSISTENT: 1, 2, 4 or 8 (default 8).  More
+ *                             steps mean less HBM traffic but a wider halo
+ *                             recomputed by every block.
+ * lmep_set_option returns LMEP_OK or LMEP_ERR_ARG (unknown option or value);
+ * lmep_get_option returns the value or LMEP_ERR_ARG. */
+#define LMEP_OPT_STEPS_PER_LAUNCH 1
+int lmep_set_option(int32_t option, int32_t value);
+int32_t lmep_get_option(int32_t option);
 
 #ifdef __cplusplus
 }

@@ -69,9 +69,13 @@ _lib.lmep_profile_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINT
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 _lib.lmep_last_error.restype = ctypes.c_char_p
+_lib.lmep_set_option.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.lmep_get_option.argtypes = [ctypes.c_int32]
+_lib.lmep_get_option.restype = ctypes.c_int32
 
 EXPORTED = ("lmep_weight_count", "lmep_scratch_bytes", "lmep_build_weights", "lmep_step", "lmep_adjoint_step",
-            "lmep_profile_last", "lmep_last_error")
+            "lmep_profile_last", "lmep_last_error", "lmep_set_option", "lmep_get_option")
+LMEP_OPT_STEPS_PER_LAUNCH = 1
 
 
 def library() -> ctypes.CDLL:
@@ -139,3 +143,11 @@ def lmep_profile_last() -> dict:
                                   ctypes.byref(m), ctypes.byref(sq)))
     return dict(build_ms=b.value, build_launches=nb.value, apply_ms=a.value, apply_launches=na.value,
                 matrices=m.value, squarings=sq.value)
+
+
+def lmep_set_option(option: int, value: int) -> None:
+    _check(_lib.lmep_set_option(int(option), int(value)))
+
+
+def lmep_get_option(option: int) -> int:
+    return _check(_lib.lmep_get_option(int(option)))

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -25,6 +26,7 @@ thread_local char t_err[512] = "";
 thread_local double t_prof_build_ms = 0.0, t_prof_apply_ms = 0.0;
 thread_local int32_t t_prof_build_n = 0, t_prof_apply_n = 0;
 thread_local int64_t t_prof_matrices = 0, t_prof_squarings = 0;
+std::atomic<int> t_steps_per_launch{8};  // LMEP_OPT_STEPS_PER_LAUNCH, process-wide
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -215,8 +217,9 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
 }
 
 // Apply groups: keyed by kernel variant; also fills the block -> table-row map.
+// multi_kb > 0: tiles of the multi-step kernel advancing multi_kb steps per launch.
 std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab,
-                              std::vector<int>& tile_inst) {
+                              std::vector<int>& tile_inst, int multi_kb = 0) {
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < count; ++k)
         by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : 0}].push_back(k);
@@ -228,7 +231,8 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         g.first = (int)tab.size();
         int64_t nodes = 0;
         for (int k : kv.second) nodes += prob[k].N;
-        g.tile = nodes < kSmallGroupNodes ? kApplyTileSmall : kApplyTile;
+        g.tile = multi_kb > 0 ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb)
+                              : (nodes < kSmallGroupNodes ? kApplyTileSmall : kApplyTile);
         int64_t tiles = 0;
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
@@ -364,6 +368,21 @@ size_t lmep_scratch_bytes(const lmep_problem* prob, int32_t count, int32_t op) {
 
 const char* lmep_last_error(void) { return t_err; }
 
+int lmep_set_option(int32_t option, int32_t value) {
+    if (option == LMEP_OPT_STEPS_PER_LAUNCH) {
+        if (value != 1 && value != 2 && value != 4 && value != 8)
+            return fail(LMEP_ERR_ARG, "steps per launch must be 1, 2, 4 or 8, got %d", value);
+        t_steps_per_launch.store(value);
+        return LMEP_OK;
+    }
+    return fail(LMEP_ERR_ARG, "unknown option %d", option);
+}
+
+int32_t lmep_get_option(int32_t option) {
+    if (option == LMEP_OPT_STEPS_PER_LAUNCH) return t_steps_per_launch.load();
+    return fail(LMEP_ERR_ARG, "unknown option %d", option);
+}
+
 int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_ms, int32_t* apply_launches,
                       int64_t* matrices, int64_t* squarings) {
     if (build_ms) *build_ms = t_prof_build_ms;
@@ -405,7 +424,12 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     if (n_steps < 1) return fail(LMEP_ERR_ARG, "n_steps must be >= 1");
     if (flags & ~(LMEP_F_GRAPH | LMEP_F_PERSISTENT | LMEP_F_CHECK_FINITE | LMEP_F_PROFILE | LMEP_F_COUNT))
         return fail(LMEP_ERR_ARG, "unknown flag bits 0x%x", flags);
-    if (flags & LMEP_F_PERSISTENT) return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT is not available");
+    const bool multi = (flags & LMEP_F_PERSISTENT) != 0;
+    if (multi)
+        for (int k = 0; k < count; ++k)
+            if (frozen(prob[k]))
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs stationary weights (instance %d is "
+                            "BURGERS_FROZEN)", k);
     if ((flags & LMEP_F_GRAPH) && (flags & (LMEP_F_PROFILE | LMEP_F_COUNT)))
         return fail(LMEP_ERR_ARG, "LMEP_F_PROFILE / LMEP_F_COUNT cannot be combined with LMEP_F_GRAPH");
     const int64_t ext = state_extent(prob, count);
@@ -423,7 +447,9 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     std::vector<DevProb> btab, atab;
     std::vector<int> tile_inst;
     auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab);
-    auto agroups = plan_apply(prob, count, atab, tile_inst);
+    const int kb = multi ? t_steps_per_launch.load() : 1;
+    auto agroups = plan_apply(prob, count, atab, tile_inst, multi ? kb : 0);
+    const int launches = (n_steps + kb - 1) / kb;  // apply launches per group
     char* base = (char*)d_scratch;
     if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s, &tile_inst, base + L.tile_inst)))
         return rc;
@@ -434,7 +460,7 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
 
     Timer timer;
     timer.on = (flags & LMEP_F_PROFILE) != 0;
-    HIP_TRY(timer.reserve(bgroups.empty() ? 0 : (size_t)n_steps, (size_t)n_steps));
+    HIP_TRY(timer.reserve(bgroups.empty() ? 0 : (size_t)launches, (size_t)launches));
     unsigned long long* counters = (flags & LMEP_F_COUNT) ? (unsigned long long*)(base + L.flag + 64) : nullptr;
     if (counters) HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(unsigned long long), s));
     const bool graph = (flags & LMEP_F_GRAPH) != 0;
@@ -450,9 +476,9 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     auto enqueue = [&]() -> int {
         // destinations alternate between the scratch state and d_u_out so that
         // the last step lands in d_u_out and no step works in place
-        for (int st = 0; st < n_steps; ++st) {
-            const double* src = (st == 0) ? d_u_in : (((n_steps - st) % 2 == 0) ? d_u_out : bufA);
-            double* dst = ((n_steps - 1 - st) % 2 == 0) ? d_u_out : bufA;
+        for (int st = 0; st < launches; ++st) {
+            const double* src = (st == 0) ? d_u_in : (((launches - st) % 2 == 0) ? d_u_out : bufA);
+            double* dst = ((launches - 1 - st) % 2 == 0) ? d_u_out : bufA;
             if (!bgroups.empty()) {
                 HIP_TRY(timer.mark(true, s, true));
                 for (auto& gr : bgroups)
@@ -462,8 +488,12 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
             HIP_TRY(timer.mark(false, s, true));
             int64_t tile0 = 0;
             for (auto& gr : agroups) {
-                HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first, dti + tile0,
-                                     gr.items, fd, d_w, src, dst, s));
+                if (multi)
+                    HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
+                                         dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
+                else
+                    HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first,
+                                         dti + tile0, gr.items, fd, d_w, src, dst, s));
                 tile0 += gr.items;
             }
             HIP_TRY(timer.mark(false, s, false));
@@ -491,20 +521,22 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     if (timer.on) {
         HIP_TRY(hipStreamSynchronize(s));
         double bms = 0.0, ams = 0.0;
-        for (auto& ev : timer.build) {
+        for (size_t k = 0; k < timer.nb; ++k) {
+            const auto& ev = timer.build[k];
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
             bms += ms;
         }
-        for (auto& ev : timer.apply) {
+        for (size_t k = 0; k < timer.na; ++k) {
+            const auto& ev = timer.apply[k];
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
             ams += ms;
         }
         t_prof_build_ms = bms;
         t_prof_apply_ms = ams;
-        t_prof_build_n = (int32_t)timer.build.size();
-        t_prof_apply_n = (int32_t)timer.apply.size();
+        t_prof_build_n = (int32_t)timer.nb;
+        t_prof_apply_n = (int32_t)timer.na;
     }
     if (counters) {
         unsigned long long hc[2] = {0, 0};

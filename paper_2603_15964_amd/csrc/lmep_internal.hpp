@@ -61,6 +61,34 @@ hipError_t launch_apply(int n, int tile, int scheme, int nonlin, bool pernode, c
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
                         const double* d_u_in, double* d_u_out, hipStream_t stream);
 
+// Stationary weights, several steps per launch (stepk.hpp).  A block stages
+// kStepRegion consecutive positions of its instance, advances them `ksteps`
+// <= kb steps in LDS (kb = 1, 2, 4 or 8) and writes the middle
+// stepk_tile(...) of them; the rest is the halo the steps consume (each
+// stencil application spoils (n-1)/2 positions at each open end).
+constexpr int kStepRegion = 2048;
+__host__ __device__ constexpr int stepk_apps(int scheme, int nonlin) {
+    // stencil applications per step
+    return (scheme == SCH_ETD2RK && nonlin != NL_NONE ? 2 : 1) *
+           (scheme != SCH_LINEAR && nonlin == NL_KDV ? 2 : 1);
+}
+__host__ __device__ constexpr int stepk_halo(int n, int scheme, int nonlin, int kb) {
+    return kb * stepk_apps(scheme, nonlin) * ((n - 1) / 2);
+}
+__host__ __device__ constexpr int stepk_tile(int n, int scheme, int nonlin, int kb) {
+    return kStepRegion - 2 * stepk_halo(n, scheme, nonlin, kb);
+}
+static_assert(stepk_tile(15, SCH_ETD2RK, NL_KDV, 8) >= 1024, "halo too wide for the staged region");
+template <int KB>
+hipError_t launch_stepk_depth(int n, int scheme, int nonlin, int ksteps, const DevProb* d_probs,
+                              const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                              const double* d_u_in, double* d_u_out, hipStream_t stream);
+// Block b of a group writes nodes [b' * tile, (b' + 1) * tile) of its instance,
+// b' = b - item_begin, tile = stepk_tile(n, scheme, nonlin, kb).
+hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const DevProb* d_probs,
+                        const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                        const double* d_u_in, double* d_u_out, hipStream_t stream);
+
 constexpr int kApplyTileSmall = 256;   // nodes per apply block for groups with few nodes
 constexpr int kApplyTile = 1024;       // nodes per apply block otherwise
 constexpr int64_t kSmallGroupNodes = 1 << 20;  // groups below this many nodes use the small tile

@@ -100,3 +100,26 @@ def test_weight_counts_and_batch_packing():
     assert b.state_size == sum(x["N"] for x in probs)
     assert all(o % 32 == 0 for o in b.weight_off)
     assert lmep.lmep_scratch_bytes(b.structs, b.count, lmep.OP_BUILD) > 0
+
+
+def test_multistep_flag_and_option():
+    """LMEP_F_PERSISTENT is refused for frozen-velocity weights before any
+    device work; the steps-per-launch option accepts 1, 2, 4 and 8 only."""
+    s = _structs()  # frozen-velocity Burgers
+    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 5,
+                                  lmep.LMEP_F_PERSISTENT, ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_UNSUPPORTED, lmep.lmep_last_error()
+    opt = lmep.LMEP_OPT_STEPS_PER_LAUNCH
+    assert lmep.lmep_get_option(opt) == 8
+    for bad in (0, 3, 5, 16, -8):
+        with pytest.raises(lmep.LmepError):
+            lmep.lmep_set_option(opt, bad)
+    with pytest.raises(lmep.LmepError):
+        lmep.lmep_set_option(99, 8)
+    with pytest.raises(lmep.LmepError):
+        lmep.lmep_get_option(99)
+    try:
+        lmep.lmep_set_option(opt, 4)
+        assert lmep.lmep_get_option(opt) == 4
+    finally:
+        lmep.lmep_set_option(opt, 8)
