@@ -52,6 +52,40 @@ def stationary_flops(p: dict) -> float:
     return f
 
 
+SCHEME_ID = {"linear": 0, "etd1": 1, "etd2rk": 2}
+NONLIN_ID = {"none": 0, "burgers_frozen": 1, "kdv": 2, "allen_cahn": 3}
+
+
+def measured_traffic(kernels):
+    """HBM bytes per launch of the named kernels (summed), from the byte-counter
+    summaries under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy
+    probe).  None unless every kernel has a line whose recorded sha256 of the
+    kernel's sources still matches the sources in this tree."""
+    import glob
+    import hashlib
+    table = {}
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(f):
+            t = line.split()
+            if len(t) >= 6 and t[0] == "traffic-bytes-per-launch" and t[3] == "sources-sha256":
+                table[t[1]] = (float(t[2]), t[4], t[5:])
+    total = 0.0
+    for k in kernels:
+        if k not in table:
+            return None
+        val, digest, files = table[k]
+        h = hashlib.sha256()
+        for rel in files:
+            path = os.path.join(ROOT, rel)
+            if not os.path.exists(path):
+                return None
+            h.update(open(path, "rb").read())
+        if h.hexdigest()[:16] != digest:
+            return None
+        total += val
+    return total
+
+
 def make_workload(name: str):
     import workloads
     if name == "burgers":
@@ -201,9 +235,10 @@ def main():
         flops = pade_flops(m, prof["matrices"], prof["squarings"])
         build_s = prof["build_ms"] / 1e3
         achieved = flops / build_s / 1e12
+        kname = f"build_pade_kernel<{p0['n']},{m - p0['n']}>"
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "kernel": f"build_pade_kernel<{p0['n']},{m - p0['n']}>",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname]),
+                "kernel": kname,
                 "avg_launch_us": prof["build_ms"] * 1e3 / prof["build_launches"],
                 "flops_per_launch": flops / prof["build_launches"],
                 "mean_squarings": prof["squarings"] / max(1, prof["matrices"])}
@@ -225,8 +260,15 @@ def main():
         if roof is None:
             # one step per launch: HBM-bound; several: the traffic is paid once
             # per launch and the FP64 work of the steps bounds the kernel
-            roof = dict(extra["apply_alu"] if kb > 1 else extra["apply"], traffic=None,
-                        kernel=("stepk_kernel" if kb > 1 else "apply_kernel"), avg_launch_us=avg_us)
+            if kb > 1:
+                names = sorted({f"stepk_kernel<{p['n']},{SCHEME_ID[p['scheme']]},"
+                                f"{NONLIN_ID[p.get('nonlin', 'none')] if p['scheme'] != 'linear' else 0},{kb}>"
+                                for p in problems})
+            else:
+                names = ["apply_kernel"]
+            roof = dict(extra["apply_alu"] if kb > 1 else extra["apply"],
+                        traffic=measured_traffic(names) if kb > 1 else None,
+                        kernel=" + ".join(names), avg_launch_us=avg_us)
     out = {
         "metric": "node-steps/s (weight build+apply, FP64)",
         "value": value,
