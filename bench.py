@@ -126,6 +126,53 @@ def bench_adjoint(problems, states, steps, every=50):
     return time.perf_counter() - t0, batch.state_size * steps
 
 
+def pair_pade_flops(m: int, squarings: float) -> float:
+    """Algorithmic flops of one Frechet derivative by degree-13 Pade on the
+    block-triangular pair [[A, E], [0, A]] of order-m blocks (2 per
+    multiply-add): a pair product is three m x m products; 6 pair products for
+    U and V (36 m^3), the pair solve (LU of Q 2m^3/3, m right-hand sides for X
+    2m^3, the correction Q_E X 2m^3, m right-hand sides for the E part 2m^3),
+    and one pair product per squaring (6 m^3)."""
+    return 36.0 * m ** 3 + (2.0 / 3.0 + 6.0) * m ** 3 + 6.0 * m ** 3 * squarings
+
+
+def adjoint_roofline(problems, states, reps: int = 5):
+    """Roofline of the Frechet kernel of the reverse step: HIP events around
+    that kernel (LMEP_OPT_PROFILE_ADJOINT) over `reps` reverse steps at u0,
+    and its squarings from a counting forward step at the same state (the
+    pair's scaling is chosen from the same local matrix)."""
+    import torch
+    import paper_2603_15964_amd as lmep
+    batch = lmep.Batch(problems, device="cuda:0")
+    u0 = batch.pack(states)
+    lam = torch.sin(torch.arange(batch.state_size, dtype=torch.float64, device="cuda:0"))
+    w = batch.empty_weights()
+    batch.step(w, u0, 1, lmep.LMEP_F_COUNT)
+    cnt = lmep.lmep_profile_last()
+    mean_s = cnt["squarings"] / max(1, cnt["matrices"])
+    batch.adjoint_step(u0, lam)  # warm-up
+    lmep.lmep_set_option(lmep.LMEP_OPT_PROFILE_ADJOINT, 1)
+    fre_ms, launches, rest_ms = 0.0, 0, 0.0
+    try:
+        for _ in range(reps):
+            batch.adjoint_step(u0, lam)
+            prof = lmep.lmep_profile_last()
+            fre_ms += prof["build_ms"]
+            launches += prof["build_launches"]
+            rest_ms += prof["apply_ms"]
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_PROFILE_ADJOINT, 0)
+    p0 = problems[0]
+    m = p0["n"] + {"linear": 0, "etd1": 1}[p0["scheme"]]
+    flops = batch.state_size * pair_pade_flops(m, mean_s) * reps
+    tf = flops / (fre_ms / 1e3) / 1e12
+    kname = f"adj_frechet_kernel<{p0['n']},{m - p0['n']}>"
+    return {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname]), "kernel": kname,
+            "avg_launch_us": fre_ms * 1e3 / max(1, launches), "flops_per_launch": flops / max(1, launches),
+            "mean_squarings": mean_s, "rest_of_reverse_step_us": rest_ms * 1e3 / reps}
+
+
 def cpu_baseline(problem, u0, budget_s: float = 15.0):
     """The oracle as it stands, on a bounded number of steps of the same workload."""
     import oracle
@@ -184,7 +231,7 @@ def main():
                "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
                "config": {"workload": desc, "instances": len(problems), "nodes": sum(p["N"] for p in problems),
                           "checkpoint_every": 50},
-               "roofline": None}
+               "roofline": adjoint_roofline(problems, states)}
         print(json.dumps(out), flush=True)
         return
     batch = lmep.Batch(problems, device=dev)

@@ -165,9 +165,18 @@ const char* lmep_last_error(void);
  *                             LMEP_F_PERSISTENT: 1, 2, 4 or 8 (default 8).  More
  *                             steps mean less HBM traffic but a wider halo
  *                             recomputed by every block.
+ *  LMEP_OPT_PROFILE_ADJOINT   1: every lmep_adjoint_step records HIP events
+ *                             around its Frechet-derivative kernel(s) and
+ *                             around the whole step on its stream, then
+ *                             synchronises; lmep_profile_last() reports the
+ *                             Frechet kernels as build_ms / build_launches and
+ *                             the rest of the step (transposed apply,
+ *                             reductions) as apply_ms with apply_launches = 1.
+ *                             0 (default): no events, no synchronisation.
  * lmep_set_option returns LMEP_OK or LMEP_ERR_ARG (unknown option or value);
  * lmep_get_option returns the value or LMEP_ERR_ARG. */
 #define LMEP_OPT_STEPS_PER_LAUNCH 1
+#define LMEP_OPT_PROFILE_ADJOINT 2
 int lmep_set_option(int32_t option, int32_t value);
 int32_t lmep_get_option(int32_t option);
 

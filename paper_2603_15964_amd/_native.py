@@ -76,6 +76,7 @@ _lib.lmep_get_option.restype = ctypes.c_int32
 EXPORTED = ("lmep_weight_count", "lmep_scratch_bytes", "lmep_build_weights", "lmep_step", "lmep_adjoint_step",
             "lmep_profile_last", "lmep_last_error", "lmep_set_option", "lmep_get_option")
 LMEP_OPT_STEPS_PER_LAUNCH = 1
+LMEP_OPT_PROFILE_ADJOINT = 2
 
 
 def library() -> ctypes.CDLL:

@@ -483,6 +483,7 @@ hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
     hipLaunchKernelGGL(adj_prep_kernel, dim3((unsigned)a.tiles), blk, 0, s, a.tile_probs, a.nprob, a.fd, a.u,
                        a.g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.frechet_begin && (e = hipEventRecord(a.frechet_begin, s)) != hipSuccess) return e;
     switch (a.n) {
         case 3: e = frechet_n<3>(a, s); break;
         case 5: e = frechet_n<5>(a, s); break;
@@ -494,6 +495,7 @@ hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
+    if (a.frechet_end && (e = hipEventRecord(a.frechet_end, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(adj_ghat_kernel, dim3((unsigned)a.tiles), blk, 0, s, a.tile_probs, a.nprob, a.u, a.lam, a.ws,
                        a.ws_stride, a.ghat);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -27,6 +27,7 @@ thread_local double t_prof_build_ms = 0.0, t_prof_apply_ms = 0.0;
 thread_local int32_t t_prof_build_n = 0, t_prof_apply_n = 0;
 thread_local int64_t t_prof_matrices = 0, t_prof_squarings = 0;
 std::atomic<int> t_steps_per_launch{8};  // LMEP_OPT_STEPS_PER_LAUNCH, process-wide
+std::atomic<int> t_profile_adjoint{0};   // LMEP_OPT_PROFILE_ADJOINT, process-wide
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -375,11 +376,17 @@ int lmep_set_option(int32_t option, int32_t value) {
         t_steps_per_launch.store(value);
         return LMEP_OK;
     }
+    if (option == LMEP_OPT_PROFILE_ADJOINT) {
+        if (value != 0 && value != 1) return fail(LMEP_ERR_ARG, "profile option must be 0 or 1, got %d", value);
+        t_profile_adjoint.store(value);
+        return LMEP_OK;
+    }
     return fail(LMEP_ERR_ARG, "unknown option %d", option);
 }
 
 int32_t lmep_get_option(int32_t option) {
     if (option == LMEP_OPT_STEPS_PER_LAUNCH) return t_steps_per_launch.load();
+    if (option == LMEP_OPT_PROFILE_ADJOINT) return t_profile_adjoint.load();
     return fail(LMEP_ERR_ARG, "unknown option %d", option);
 }
 
@@ -611,6 +618,11 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
     if ((rc = upload(ntab, ttab, base + L.build_tab, base + L.apply_tab, s))) return rc;
     const DevProb* dn = (const DevProb*)(base + L.build_tab);
     const DevProb* dtt = (const DevProb*)(base + L.apply_tab);
+    // optional profiling: events around each group's Frechet kernel and around the whole step
+    Timer timer;
+    timer.on = t_profile_adjoint.load() != 0;
+    HIP_TRY(timer.reserve(groups.size(), 1));
+    HIP_TRY(timer.mark(false, s, true));
     int64_t part_base = 0;
     for (auto& g : groups) {
         AdjointLaunch a;
@@ -632,8 +644,29 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
         a.ws_stride = L.ws_stride;
         a.dparam = (double*)(base + L.dparam);
         a.part = (double*)(base + L.part) + 3 * part_base;
+        if (timer.on) {
+            a.frechet_begin = timer.build[timer.nb].first;
+            a.frechet_end = timer.build[timer.nb].second;
+            ++timer.nb;
+        }
         HIP_TRY(launch_adjoint(a, s));
         part_base += g.tiles;
+    }
+    HIP_TRY(timer.mark(false, s, false));
+    if (timer.on) {
+        HIP_TRY(hipStreamSynchronize(s));
+        double fms = 0.0;
+        for (size_t k = 0; k < timer.nb; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, timer.build[k].first, timer.build[k].second));
+            fms += ms;
+        }
+        float all = 0.f;
+        HIP_TRY(hipEventElapsedTime(&all, timer.apply[0].first, timer.apply[0].second));
+        t_prof_build_ms = fms;
+        t_prof_build_n = (int32_t)timer.nb;
+        t_prof_apply_ms = (double)all - fms;
+        t_prof_apply_n = 1;
     }
     return LMEP_OK;
 }

@@ -115,6 +115,7 @@ struct AdjointLaunch {
     int ws_stride = 0;
     double* dparam = nullptr;
     double* part = nullptr;
+    hipEvent_t frechet_begin = nullptr, frechet_end = nullptr;  // recorded around the Frechet kernel if set
 };
 hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t stream);
 

@@ -139,3 +139,22 @@ def test_gradient_vanishes_at_target():
     loss.backward()
     assert float(loss) == 0.0
     assert torch.all(u0.grad == 0) and torch.all(nu.grad == 0)
+
+
+def test_profiled_reverse_step_is_unchanged():
+    """LMEP_OPT_PROFILE_ADJOINT only adds events: same bits, positive times."""
+    _case("profiled reverse step")
+    p = CASES[0][1]
+    b = lmep.Batch([p], device=DEV)
+    u = b.pack([_state(p, 3)])
+    lam = b.pack([_state(p, 4)])
+    ref_lam, ref_g = b.adjoint_step(u, lam)
+    lmep.lmep_set_option(lmep.LMEP_OPT_PROFILE_ADJOINT, 1)
+    try:
+        got_lam, got_g = b.adjoint_step(u, lam)
+        prof = lmep.lmep_profile_last()
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_PROFILE_ADJOINT, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(ref_lam, got_lam) and torch.equal(ref_g, got_g)
+    assert prof["build_launches"] == 1 and prof["build_ms"] > 0.0 and prof["apply_ms"] >= 0.0
