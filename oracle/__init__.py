@@ -9,7 +9,7 @@ plain dicts (see ``workloads``) with the keys
     bc_left, bc_right
 
 using the string names ``bc in {"periodic", "dirichlet", "neumann"}``,
-``scheme in {"linear", "etd1", "etd2rk"}`` and
+``scheme in {"linear", "etd1", "etd2rk", "etdrk4"}`` and
 ``nonlin in {"none", "burgers_frozen", "kdv", "allen_cahn"}``.
 
 Every function cites the passage of the paper it follows; all arithmetic is
@@ -26,9 +26,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_lmep_oracle.so")
 
 BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
-SCHEME = {"linear": 0, "etd1": 1, "etd2rk": 2}
+SCHEME = {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}
 NONLIN = {"none": 0, "burgers_frozen": 1, "kdv": 2, "allen_cahn": 3}
-P_OF_SCHEME = {"linear": 0, "etd1": 1, "etd2rk": 2}
+P_OF_SCHEME = {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}
+# weight rows stored per node (ETDRK4: E(dt/2), (dt/2)phi1(dt/2), E(dt), dt*alpha, dt*beta, dt*gamma)
+KINDS_OF_SCHEME = {"linear": 1, "etd1": 2, "etd2rk": 3, "etdrk4": 6}
 
 
 class _Prob(ctypes.Structure):
@@ -103,31 +105,32 @@ def window_offset(p: dict, i: int) -> int:
 def augmented_row(L, dt: float, r: int, p: int, nilpotent: bool = True):
     """Row r of the first block row of exp(dt * Atilde) (Sec. 3.1 steps 1-2).
 
-    Returns (W0, W1, W2) = (row r of e^{dt L}, row r of dt phi1(dt L),
-    row r of dt phi2(dt L)); entries beyond p are None.
+    Returns (W0, W1, W2, W3) = rows r of e^{dt L}, dt phi1(dt L),
+    dt phi2(dt L), dt phi3(dt L); entries beyond p are None.
     """
     L = _f64(L)
     n = L.shape[0]
-    out = np.zeros(3 * n)
+    out = np.zeros(4 * n)
     if _load().ora_augmented_row(n, p, _ptr(L), dt, r, 1 if nilpotent else 0, _ptr(out)):
         raise ValueError("bad arguments")
-    return tuple(out[k * n:(k + 1) * n].copy() if k <= p else None for k in range(3))
+    return tuple(out[k * n:(k + 1) * n].copy() if k <= p else None for k in range(4))
 
 
 def augmented_row_complex(L, dt: float, r: int, p: int):
     """Complex version of augmented_row (terminating series; complex-step checks)."""
     L = np.ascontiguousarray(L, dtype=np.complex128)
     n = L.shape[0]
-    out = np.zeros(3 * n, dtype=np.complex128)
+    out = np.zeros(4 * n, dtype=np.complex128)
     if _load().ora_augmented_row_z(n, p, L.ctypes.data, dt, r, out.ctypes.data):
         raise ValueError("bad arguments")
-    return tuple(out[k * n:(k + 1) * n].copy() if k <= p else None for k in range(3))
+    return tuple(out[k * n:(k + 1) * n].copy() if k <= p else None for k in range(4))
 
 
 def build_weights(p: dict, u=None) -> np.ndarray:
-    """Weights of every node, shape [N, 1+p, n] (steps a1-a6)."""
-    N, n, q = int(p["N"]), int(p["n"]), P_OF_SCHEME[p["scheme"]]
-    w = np.zeros((N, q + 1, n))
+    """Weights of every node, shape [N, kinds, n] (steps a1-a6); kinds = 1 + p,
+    or 6 for ETDRK4 (KINDS_OF_SCHEME)."""
+    N, n, q = int(p["N"]), int(p["n"]), KINDS_OF_SCHEME[p["scheme"]]
+    w = np.zeros((N, q, n))
     uu = _f64(u) if u is not None else None
     pr = _prob(p)
     if _load().ora_build_weights(ctypes.byref(pr), _ptr(uu) if uu is not None else None, _ptr(w)):

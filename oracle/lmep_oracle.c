@@ -28,7 +28,7 @@
 #include <string.h>
 
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
-enum { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2 };
+enum { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2, SCH_ETDRK4 = 3 };
 enum { NL_NONE = 0, NL_BURGERS_FROZEN = 1, NL_KDV = 2, NL_ALLEN_CAHN = 3 };
 
 /* The oracle's own problem record (the GPU library has its own, unrelated one). */
@@ -45,7 +45,15 @@ typedef struct {
     double bc_left, bc_right; /* Dirichlet end values */
 } ora_prob;
 
-static int scheme_p(int scheme) { return scheme == SCH_ETD2RK ? 2 : (scheme == SCH_ETD1 ? 1 : 0); }
+/* Highest phi-function a scheme needs (blocks of the augmented matrix minus one). */
+static int scheme_p(int scheme)
+{
+    return scheme == SCH_ETDRK4 ? 3 : (scheme == SCH_ETD2RK ? 2 : (scheme == SCH_ETD1 ? 1 : 0));
+}
+
+/* Weight vectors stored per node: W0..Wp, or for ETDRK4 the six rows
+ * E(dt/2), (dt/2) phi1(dt/2), E(dt), dt alpha, dt beta, dt gamma. */
+static int scheme_kinds(int scheme) { return scheme == SCH_ETDRK4 ? 6 : scheme_p(scheme) + 1; }
 
 /* Step a1 -- stencil of node i: grid indices i+o .. i+o+n-1 (before wrapping).
  * Periodic and Neumann: centred, o = -(n-1)/2.  Dirichlet: the n nearest
@@ -173,7 +181,7 @@ int ora_fd_matrices(int n, double h, double *D1, double *D2, double *D3)
 static int check_prob(const ora_prob *P)
 {
     if (!P || P->n < 1 || (P->n % 2) == 0 || P->N < P->n || !(P->h > 0) || !(P->dt > 0)) return -1;
-    if (P->bc < 0 || P->bc > 2 || P->scheme < 0 || P->scheme > 2 || P->nonlin < 0 || P->nonlin > 3) return -1;
+    if (P->bc < 0 || P->bc > 2 || P->scheme < 0 || P->scheme > 3 || P->nonlin < 0 || P->nonlin > 3) return -1;
     if (P->bc == BC_NEUMANN && (P->n - 1) / 2 > P->N - 1) return -1;
     if (P->nonlin == NL_BURGERS_FROZEN && P->scheme != SCH_ETD1) return -1;
     return 0;
@@ -185,10 +193,10 @@ static int check_prob(const ora_prob *P)
 int64_t ora_window_offset(const ora_prob *P, int64_t i) { return window_offset(i, P->N, P->n, P->bc); }
 
 /* Row r of the augmented exponential for a given local operator L (n x n,
- * row major): out = [W0 | W1 | W2] as in augmented_row. */
+ * row major): out = [W0 | W1 | W2 | W3] as in augmented_row (p + 1 parts). */
 int ora_augmented_row(int n, int p, const double *L, double dt, int r, int nilpotent, double *out)
 {
-    if (n < 1 || n > 63 || p < 0 || p > 2 || r < 0 || r >= n) return -1;
+    if (n < 1 || n > 63 || p < 0 || p > 3 || r < 0 || r >= n) return -1;
     long double Lw[64 * 64];
     for (int a = 0; a < n * n; ++a) Lw[a] = L[a];
     augmented_row_d(n, p, Lw, dt, r, nilpotent, out);
@@ -198,14 +206,15 @@ int ora_augmented_row(int n, int p, const double *L, double dt, int r, int nilpo
 /* Same for a complex local operator (complex-step checks of the exponential). */
 int ora_augmented_row_z(int n, int p, const double complex *L, double dt, int r, double complex *out)
 {
-    if (n < 1 || n > 63 || p < 0 || p > 2 || r < 0 || r >= n) return -1;
+    if (n < 1 || n > 63 || p < 0 || p > 3 || r < 0 || r >= n) return -1;
     long double complex Lw[64 * 64];
     for (int a = 0; a < n * n; ++a) Lw[a] = L[a];
     augmented_row_z(n, p, Lw, dt, r, 1, out);
     return 0;
 }
 
-/* Weights of every node: w[i][kind][k], kind = W0, W1 (ETD), W2 (ETD2RK).
+/* Weights of every node: w[i][kind][k], kind = W0, W1 (ETD), W2 (ETD2RK), or
+ * the six ETDRK4 rows (scheme_kinds).
  * u is read only for the frozen-velocity case (may be NULL otherwise). */
 int ora_build_weights(const ora_prob *P, const double *u, double *w)
 {
@@ -256,7 +265,7 @@ int ora_run_z(const ora_prob *P, double c_im, double nu_im, double delta_im,
  * Dirichlet end nodes are not updated, so their entries of lam are unused. */
 int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, double *lam_out, double *grad)
 {
-    if (check_prob(P) || P->scheme == SCH_ETD2RK || P->nonlin == NL_KDV || P->react != 0.0) return -1;
+    if (check_prob(P) || P->scheme >= SCH_ETD2RK || P->nonlin == NL_KDV || P->react != 0.0) return -1;
     const int n = P->n, p = scheme_p(P->scheme), W = (p + 1) * n;
     const int64_t N = P->N;
     const double gam = P->nl_coef;

@@ -99,7 +99,7 @@ def test_example1_lax_wendroff_beam_warming(nu):
     D1, _, _ = oracle.fd_matrices(3, 1.0)
     for label, r, exprs in _golden_rows("example1_advective_rows.txt"):
         want = np.array([float(_eval(e, nu=nu)) for e in exprs])
-        w0, _, _ = oracle.augmented_row(D1, float(nu), r, 0)
+        w0, *_ = oracle.augmented_row(D1, float(nu), r, 0)
         assert np.max(np.abs(w0 - want)) <= 2e-15 * max(1.0, np.max(np.abs(want))), label
         # the same row through the problem API: a u_x with a = -nu (h = dt = 1)
         p = make_problem(N=3, n=3, bc="dirichlet", h=1.0, dt=1.0, c=-float(nu), scheme="linear")
@@ -116,7 +116,7 @@ def test_example2_ftcs_and_five_point(mu):
         want = np.array([float(_eval(e, mu=mu)) for e in exprs])
         for h in (1.0, 0.1):
             _, D2, _ = oracle.fd_matrices(n, h)
-            w0, _, _ = oracle.augmented_row(D2, float(mu) * h * h, (n - 1) // 2, 0)
+            w0, *_ = oracle.augmented_row(D2, float(mu) * h * h, (n - 1) // 2, 0)
             assert np.max(np.abs(w0 - want)) <= 4e-15 * max(1.0, np.max(np.abs(want))), (label, h)
 
 
@@ -168,20 +168,22 @@ def _phi_series(q, j, n):
     return out
 
 
-@pytest.mark.parametrize("n,p,o", [(5, 2, -1), (5, 2, -2), (7, 1, -3), (7, 1, 0), (9, 2, -4), (3, 1, -2)])
+@pytest.mark.parametrize("n,p,o", [(5, 2, -1), (5, 2, -2), (7, 1, -3), (7, 1, 0), (9, 2, -4), (3, 1, -2),
+                                   (7, 3, -3), (9, 3, -2), (5, 3, 0)])
 def test_theorem2_moments(n, p, o):
     """Exact evolution of the interpolant (Thm 2): applied to (x - x_i)^q, q < n,
-    W0 returns q! [z^q] e^{dt P(z)}, W1 returns q! [z^q] dt phi1(dt P(z)) and W2
-    q! [z^q] dt phi2(dt P(z)), with P(z) = -c z + nu z^2 - delta z^3 the symbol."""
+    W0 returns q! [z^q] e^{dt P(z)}, W1 returns q! [z^q] dt phi1(dt P(z)), W2
+    q! [z^q] dt phi2(dt P(z)) and W3 q! [z^q] dt phi3(dt P(z)), with
+    P(z) = -c z + nu z^2 - delta z^3 the symbol."""
     h, dt, c, nu, de = Fraction(3, 10), Fraction(7, 100), Fraction(13, 10), Fraction(1, 20), Fraction(1, 1000)
     D = oracle.fd_matrices(n, float(h))
     L = -float(c) * D[0] + float(nu) * D[1] - float(de) * D[2]
     r = -o
     W = oracle.augmented_row(L, float(dt), r, p)
     q_ser = _series([0, -c * dt, nu * dt, -de * dt], n)
-    targets = [_phi_series(q_ser, j, n) for j in range(3)]
-    targets[1] = [dt * t for t in targets[1]]
-    targets[2] = [dt * t for t in targets[2]]
+    targets = [_phi_series(q_ser, j, n) for j in range(4)]
+    for j in (1, 2, 3):
+        targets[j] = [dt * t for t in targets[j]]
     xrel = [(k - r) * h for k in range(n)]
     for kind in range(p + 1):
         for q in range(n):
@@ -193,20 +195,22 @@ def test_theorem2_moments(n, p, o):
 # ------------------------------------------------------------------ P6 ----
 @pytest.mark.parametrize("n", [3, 5, 7, 9, 11, 13])
 def test_row_sums(n):
-    """L annihilates constants: rows of e^{dt L}, dt phi1, dt phi2 sum to 1, dt, dt/2."""
+    """L annihilates constants: rows of e^{dt L}, dt phi1, dt phi2, dt phi3 sum to
+    1, dt, dt/2, dt/6 (phi_j(0) = 1/j!)."""
     D = oracle.fd_matrices(n, 0.2)
     L = -0.9 * D[0] + 0.03 * D[1] - 0.0004 * D[2]
     dt = 0.11
     for r in range(n):
-        w0, w1, w2 = oracle.augmented_row(L, dt, r, 2)
+        w0, w1, w2, w3 = oracle.augmented_row(L, dt, r, 3)
         s = max(1.0, np.sum(np.abs(w0)))
         assert abs(w0.sum() - 1.0) <= 1e-14 * s
         assert abs(w1.sum() - dt) <= 1e-14 * s
         assert abs(w2.sum() - dt / 2) <= 1e-14 * s
+        assert abs(w3.sum() - dt / 6) <= 1e-14 * s
 
 
 # ------------------------------------------------------------------ P7 ----
-@pytest.mark.parametrize("n,p", [(5, 1), (5, 2), (7, 1), (9, 2), (11, 1)])
+@pytest.mark.parametrize("n,p", [(5, 1), (5, 2), (7, 1), (9, 2), (11, 1), (5, 3), (9, 3), (13, 3)])
 def test_block_form_equals_compact_form(n, p):
     """First block row of the paper's block exponential (Sec. 3.1) equals the
     harvest from the compact matrix dt [[L^T, e_r, 0], [0, 0, 1], [0, 0, 0]],
@@ -220,11 +224,11 @@ def test_block_form_equals_compact_form(n, p):
         M = np.zeros((m, m))
         M[:n, :n] = L.T
         M[r, n] = 1.0
-        if p == 2:
-            M[n, n + 1] = 1.0
+        for b in range(1, p):
+            M[n + b - 1, n + b] = 1.0
         E = scipy.linalg.expm(dt * M)
         W = oracle.augmented_row(L, dt, r, p)
-        ref = [E[:n, r], E[:n, n]] + ([E[:n, n + 1] / dt] if p == 2 else [])
+        ref = [E[:n, r], E[:n, n]] + [E[:n, n + b] / dt ** b for b in range(1, p)]
         for kind in range(p + 1):
             assert np.max(np.abs(W[kind] - ref[kind])) <= 1e-13 * max(1.0, np.max(np.abs(ref[kind])))
     s = p + 1
@@ -237,6 +241,9 @@ def test_block_form_equals_compact_form(n, p):
     if s == 3:
         assert np.allclose(E[n:2 * n, 2 * n:], dt * np.eye(n), atol=1e-14)
         assert np.allclose(E[2 * n:, 2 * n:], np.eye(n), atol=1e-14)
+    if s == 4:  # second block row [0, I, dt I, dt^2/2 I] (Sec. 3, augmented matrix)
+        assert np.allclose(E[n:2 * n, 2 * n:3 * n], dt * np.eye(n), atol=1e-14)
+        assert np.allclose(E[n:2 * n, 3 * n:], dt * dt / 2 * np.eye(n), atol=1e-14)
 
 
 # ------------------------------------------------------------------ P8 ----
@@ -296,13 +303,15 @@ def _phi_scalar(j, z):
 
 @pytest.mark.parametrize("z", [-3.0, -0.4, 0.05, 0.7, 2.0])
 def test_one_node_stencil_gives_scalar_phi(z):
-    """n = 1: the augmented row reduces to e^z, dt phi1(z), dt phi2(z) with z = react dt."""
+    """n = 1: the augmented row reduces to e^z, dt phi1(z), dt phi2(z), dt phi3(z)
+    with z = react dt."""
     dt = 0.25
     L = np.array([[z / dt]])
-    W = oracle.augmented_row(L, dt, 0, 2, nilpotent=False)
+    W = oracle.augmented_row(L, dt, 0, 3, nilpotent=False)
     assert abs(W[0][0] - math.exp(z)) <= 1e-15 * math.exp(abs(z))
     assert abs(W[1][0] - dt * _phi_scalar(1, z)) <= 2e-15 * dt * math.exp(abs(z))
     assert abs(W[2][0] - dt * _phi_scalar(2, z)) <= 2e-15 * dt * math.exp(abs(z))
+    assert abs(W[3][0] - dt * _phi_scalar(3, z)) <= 2e-15 * dt * math.exp(abs(z))
 
 
 def test_reaction_factor_theorem2():
@@ -311,8 +320,8 @@ def test_reaction_factor_theorem2():
     D = oracle.fd_matrices(n, 0.3)
     K = -0.5 * D[0] + 0.02 * D[1]
     for r in (0, 3, 6):
-        a, _, _ = oracle.augmented_row(K + c0 * np.eye(n), dt, r, 0, nilpotent=False)
-        b, _, _ = oracle.augmented_row(K, dt, r, 0)
+        a, *_ = oracle.augmented_row(K + c0 * np.eye(n), dt, r, 0, nilpotent=False)
+        b, *_ = oracle.augmented_row(K, dt, r, 0)
         assert np.max(np.abs(a - math.exp(c0 * dt) * b)) <= 1e-14 * np.max(np.abs(b))
 
 
