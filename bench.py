@@ -44,6 +44,11 @@ def stationary_flops(p: dict) -> float:
     nl = p.get("nonlin", "none")
     has_n = p["scheme"] != "linear" and nl != "none"
     n_cost = {"allen_cahn": 4.0, "kdv": 3.0 * n + 2.0}.get(nl, 0.0)
+    if p["scheme"] == "etdrk4":
+        # E2.u once, P2.N(u), P2.N(a), E2.a + P2.(2N(b) - N(u)), E.u + A.N(u) +
+        # B.(N(a) + N(b)) + C.N(c): nine n-term sums, three pointwise combinations,
+        # four evaluations of N; without N only E.u
+        return 2.0 * n * 9 + 3.0 + 4.0 * n_cost if has_n else 2.0 * n
     f = 2.0 * n
     if has_n:
         f += 2.0 * n + n_cost
@@ -52,7 +57,7 @@ def stationary_flops(p: dict) -> float:
     return f
 
 
-SCHEME_ID = {"linear": 0, "etd1": 1, "etd2rk": 2}
+SCHEME_ID = {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}
 NONLIN_ID = {"none": 0, "burgers_frozen": 1, "kdv": 2, "allen_cahn": 3}
 
 
@@ -97,6 +102,10 @@ def make_workload(name: str):
     if name == "allen_cahn_batch":
         ps, us = workloads.allen_cahn_batch()
         return ps, us, "4096 Allen-Cahn instances N_k in [512,65536], n_k in {5,7,9,11}, ETD1, stationary weights"
+    if name == "burgers_etdrk4":
+        p, u0 = workloads.burgers_etdrk4()
+        return [p], [u0], ("the paper's Burgers run: periodic N=1048576 n=13, nu=0.03, stationary L = nu D2, "
+                           "N = -u u_x, ETDRK4")
     if name == "advection_diffusion":
         p, u0 = workloads.advection_diffusion()
         return [p], [u0], "periodic advection-diffusion N=256 n=5 CFL 2, LINEAR"
@@ -307,10 +316,13 @@ def main():
         if roof is None:
             # one step per launch: HBM-bound; several: the traffic is paid once
             # per launch and the FP64 work of the steps bounds the kernel
-            if kb > 1:
-                names = sorted({f"stepk_kernel<{p['n']},{SCHEME_ID[p['scheme']]},"
-                                f"{NONLIN_ID[p.get('nonlin', 'none')] if p['scheme'] != 'linear' else 0},{kb}>"
-                                for p in problems})
+            def kname(p):
+                nl = NONLIN_ID[p.get("nonlin", "none")] if p["scheme"] != "linear" else 0
+                if p["scheme"] == "etdrk4":
+                    return f"stepk_rk4_kernel<{p['n']},{nl},{kb}>"
+                return f"stepk_kernel<{p['n']},{SCHEME_ID[p['scheme']]},{nl},{kb}>"
+            if kb > 1 or any(p["scheme"] == "etdrk4" for p in problems):
+                names = sorted({kname(p) for p in problems})
             else:
                 names = ["apply_kernel"]
             roof = dict(extra["apply_alu"] if kb > 1 else extra["apply"],

@@ -57,7 +57,11 @@ enum { LMEP_BC_PERIODIC = 0, LMEP_BC_DIRICHLET = 1, LMEP_BC_NEUMANN = 2 };
 /* Time schemes (Sec. 3): LINEAR u+ = W0.u (p = 0 phi-blocks); ETD1 adds
  * W1.N (ETD-s with s = 1, p = 1); ETD2RK is the Cox-Matthews two-stage
  * scheme a = W0.u + W1.N(u), u+ = a + W2.(N(a) - N(u)) (p = 2). */
-enum { LMEP_LINEAR = 0, LMEP_ETD1 = 1, LMEP_ETD2RK = 2 };
+/* Schemes (Sec. 3): LINEAR u+ = W0 u; ETD1 (ETD-s with s = 1); ETD2RK
+ * (Cox-Matthews); ETDRK4 (the four-stage scheme of Sec. 3 with
+ * alpha, beta, gamma built from phi1..phi3, stationary weights only,
+ * n + 3 <= 16).  p = 0, 1, 2, 3 phi-functions. */
+enum { LMEP_LINEAR = 0, LMEP_ETD1 = 1, LMEP_ETD2RK = 2, LMEP_ETDRK4 = 3 };
 
 /* Nonlinear terms N(u), g = nl_coef:
  *  BURGERS_FROZEN  u_t + g u u_x = ...: the node's own velocity is frozen into
@@ -97,7 +101,7 @@ typedef struct {
     double  nu;         /* diffusion coefficient                                      */
     double  delta;      /* dispersion coefficient                                     */
     double  react;      /* linear reaction coefficient (c0 of Thm 2)                  */
-    int32_t scheme;     /* LMEP_LINEAR / LMEP_ETD1 / LMEP_ETD2RK                      */
+    int32_t scheme;     /* LMEP_LINEAR / LMEP_ETD1 / LMEP_ETD2RK / LMEP_ETDRK4        */
     int32_t nonlin;     /* LMEP_NL_*                                                  */
     double  nl_coef;    /* g of the nonlinear term                                    */
     double  bc_left;    /* Dirichlet value held at node 0                             */
@@ -106,13 +110,16 @@ typedef struct {
     int64_t weight_off; /* offset (in doubles) of the weights in the weight buffer    */
 } lmep_problem;
 
-/* Number of doubles of harvested weights one instance needs (p = 0, 1, 2 for
- * LINEAR, ETD1, ETD2RK):
- *   weights rebuilt per node (BURGERS_FROZEN): (1+p) * n * N, layout
+/* Number of doubles of harvested weights one instance needs (kinds = 1 + p =
+ * 1, 2, 3 for LINEAR, ETD1, ETD2RK; 6 for ETDRK4):
+ *   weights rebuilt per node (BURGERS_FROZEN): kinds * n * N, layout
  *       [kind][k][i]  -- weight k of node i's stencil, kind 0 = W0 (row of
  *       e^{dt L}), 1 = W1 (row of dt phi1(dt L)), 2 = W2 (row of dt phi2(dt L));
- *   stationary operators: (1+p) * n * n, layout [kind][r][k] -- the harvest of
+ *   stationary operators: kinds * n * n, layout [kind][r][k] -- the harvest of
  *       stencil row r (every node harvests row r = -offset of its stencil).
+ *       ETDRK4's kinds are rows of e^{L dt/2}, (dt/2) phi1(L dt/2), e^{L dt},
+ *       dt alpha, dt beta and dt gamma with alpha = phi1 - 3 phi2 + 4 phi3,
+ *       beta = 2 phi2 - 4 phi3, gamma = 4 phi3 - phi2 (phi_j = phi_j(L dt)).
  * Returns -1 for an invalid problem. */
 int64_t lmep_weight_count(const lmep_problem* prob);
 
@@ -135,7 +142,7 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
               double* d_u_out, int32_t n_steps, uint32_t flags, void* d_scratch,
               size_t scratch_bytes, void* hip_stream);
 
-/* Reverse of one LINEAR or ETD1 step (not ETD2RK / KDV).  Given the forward
+/* Reverse of one LINEAR or ETD1 step (not ETD2RK / ETDRK4 / KDV).  Given the forward
  * state d_u_k = u^k and d_lambda_next = d loss / d u^{k+1}, write
  * d_lambda_k = d loss / d u^k and add this step's parameter derivatives to
  * d_grad[3 * k + {0, 1, 2}] = (d loss/d nu, d loss/d c, d loss/d delta) of

@@ -21,14 +21,14 @@ LMEP_ERR_NONFINITE = -4
 LMEP_ERR_SCRATCH = -5
 
 LMEP_BC_PERIODIC, LMEP_BC_DIRICHLET, LMEP_BC_NEUMANN = 0, 1, 2
-LMEP_LINEAR, LMEP_ETD1, LMEP_ETD2RK = 0, 1, 2
+LMEP_LINEAR, LMEP_ETD1, LMEP_ETD2RK, LMEP_ETDRK4 = 0, 1, 2, 3
 LMEP_NL_NONE, LMEP_NL_BURGERS_FROZEN, LMEP_NL_KDV, LMEP_NL_ALLEN_CAHN = 0, 1, 2, 3
 LMEP_F_GRAPH, LMEP_F_PERSISTENT, LMEP_F_CHECK_FINITE, LMEP_F_PROFILE, LMEP_F_COUNT = 0x1, 0x2, 0x4, 0x8, 0x10
 
 OP_BUILD, OP_STEP, OP_ADJOINT = 0, 1, 2
 
 BC_NAMES = {"periodic": LMEP_BC_PERIODIC, "dirichlet": LMEP_BC_DIRICHLET, "neumann": LMEP_BC_NEUMANN}
-SCHEME_NAMES = {"linear": LMEP_LINEAR, "etd1": LMEP_ETD1, "etd2rk": LMEP_ETD2RK}
+SCHEME_NAMES = {"linear": LMEP_LINEAR, "etd1": LMEP_ETD1, "etd2rk": LMEP_ETD2RK, "etdrk4": LMEP_ETDRK4}
 NONLIN_NAMES = {"none": LMEP_NL_NONE, "burgers_frozen": LMEP_NL_BURGERS_FROZEN, "kdv": LMEP_NL_KDV,
                 "allen_cahn": LMEP_NL_ALLEN_CAHN}
 

@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
         A[k] = lane < NN ? v : 0.0;
     }
     if constexpr (PP >= 1) A[NN] = (lane == r) ? dt : 0.0;
-    if constexpr (PP == 2) A[NN + 1] = (lane == NN) ? dt : 0.0;
+    if constexpr (PP >= 2) A[NN + 1] = (lane == NN) ? dt : 0.0;
+    if constexpr (PP >= 3) A[NN + 2] = (lane == NN + 1) ? dt : 0.0;
 
     double rs = 0.0;
 #pragma unroll
@@ -163,13 +164,15 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
 #pragma unroll
         for (int j = 0; j < M; ++j) X[j] = A[j];
     }
-    double w0 = column(X, r), w1 = 0.0, w2 = 0.0;
+    double w0 = column(X, r), w1 = 0.0, w2 = 0.0, w3 = 0.0;
     if constexpr (PP >= 1) w1 = X[NN];
-    if constexpr (PP == 2) w2 = X[NN + 1];
+    if constexpr (PP >= 2) w2 = X[NN + 1];
+    if constexpr (PP >= 3) w3 = X[NN + 2];
     if (q >= 1) {
         w0 = square_column(X, w0);
         if constexpr (PP >= 1) w1 = square_column(X, w1);
-        if constexpr (PP == 2) w2 = square_column(X, w2);
+        if constexpr (PP >= 2) w2 = square_column(X, w2);
+        if constexpr (PP >= 3) w3 = square_column(X, w3);
     }
 
     if (stats && lane == 0) {  // profiling only: matrices built and squarings done
@@ -183,7 +186,16 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
         wb[(int64_t)lane * N + node] = w0;
         if constexpr (PP >= 1) wb[(int64_t)(NN + lane) * N + node] = w1;
         if constexpr (PP == 2) wb[(int64_t)(2 * NN + lane) * N + node] = w2 / dt;
+    } else if constexpr (PP == 3) {
+        // ETDRK4 full step: e^{L dt} and dt alpha, dt beta, dt gamma from the
+        // rows dt phi1 = w1, dt phi2 = w2 / dt, dt phi3 = w3 / dt^2 (Sec. 3)
+        const double f1 = w1, f2 = w2 / dt, f3 = w3 / (dt * dt);
+        wb[(2 * NN + r) * NN + lane] = w0;
+        wb[(3 * NN + r) * NN + lane] = f1 - 3.0 * f2 + 4.0 * f3;
+        wb[(4 * NN + r) * NN + lane] = 2.0 * f2 - 4.0 * f3;
+        wb[(5 * NN + r) * NN + lane] = 4.0 * f3 - f2;
     } else {
+        // plain harvest, or the ETDRK4 half step (p = 1 at dt / 2: kinds 0, 1)
         wb[r * NN + lane] = w0;
         if constexpr (PP >= 1) wb[(NN + r) * NN + lane] = w1;
         if constexpr (PP == 2) wb[(2 * NN + r) * NN + lane] = w2 / dt;
@@ -210,6 +222,7 @@ hipError_t launch_n(int p, const DevProb* d_probs, int nprob, int64_t items, con
         case 0: return launch_np<NN, 0>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
         case 1: return launch_np<NN, 1>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
         case 2: return launch_np<NN, 2>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 3: return launch_np<NN, 3>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
         default: return hipErrorInvalidValue;
     }
 }

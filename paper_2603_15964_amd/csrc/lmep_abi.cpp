@@ -43,11 +43,14 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(LMEP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-int scheme_p(int scheme) { return scheme == LMEP_ETD2RK ? 2 : (scheme == LMEP_ETD1 ? 1 : 0); }
+int scheme_p(int scheme) {
+    return scheme == LMEP_ETDRK4 ? 3 : (scheme == LMEP_ETD2RK ? 2 : (scheme == LMEP_ETD1 ? 1 : 0));
+}
+int scheme_kinds(int scheme) { return scheme == LMEP_ETDRK4 ? 6 : 1 + scheme_p(scheme); }
 bool frozen(const lmep_problem& q) { return q.nonlin == LMEP_NL_BURGERS_FROZEN; }
 
 int64_t weight_count(const lmep_problem& q) {
-    const int64_t kinds = 1 + scheme_p(q.scheme);
+    const int64_t kinds = scheme_kinds(q.scheme);
     return frozen(q) ? kinds * q.n * q.N : kinds * q.n * q.n;
 }
 
@@ -65,7 +68,7 @@ int check_problem(const lmep_problem& q, int k) {
         !finite(q.bc_left) || !finite(q.bc_right))
         return fail(LMEP_ERR_ARG, "instance %d: non-finite coefficient", k);
     if (q.bc < 0 || q.bc > 2) return fail(LMEP_ERR_ARG, "instance %d: unknown boundary type %d", k, q.bc);
-    if (q.scheme < 0 || q.scheme > 2) return fail(LMEP_ERR_ARG, "instance %d: unknown scheme %d", k, q.scheme);
+    if (q.scheme < 0 || q.scheme > 3) return fail(LMEP_ERR_ARG, "instance %d: unknown scheme %d", k, q.scheme);
     if (q.nonlin < 0 || q.nonlin > 3) return fail(LMEP_ERR_ARG, "instance %d: unknown nonlinearity %d", k, q.nonlin);
     if (q.scheme == LMEP_LINEAR && q.nonlin != LMEP_NL_NONE)
         return fail(LMEP_ERR_ARG, "instance %d: LINEAR scheme with a nonlinear term", k);
@@ -126,7 +129,7 @@ Layout layout(const lmep_problem* prob, int32_t count, int op) {
     size_t off = 0;
     const size_t tab = align256(sizeof(DevProb) * (size_t)count);
     L.build_tab = off;
-    off += tab;
+    off += 2 * tab;  // an ETDRK4 instance has two build parts
     L.apply_tab = off;
     off += tab;
     if (op == 1) {
@@ -187,6 +190,7 @@ DevProb to_dev(const lmep_problem& q, int index) {
 struct Group {
     int n = 0, p = 0, scheme = 0, nonlin = 0, tile = 0;
     bool pernode = false;
+    bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
 };
@@ -194,9 +198,20 @@ struct Group {
 // Build groups: keyed by (n, p).  Instances selected by `want`.
 template <class Want>
 std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want, std::vector<DevProb>& tab) {
-    std::map<std::pair<int, int>, std::vector<int>> by;
-    for (int k = 0; k < count; ++k)
-        if (want(prob[k])) by[{prob[k].n, scheme_p(prob[k].scheme)}].push_back(k);
+    // one build part per exponential: ETDRK4 needs two (p = 3 at dt, p = 1 at dt/2)
+    struct Part {
+        int k, harvest;
+    };
+    std::map<std::pair<int, int>, std::vector<Part>> by;
+    for (int k = 0; k < count; ++k) {
+        if (!want(prob[k])) continue;
+        if (prob[k].scheme == LMEP_ETDRK4) {
+            by[{prob[k].n, 3}].push_back({k, HARVEST_RK4_FULL});
+            by[{prob[k].n, 1}].push_back({k, HARVEST_RK4_HALF});
+        } else {
+            by[{prob[k].n, scheme_p(prob[k].scheme)}].push_back({k, HARVEST_PLAIN});
+        }
+    }
     std::vector<Group> groups;
     for (auto& kv : by) {
         Group g;
@@ -204,10 +219,13 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         g.p = kv.first.second;
         g.first = (int)tab.size();
         int64_t items = 0;
-        for (int k : kv.second) {
-            DevProb d = to_dev(prob[k], k);
+        for (const Part& part : kv.second) {
+            DevProb d = to_dev(prob[part.k], part.k);
+            d.p = g.p;
+            d.harvest = part.harvest;
+            if (part.harvest == HARVEST_RK4_HALF) d.dt = 0.5 * prob[part.k].dt;
             d.item_begin = items;
-            items += frozen(prob[k]) ? prob[k].N : prob[k].n;
+            items += frozen(prob[part.k]) ? prob[part.k].N : prob[part.k].n;
             tab.push_back(d);
         }
         g.count = (int)kv.second.size();
@@ -232,8 +250,9 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         g.first = (int)tab.size();
         int64_t nodes = 0;
         for (int k : kv.second) nodes += prob[k].N;
-        g.tile = multi_kb > 0 ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb)
-                              : (nodes < kSmallGroupNodes ? kApplyTileSmall : kApplyTile);
+        g.stepk = multi_kb > 0 || g.scheme == LMEP_ETDRK4;
+        g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb > 0 ? multi_kb : 1)
+                         : (nodes < kSmallGroupNodes ? kApplyTileSmall : kApplyTile);
         int64_t tiles = 0;
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
@@ -495,7 +514,7 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
             HIP_TRY(timer.mark(false, s, true));
             int64_t tile0 = 0;
             for (auto& gr : agroups) {
-                if (multi)
+                if (gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
                                          dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
                 else
@@ -572,7 +591,7 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
     if (rc) return rc;
     for (int k = 0; k < count; ++k) {
         const lmep_problem& q = prob[k];
-        if (q.scheme == LMEP_ETD2RK || q.nonlin == LMEP_NL_KDV)
+        if (q.scheme == LMEP_ETD2RK || q.scheme == LMEP_ETDRK4 || q.nonlin == LMEP_NL_KDV)
             return fail(LMEP_ERR_UNSUPPORTED, "instance %d: the reverse step covers LINEAR and ETD1 without KdV", k);
     }
     if (!d_u_k || !d_lambda_next || !d_lambda_k || !d_grad) return fail(LMEP_ERR_ARG, "NULL pointer argument");

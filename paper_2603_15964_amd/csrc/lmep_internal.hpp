@@ -24,14 +24,18 @@ struct DevProb {
     int64_t weight_off;
     int64_t item_begin;
     int32_t n, bc, scheme, nonlin;
-    int32_t p, frozen, index, pad;
+    int32_t p, frozen, index, harvest;  // harvest: what the build writes (HARVEST_*)
     double h, dt, c, nu, delta, react, nl_coef, bc_left, bc_right;
     double pad2[3];
 };
 static_assert(sizeof(DevProb) == 160, "DevProb layout");
 
 enum : int { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
-enum : int { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2 };
+enum : int { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2, SCH_ETDRK4 = 3 };
+// Build parts: the harvested rows W0..Wp of one exponential, or for ETDRK4
+// the full step (p = 3 at dt: kinds 2..5 = e^{L dt}, dt alpha, dt beta,
+// dt gamma) and the half step (p = 1 at dt/2: kinds 0, 1).
+enum : int { HARVEST_PLAIN = 0, HARVEST_RK4_FULL = 1, HARVEST_RK4_HALF = 2 };
 enum : int { NL_NONE = 0, NL_BURGERS = 1, NL_KDV = 2, NL_AC = 3 };
 
 // Table of finite-difference weights on the centred integer stencil
@@ -68,8 +72,8 @@ hipError_t launch_apply(int n, int tile, int scheme, int nonlin, bool pernode, c
 // stencil application spoils (n-1)/2 positions at each open end).
 constexpr int kStepRegion = 2048;
 __host__ __device__ constexpr int stepk_apps(int scheme, int nonlin) {
-    // stencil applications per step
-    return (scheme == SCH_ETD2RK && nonlin != NL_NONE ? 2 : 1) *
+    // stencil applications per step: one per stage, one more per KdV N pass
+    return (scheme == SCH_ETDRK4 && nonlin != NL_NONE ? 4 : (scheme == SCH_ETD2RK && nonlin != NL_NONE ? 2 : 1)) *
            (scheme != SCH_LINEAR && nonlin == NL_KDV ? 2 : 1);
 }
 __host__ __device__ constexpr int stepk_halo(int n, int scheme, int nonlin, int kb) {
@@ -79,6 +83,7 @@ __host__ __device__ constexpr int stepk_tile(int n, int scheme, int nonlin, int 
     return kStepRegion - 2 * stepk_halo(n, scheme, nonlin, kb);
 }
 static_assert(stepk_tile(15, SCH_ETD2RK, NL_KDV, 8) >= 1024, "halo too wide for the staged region");
+static_assert(stepk_tile(13, SCH_ETDRK4, NL_KDV, 8) >= 1024, "halo too wide for the staged region");
 template <int KB>
 hipError_t launch_stepk_depth(int n, int scheme, int nonlin, int ksteps, const DevProb* d_probs,
                               const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,

@@ -42,8 +42,8 @@ def make_problem(**kw) -> dict:
 
 
 def stencil_p(scheme: str) -> int:
-    """Number of phi-weight vectors beyond W0 that a scheme uses."""
-    return {"linear": 0, "etd1": 1, "etd2rk": 2}[scheme]
+    """Highest phi-function a scheme uses (p; its augmented local matrix has order n + p)."""
+    return {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}[scheme]
 
 
 # ---------------------------------------------------------------- C1 ------
@@ -146,5 +146,20 @@ def burgers_adjoint_batch(batch: int = 64, N: int = 262144, n: int = 9, nu: floa
     return p, pt, u0s
 
 
+# ------------------------------------------------- ETDRK4 (next row) ------
+def burgers_etdrk4(N: int = 2 ** 20, n: int = 13, nu: float = 0.03, mu: float = 0.5):
+    """The paper's own Burgers run (Sec. 4.3.1) at a throughput size: periodic
+    [-pi, pi), nu = 0.03, u0 = exp(-10 sin^2(x/2)), stationary L = nu D2 and
+    N = -u u_x in the conservative form -(1/2) d/dx(u^2) (the KdV-form term with
+    coefficient 1), ETDRK4.  n = 13 is the largest stencil with n + 3 <= 16
+    (the paper uses n = 19); dt = mu h^2 / nu.  Deterministic, no seed."""
+    h = 2.0 * math.pi / N
+    x = -math.pi + h * np.arange(N)
+    u0 = np.exp(-10.0 * np.sin(x / 2.0) ** 2)
+    p = make_problem(N=N, n=n, bc="periodic", h=h, dt=mu * h * h / nu, nu=nu, scheme="etdrk4", nonlin="kdv",
+                     nl_coef=1.0)
+    return p, u0
+
+
 STEPS = {"advection_diffusion": 100, "burgers": 1000, "kdv": 2000, "allen_cahn_batch": 500,
-         "burgers_adjoint_batch": 500}
+         "burgers_adjoint_batch": 500, "burgers_etdrk4": 1000}
