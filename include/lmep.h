@@ -136,7 +136,8 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
 
 /* Advance every instance n_steps >= 1 steps: d_u_out = (step)^n_steps(d_u_in).
  * d_w must hold the weights of stationary instances (lmep_build_weights);
- * for BURGERS_FROZEN instances the weights are rebuilt into d_w every step.
+ * for BURGERS_FROZEN instances the weights are rebuilt every step (into d_w
+ * only when LMEP_OPT_FUSE_FROZEN is 0).
  * d_u_in is not modified and must not overlap d_u_out. */
 int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in,
               double* d_u_out, int32_t n_steps, uint32_t flags, void* d_scratch,
@@ -180,10 +181,19 @@ const char* lmep_last_error(void);
  *                             the rest of the step (transposed apply,
  *                             reductions) as apply_ms with apply_launches = 1.
  *                             0 (default): no events, no synchronisation.
+ *  LMEP_OPT_FUSE_FROZEN       1 (default): lmep_step advances BURGERS_FROZEN
+ *                             instances with one kernel per step that builds
+ *                             each node's weights and applies them at once;
+ *                             d_w is then not written.  0: build the weights
+ *                             into d_w, then apply them (two kernels).  The
+ *                             two agree to rounding, not bit for bit (the
+ *                             fused kernel sums a node's stencil terms as a
+ *                             tree over the lanes).
  * lmep_set_option returns LMEP_OK or LMEP_ERR_ARG (unknown option or value);
  * lmep_get_option returns the value or LMEP_ERR_ARG. */
 #define LMEP_OPT_STEPS_PER_LAUNCH 1
 #define LMEP_OPT_PROFILE_ADJOINT 2
+#define LMEP_OPT_FUSE_FROZEN 3
 int lmep_set_option(int32_t option, int32_t value);
 int32_t lmep_get_option(int32_t option);
 

@@ -77,6 +77,7 @@ EXPORTED = ("lmep_weight_count", "lmep_scratch_bytes", "lmep_build_weights", "lm
             "lmep_profile_last", "lmep_last_error", "lmep_set_option", "lmep_get_option")
 LMEP_OPT_STEPS_PER_LAUNCH = 1
 LMEP_OPT_PROFILE_ADJOINT = 2
+LMEP_OPT_FUSE_FROZEN = 3
 
 
 def library() -> ctypes.CDLL:

@@ -97,12 +97,19 @@ __device__ __forceinline__ double square_column(const double (&X)[M], double v) 
     return c;
 }
 
-template <int NN, int PP>
+// FUSE (frozen-velocity ETD1 only): instead of writing the weights, the row
+// goes on to the node's update (step a8): lane k forms W0[k] u_j + W1[k] N_j at
+// stencil position j = S_i(k), with N_j = -g (u_j - u_i) (du/dx)_j and
+// (du/dx)_j from j's own stencil, and the sixteen lanes' terms are summed into
+// u_out[i].  The weights never reach HBM.
+template <int NN, int PP, bool FUSE>
 __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restrict__ probs, int nprob, int64_t items,
                                                          const double* __restrict__ fd, const double* __restrict__ u,
                                                          double* __restrict__ w,
-                                                         unsigned long long* __restrict__ stats) {
+                                                         unsigned long long* __restrict__ stats,
+                                                         double* __restrict__ u_out) {
     constexpr int M = NN + PP;
+    static_assert(!FUSE || PP == 1, "the fused update is ETD1");
     static_assert(M <= kMaxM, "local matrix exceeds one DPP row");
     const int lane = threadIdx.x & 15;
     const int64_t item = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
@@ -179,6 +186,31 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
         atomicAdd(stats, 1ull);
         atomicAdd(stats + 1, (unsigned long long)s);
     }
+    if constexpr (FUSE) {
+        const int64_t N = P.N;
+        const int bc = P.bc;
+        const double* __restrict__ us = u + P.state_off;
+        double term = 0.0;
+        if (lane < NN) {
+            const double ih = 1.0 / P.h;
+            const int64_t j = map_index(node - r + lane, N, bc);  // stencil position (mirror node for Neumann)
+            const double uj = us[j];
+            const int64_t oj = window_offset(j, N, NN, bc);
+            const int rj = (int)(-oj);
+            double d = 0.0;
+#pragma unroll
+            for (int l = 0; l < NN; ++l) d += (fd[fd_index(NN, 0, rj, l)] * ih) * us[map_index(j + oj + l, N, bc)];
+            const double Nj = -P.nl_coef * (uj - us[node]) * d;
+            term = w0 * uj;
+            term += w1 * Nj;
+        }
+        const double sum = row_sum16(term);
+        if (lane == 0) {
+            const bool fixed = bc == BC_DIRICHLET && (node == 0 || node == N - 1);
+            u_out[P.state_off + node] = fixed ? (node == 0 ? P.bc_left : P.bc_right) : sum;
+        }
+        return;
+    }
     if (lane >= NN) return;
     double* __restrict__ wb = w + P.weight_off;
     if (frozen) {
@@ -204,25 +236,33 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
 
 template <int NN, int PP>
 hipError_t launch_np(const DevProb* d_probs, int nprob, int64_t items, const double* fd, const double* d_u,
-                     double* d_w, unsigned long long* stats, hipStream_t stream) {
+                     double* d_w, unsigned long long* stats, double* d_u_out, hipStream_t stream) {
     if constexpr (NN + PP > kMaxM) {
         return hipErrorInvalidValue;
     } else {
         const int64_t blocks = (items + 15) / 16;
-        hipLaunchKernelGGL((build_pade_kernel<NN, PP>), dim3((unsigned)blocks), dim3(256), 0, stream, d_probs, nprob,
-                           items, fd, d_u, d_w, stats);
+        if (d_u_out) {
+            if constexpr (PP == 1)
+                hipLaunchKernelGGL((build_pade_kernel<NN, PP, true>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                                   d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out);
+            else
+                return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((build_pade_kernel<NN, PP, false>), dim3((unsigned)blocks), dim3(256), 0, stream,
+                               d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out);
+        }
         return hipGetLastError();
     }
 }
 
 template <int NN>
 hipError_t launch_n(int p, const DevProb* d_probs, int nprob, int64_t items, const double* fd, const double* d_u,
-                    double* d_w, unsigned long long* stats, hipStream_t stream) {
+                    double* d_w, unsigned long long* stats, double* d_u_out, hipStream_t stream) {
     switch (p) {
-        case 0: return launch_np<NN, 0>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 1: return launch_np<NN, 1>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 2: return launch_np<NN, 2>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 3: return launch_np<NN, 3>(d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 0: return launch_np<NN, 0>(d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 1: return launch_np<NN, 1>(d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 2: return launch_np<NN, 2>(d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 3: return launch_np<NN, 3>(d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -230,16 +270,17 @@ hipError_t launch_n(int p, const DevProb* d_probs, int nprob, int64_t items, con
 }  // namespace
 
 hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t items, const double* fd,
-                        const double* d_u, double* d_w, unsigned long long* stats, hipStream_t stream) {
+                        const double* d_u, double* d_w, unsigned long long* stats, hipStream_t stream,
+                        double* d_u_out) {
     if (items <= 0) return hipSuccess;
     switch (n) {
-        case 3: return launch_n<3>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 5: return launch_n<5>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 7: return launch_n<7>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 9: return launch_n<9>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 11: return launch_n<11>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 13: return launch_n<13>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
-        case 15: return launch_n<15>(p, d_probs, nprob, items, fd, d_u, d_w, stats, stream);
+        case 3: return launch_n<3>(p, d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 5: return launch_n<5>(p, d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 7: return launch_n<7>(p, d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 9: return launch_n<9>(p, d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 11: return launch_n<11>(p, d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 13: return launch_n<13>(p, d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
+        case 15: return launch_n<15>(p, d_probs, nprob, items, fd, d_u, d_w, stats, d_u_out, stream);
         default: return hipErrorInvalidValue;
     }
 }

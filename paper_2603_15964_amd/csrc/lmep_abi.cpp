@@ -28,6 +28,7 @@ thread_local int32_t t_prof_build_n = 0, t_prof_apply_n = 0;
 thread_local int64_t t_prof_matrices = 0, t_prof_squarings = 0;
 std::atomic<int> t_steps_per_launch{8};  // LMEP_OPT_STEPS_PER_LAUNCH, process-wide
 std::atomic<int> t_profile_adjoint{0};   // LMEP_OPT_PROFILE_ADJOINT, process-wide
+std::atomic<int> t_fuse_frozen{1};       // LMEP_OPT_FUSE_FROZEN, process-wide
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -395,9 +396,9 @@ int lmep_set_option(int32_t option, int32_t value) {
         t_steps_per_launch.store(value);
         return LMEP_OK;
     }
-    if (option == LMEP_OPT_PROFILE_ADJOINT) {
-        if (value != 0 && value != 1) return fail(LMEP_ERR_ARG, "profile option must be 0 or 1, got %d", value);
-        t_profile_adjoint.store(value);
+    if (option == LMEP_OPT_PROFILE_ADJOINT || option == LMEP_OPT_FUSE_FROZEN) {
+        if (value != 0 && value != 1) return fail(LMEP_ERR_ARG, "option %d takes 0 or 1, got %d", option, value);
+        (option == LMEP_OPT_PROFILE_ADJOINT ? t_profile_adjoint : t_fuse_frozen).store(value);
         return LMEP_OK;
     }
     return fail(LMEP_ERR_ARG, "unknown option %d", option);
@@ -406,6 +407,7 @@ int lmep_set_option(int32_t option, int32_t value) {
 int32_t lmep_get_option(int32_t option) {
     if (option == LMEP_OPT_STEPS_PER_LAUNCH) return t_steps_per_launch.load();
     if (option == LMEP_OPT_PROFILE_ADJOINT) return t_profile_adjoint.load();
+    if (option == LMEP_OPT_FUSE_FROZEN) return t_fuse_frozen.load();
     return fail(LMEP_ERR_ARG, "unknown option %d", option);
 }
 
@@ -499,6 +501,9 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     }
 
+    const bool fuse = t_fuse_frozen.load() != 0;
+    bool apply_launched = false;  // any apply kernel besides the fused ones
+    for (auto& gr : agroups) apply_launched |= !(gr.pernode && fuse);
     auto enqueue = [&]() -> int {
         // destinations alternate between the scratch state and d_u_out so that
         // the last step lands in d_u_out and no step works in place
@@ -506,23 +511,27 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
             const double* src = (st == 0) ? d_u_in : (((launches - st) % 2 == 0) ? d_u_out : bufA);
             double* dst = ((launches - 1 - st) % 2 == 0) ? d_u_out : bufA;
             if (!bgroups.empty()) {
+                // frozen-velocity groups: weights rebuilt, and with fusion applied
+                // in the same kernel (their apply groups are then skipped)
                 HIP_TRY(timer.mark(true, s, true));
                 for (auto& gr : bgroups)
-                    HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters, s));
+                    HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters, s,
+                                         fuse ? dst : nullptr));
                 HIP_TRY(timer.mark(true, s, false));
             }
-            HIP_TRY(timer.mark(false, s, true));
+            if (apply_launched) HIP_TRY(timer.mark(false, s, true));
             int64_t tile0 = 0;
             for (auto& gr : agroups) {
-                if (gr.stepk)
+                const bool fused = gr.pernode && fuse;  // already advanced by its build kernel
+                if (!fused && gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
                                          dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
-                else
+                else if (!fused)
                     HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first,
                                          dti + tile0, gr.items, fd, d_w, src, dst, s));
                 tile0 += gr.items;
             }
-            HIP_TRY(timer.mark(false, s, false));
+            if (apply_launched) HIP_TRY(timer.mark(false, s, false));
         }
         return LMEP_OK;
     };

@@ -52,10 +52,12 @@ hipError_t fd_table_init(const double** d_table_out);
 
 // Build weights for one group of instances sharing (n, p).  items = total
 // matrices of the group.  stats (nullable, profiling): stats[0] += matrices
-// built, stats[1] += squarings performed.
+// built, stats[1] += squarings performed.  d_u_out (frozen-velocity ETD1
+// groups only): fuse the step -- each node's row applies its weights at once
+// and writes the node's new value into d_u_out; d_w is then not touched.
 hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t items,
                         const double* fd, const double* d_u, double* d_w, unsigned long long* stats,
-                        hipStream_t stream);
+                        hipStream_t stream, double* d_u_out = nullptr);
 
 // One time step over a group of instances sharing (n, scheme, nonlin,
 // per-node weights); ETD2RK's two stages run in one kernel.  d_tile_inst maps

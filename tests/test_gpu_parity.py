@@ -250,3 +250,26 @@ def test_full_size_kdv_conservation_and_sample():
     assert state_rel_err(got, oracle.run(p, u0, 3)) <= 1e-12
     got50 = gpu_run([p], [u0], 50)[0]
     assert abs(got50.sum() - u0.sum()) <= 1e-11 * np.sum(np.abs(u0))
+
+
+@pytest.mark.parametrize("name,make", [
+    ("burgers dirichlet n7", lambda: workloads.burgers(N=3000, n=7)),
+    ("burgers periodic n9", lambda: (dict(workloads.burgers(N=2000, n=9)[0], bc="periodic"),
+                                     np.sin(np.linspace(0, 2 * np.pi, 2000, endpoint=False)))),
+    ("burgers neumann n5", lambda: (dict(workloads.burgers(N=1500, n=5)[0], bc="neumann", c=0.2),
+                                    0.6 * np.cos(np.linspace(0, 3 * np.pi, 1500)) + 0.1)),
+], ids=["dirichlet", "periodic", "neumann"])
+def test_fused_frozen_step_matches_two_kernel_step(name, make):
+    """Frozen velocity: the fused build-and-apply kernel (default) and the
+    build-then-apply pair agree to rounding and both match the oracle."""
+    _print_case("fused vs unfused", name)
+    p, u0 = make()
+    fused = gpu_run([p], [u0], 5)[0]
+    lmep.lmep_set_option(lmep.LMEP_OPT_FUSE_FROZEN, 0)
+    try:
+        pair = gpu_run([p], [u0], 5)[0]
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_FUSE_FROZEN, 1)
+    want = oracle.run(p, u0, 5)
+    assert state_rel_err(fused, pair) <= 1e-13
+    assert state_rel_err(fused, want) <= 1e-10 and state_rel_err(pair, want) <= 1e-10
