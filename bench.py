@@ -291,7 +291,8 @@ def main():
         flops = pade_flops(m, prof["matrices"], prof["squarings"])
         build_s = prof["build_ms"] / 1e3
         achieved = flops / build_s / 1e12
-        kname = f"build_pade_kernel<{p0['n']},{m - p0['n']}>"
+        fused = lmep.lmep_get_option(lmep.LMEP_OPT_FUSE_FROZEN) == 1
+        kname = f"build_pade_kernel<{p0['n']},{m - p0['n']},{'true' if fused else 'false'}>"
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname]),
                 "kernel": kname,

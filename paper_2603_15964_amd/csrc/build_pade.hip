@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
     static_assert(!FUSE || PP == 1, "the fused update is ETD1");
     static_assert(M <= kMaxM, "local matrix exceeds one DPP row");
     const int lane = threadIdx.x & 15;
-    const int64_t item = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int64_t item = xcd_block(blockIdx.x, gridDim.x) * 16 + (threadIdx.x >> 4);
     if (item >= items) return;  // the whole 16-lane row leaves together
 
     const DevProb& P = probs[find_instance(probs, nprob, item)];
@@ -190,16 +190,27 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
         const int64_t N = P.N;
         const int bc = P.bc;
         const double* __restrict__ us = u + P.state_off;
+        constexpr int R = (NN - 1) / 2;
         double term = 0.0;
         if (lane < NN) {
             const double ih = 1.0 / P.h;
-            const int64_t j = map_index(node - r + lane, N, bc);  // stencil position (mirror node for Neumann)
-            const double uj = us[j];
-            const int64_t oj = window_offset(j, N, NN, bc);
-            const int rj = (int)(-oj);
-            double d = 0.0;
+            double uj, d = 0.0;
+            if (node >= 2 * R && node + 2 * R <= N - 1) {
+                // interior: the node's window and each window node's own window
+                // are centred and in the grid
+                const double* __restrict__ wj = us + (node - 2 * R + lane);
+                uj = wj[R];
 #pragma unroll
-            for (int l = 0; l < NN; ++l) d += (fd[fd_index(NN, 0, rj, l)] * ih) * us[map_index(j + oj + l, N, bc)];
+                for (int l = 0; l < NN; ++l) d += (fd[fd_index(NN, 0, R, l)] * ih) * wj[l];
+            } else {
+                const int64_t j = map_index(node - r + lane, N, bc);  // stencil position (mirror node for Neumann)
+                const int64_t oj = window_offset(j, N, NN, bc);
+                const int rj = (int)(-oj);
+                uj = us[j];
+#pragma unroll
+                for (int l = 0; l < NN; ++l)
+                    d += (fd[fd_index(NN, 0, rj, l)] * ih) * us[map_index(j + oj + l, N, bc)];
+            }
             const double Nj = -P.nl_coef * (uj - us[node]) * d;
             term = w0 * uj;
             term += w1 * Nj;

@@ -60,6 +60,17 @@ __device__ __forceinline__ int find_instance(const DevProb* __restrict__ probs, 
     return lo;
 }
 
+// Blocks of a launch are handed to the 8 XCDs round-robin (block b runs on
+// XCD b % 8), and each XCD has its own L2.  Renumbering so that XCD x works
+// through a contiguous range of logical blocks keeps neighbouring nodes, and
+// the stencil windows they share, in one L2.  A bijection of [0, gridDim.x).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t blocks) {
+    const int64_t x = b % kXcds, idx = b / kXcds;
+    const int64_t cnt = blocks / kXcds, rem = blocks % kXcds;
+    return x * cnt + (x < rem ? x : rem) + idx;
+}
+
 // --------------------------------------------------------- compile-time for
 template <class F, int... Is>
 __device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, Is...>) {
