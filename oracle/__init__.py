@@ -6,7 +6,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 plain dicts (see ``workloads``) with the keys
 
     N, n, bc, h, dt, c, nu, delta, react, scheme, nonlin, nl_coef,
-    bc_left, bc_right
+    bc_left, bc_right, window (optional: "centred" or "upwind")
 
 using the string names ``bc in {"periodic", "dirichlet", "neumann"}``,
 ``scheme in {"linear", "etd1", "etd2rk", "etdrk4"}`` and
@@ -28,6 +28,7 @@ _SO = os.path.join(_HERE, "_lmep_oracle.so")
 BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 SCHEME = {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}
 NONLIN = {"none": 0, "burgers_frozen": 1, "kdv": 2, "allen_cahn": 3}
+WINDOW = {"centred": 0, "upwind": 1}
 P_OF_SCHEME = {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}
 # weight rows stored per node (ETDRK4: E(dt/2), (dt/2)phi1(dt/2), E(dt), dt*alpha, dt*beta, dt*gamma)
 KINDS_OF_SCHEME = {"linear": 1, "etd1": 2, "etd2rk": 3, "etdrk4": 6}
@@ -41,6 +42,7 @@ class _Prob(ctypes.Structure):
         ("react", ctypes.c_double),
         ("scheme", ctypes.c_int32), ("nonlin", ctypes.c_int32),
         ("nl_coef", ctypes.c_double), ("bc_left", ctypes.c_double), ("bc_right", ctypes.c_double),
+        ("window", ctypes.c_int32),
     ]
 
 
@@ -57,7 +59,7 @@ def _load():
         lib = ctypes.CDLL(_SO)
         P = ctypes.POINTER(_Prob)
         lib.ora_fd_matrices.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, _D]
-        lib.ora_window_offset.argtypes = [P, ctypes.c_int64]
+        lib.ora_window_offset.argtypes = [P, ctypes.c_int64, ctypes.c_double]
         lib.ora_window_offset.restype = ctypes.c_int64
         lib.ora_augmented_row.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_int, _D]
@@ -85,7 +87,8 @@ def _prob(p: dict) -> _Prob:
     return _Prob(int(p["N"]), int(p["n"]), BC[p["bc"]], float(p["h"]), float(p["dt"]),
                  float(p.get("c", 0.0)), float(p.get("nu", 0.0)), float(p.get("delta", 0.0)),
                  float(p.get("react", 0.0)), SCHEME[p["scheme"]], NONLIN[p.get("nonlin", "none")],
-                 float(p.get("nl_coef", 0.0)), float(p.get("bc_left", 0.0)), float(p.get("bc_right", 0.0)))
+                 float(p.get("nl_coef", 0.0)), float(p.get("bc_left", 0.0)), float(p.get("bc_right", 0.0)),
+                 WINDOW[p.get("window", "centred")])
 
 
 def fd_matrices(n: int, h: float = 1.0):
@@ -96,10 +99,13 @@ def fd_matrices(n: int, h: float = 1.0):
     return D
 
 
-def window_offset(p: dict, i: int) -> int:
-    """Offset o of node i's stencil (step a1; edge rows next to Dirichlet ends, Sec. 2.1 step 3)."""
+def window_offset(p: dict, i: int, a: float = None) -> int:
+    """Offset o of node i's stencil for a node with advection speed a (default:
+    the problem's c): centred, or fully one-sided against the flow for
+    window="upwind" (Sec. 4.1); edge rows next to Dirichlet ends (Sec. 2.1 step 3)."""
     pr = _prob(p)
-    return int(_load().ora_window_offset(ctypes.byref(pr), int(i)))
+    speed = float(p.get("c", 0.0)) if a is None else float(a)
+    return int(_load().ora_window_offset(ctypes.byref(pr), int(i), speed))
 
 
 def augmented_row(L, dt: float, r: int, p: int, nilpotent: bool = True):

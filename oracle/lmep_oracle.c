@@ -6,8 +6,9 @@
  * its caller.
  *
  * What it computes, following the paper's order:
- *   a1  stencil window of each node (centred; one-sided "edge rows" next to
- *       Dirichlet ends, Sec. 2.1 step 3; reflected for Neumann ends),
+ *   a1  stencil window of each node (centred, or fully one-sided against the
+ *       flow, Sec. 4.1; one-sided "edge rows" next to Dirichlet ends,
+ *       Sec. 2.1 step 3; reflected for Neumann ends),
  *   a2  differentiation matrices on the stencil (Sec. 2.1 step 1),
  *   a3  local operator L = -c D1 + nu D2 - delta D3 + react I (Thm 2, Remark),
  *   a4  the paper's s n x s n augmented block matrix (Sec. 3.1 step 1),
@@ -30,6 +31,7 @@
 enum { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_NEUMANN = 2 };
 enum { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2, SCH_ETDRK4 = 3 };
 enum { NL_NONE = 0, NL_BURGERS_FROZEN = 1, NL_KDV = 2, NL_ALLEN_CAHN = 3 };
+enum { WIN_CENTRED = 0, WIN_UPWIND = 1 };
 
 /* The oracle's own problem record (the GPU library has its own, unrelated one). */
 typedef struct {
@@ -43,6 +45,7 @@ typedef struct {
     int32_t nonlin;  /* NL_* */
     double nl_coef;  /* coefficient g of the nonlinear term */
     double bc_left, bc_right; /* Dirichlet end values */
+    int32_t window;  /* WIN_*: centred stencils, or fully one-sided against the flow */
 } ora_prob;
 
 /* Highest phi-function a scheme needs (blocks of the augmented matrix minus one). */
@@ -56,18 +59,32 @@ static int scheme_p(int scheme)
 static int scheme_kinds(int scheme) { return scheme == SCH_ETDRK4 ? 6 : scheme_p(scheme) + 1; }
 
 /* Step a1 -- stencil of node i: grid indices i+o .. i+o+n-1 (before wrapping).
- * Periodic and Neumann: centred, o = -(n-1)/2.  Dirichlet: the n nearest
- * in-domain nodes, so nodes next to an end use a one-sided stencil and harvest
- * an edge row (Sec. 2.1 step 3; Example 1's Beam-Warming row).  The harvest
- * row is r = -o. */
-static int64_t window_offset(int64_t i, int64_t N, int n, int bc)
+ * Centred windows: o = -(n-1)/2.  Upwind windows (the fully one-sided stencils
+ * of Sec. 4.1, which the paper runs up to CFL (n+1)/2): the window ends at i
+ * when the node's advection speed a is positive (o = -(n-1)), starts at i when
+ * it is negative (o = 0), and is centred when a = 0.  Dirichlet: the window is
+ * then moved to the n nearest in-domain nodes where it would leave the grid,
+ * so nodes next to an end use an edge row (Sec. 2.1 step 3; Example 1's
+ * Beam-Warming row).  Periodic windows wrap; Neumann windows reflect.  The
+ * harvest row is r = -o. */
+static int64_t window_offset_a(int64_t i, int64_t N, int n, int bc, int window, double a)
 {
     int64_t o = -(int64_t)(n - 1) / 2;
+    if (window == WIN_UPWIND) {
+        if (a > 0) o = -(int64_t)(n - 1);
+        else if (a < 0) o = 0;
+    }
     if (bc == BC_DIRICHLET) {
         if (o < -i) o = -i;
         if (o > N - n - i) o = N - n - i;
     }
     return o;
+}
+
+/* Window of node i of problem P for a node whose advection speed is a. */
+static int64_t window_offset_p(const ora_prob *P, int64_t i, double a)
+{
+    return window_offset_a(i, P->N, P->n, P->bc, P->window, a);
 }
 
 /* Grid index of stencil position j: wrapped (periodic), reflected about the end
@@ -101,48 +118,18 @@ static int is_fixed_node(const ora_prob *P, int64_t i)
  * < n), the m-th derivative matrix is the m-th power of D1 (proof of Thm 1).
  * The nodes are the centred integers (a - (n-1)/2), the result is scaled by
  * h^-m; a uniform stencil's matrix does not depend on where it sits.
- * Arithmetic in long double; the weights are built from these long double
- * matrices and rounded to double once, at the end. */
-static int fd_matrices_ld(int n, double h, long double *D1, long double *D2, long double *D3)
-{
-    if (n < 1 || n > 63 || !(h > 0)) return -1;
-    long double x[64], pi[64];
-    long double A1[64 * 64], A2[64 * 64], A3[64 * 64];
-    for (int a = 0; a < n; ++a) x[a] = (long double)a - (long double)(n - 1) / 2.0L;
-    for (int b = 0; b < n; ++b) {
-        pi[b] = 1.0L;
-        for (int l = 0; l < n; ++l)
-            if (l != b) pi[b] *= (x[b] - x[l]);
-    }
-    for (int a = 0; a < n; ++a) {
-        long double diag = 0.0L;
-        for (int b = 0; b < n; ++b) {
-            if (b == a) continue;
-            A1[a * n + b] = (pi[a] / pi[b]) / (x[a] - x[b]);
-            diag += 1.0L / (x[a] - x[b]);
-        }
-        A1[a * n + a] = diag;
-    }
-    for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) {
-            long double s = 0.0L;
-            for (int k = 0; k < n; ++k) s += A1[a * n + k] * A1[k * n + b];
-            A2[a * n + b] = s;
-        }
-    for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) {
-            long double s = 0.0L;
-            for (int k = 0; k < n; ++k) s += A2[a * n + k] * A1[k * n + b];
-            A3[a * n + b] = s;
-        }
-    const long double hl = h;
-    for (int a = 0; a < n * n; ++a) {
-        D1[a] = A1[a] / hl;
-        D2[a] = A2[a] / (hl * hl);
-        D3[a] = A3[a] / (hl * hl * hl);
-    }
-    return 0;
-}
+ * Arithmetic in long double (binary128 for one-sided windows); the weights are
+ * built from these wide matrices and rounded to double once, at the end. */
+#define FDT long double
+#define FDFN fd_matrices_ld
+#include "lmep_oracle_fd.inc"
+#undef FDT
+#undef FDFN
+#define FDT __float128
+#define FDFN fd_matrices_q
+#include "lmep_oracle_fd.inc"
+#undef FDT
+#undef FDFN
 
 /* The same matrices rounded to double (exported; also used for the
  * derivative terms of the nonlinearity, which are plain FP64 dot products). */
@@ -158,11 +145,18 @@ int ora_fd_matrices(int n, double h, double *D1, double *D2, double *D3)
     return 0;
 }
 
-/* ---- the type-generic part, instantiated for real and complex ---- */
+/* ---- the type-generic part: real, complex, and real carried in binary128 ---- */
+static __float128 absq_(__float128 x) { return x < 0 ? -x : x; }
+
 #define T double
 #define TW long double
+#define RW long double
+#define DW long double
+#define EPSW 0x1p-80L
+#define FD_WIDE fd_matrices_ld
 #define ABSW(x) fabsl(x)
 #define FN(name) name##_d
+#define RE(x) (x)
 #include "lmep_oracle_core.inc"
 #undef T
 #undef TW
@@ -172,11 +166,37 @@ int ora_fd_matrices(int n, double h, double *D1, double *D2, double *D3)
 #define TW long double complex
 #define ABSW(x) cabsl(x)
 #define FN(name) name##_z
+#undef RE
+#define RE(x) creal(x)
 #include "lmep_oracle_core.inc"
 #undef T
 #undef TW
+#undef RW
+#undef DW
+#undef EPSW
+#undef FD_WIDE
 #undef ABSW
 #undef FN
+#undef RE
+#define T double
+#define TW __float128
+#define RW __float128
+#define DW __float128
+#define EPSW ((__float128)0x1p-120)
+#define FD_WIDE fd_matrices_q
+#define ABSW(x) absq_(x)
+#define FN(name) name##_q
+#define RE(x) (x)
+#include "lmep_oracle_core.inc"
+#undef T
+#undef TW
+#undef RW
+#undef DW
+#undef EPSW
+#undef FD_WIDE
+#undef ABSW
+#undef FN
+#undef RE
 
 static int check_prob(const ora_prob *P)
 {
@@ -184,13 +204,14 @@ static int check_prob(const ora_prob *P)
     if (P->bc < 0 || P->bc > 2 || P->scheme < 0 || P->scheme > 3 || P->nonlin < 0 || P->nonlin > 3) return -1;
     if (P->bc == BC_NEUMANN && (P->n - 1) / 2 > P->N - 1) return -1;
     if (P->nonlin == NL_BURGERS_FROZEN && P->scheme != SCH_ETD1) return -1;
+    if (P->window != WIN_CENTRED && P->window != WIN_UPWIND) return -1;
     return 0;
 }
 
 /* ---------------------------- exported API ---------------------------- */
 
 /* Stencil offset o of node i (integer step a1). */
-int64_t ora_window_offset(const ora_prob *P, int64_t i) { return window_offset(i, P->N, P->n, P->bc); }
+int64_t ora_window_offset(const ora_prob *P, int64_t i, double a) { return window_offset_p(P, i, a); }
 
 /* Row r of the augmented exponential for a given local operator L (n x n,
  * row major): out = [W0 | W1 | W2 | W3] as in augmented_row (p + 1 parts). */
@@ -220,9 +241,15 @@ int ora_build_weights(const ora_prob *P, const double *u, double *w)
 {
     if (check_prob(P)) return -1;
     const int n = P->n;
+    if (P->nonlin == NL_BURGERS_FROZEN && !u) return -1;
+    if (P->window == WIN_UPWIND) {
+        __float128 Q1[64 * 64], Q2[64 * 64], Q3[64 * 64];
+        if (fd_matrices_q(n, P->h, Q1, Q2, Q3)) return -1;
+        all_weights_q(P, Q1, Q2, Q3, P->c, P->nu, P->delta, u, w);
+        return 0;
+    }
     long double D1[64 * 64], D2[64 * 64], D3[64 * 64];
     if (fd_matrices_ld(n, P->h, D1, D2, D3)) return -1;
-    if (P->nonlin == NL_BURGERS_FROZEN && !u) return -1;
     all_weights_d(P, D1, D2, D3, P->c, P->nu, P->delta, u, w);
     return 0;
 }
@@ -231,6 +258,7 @@ int ora_build_weights(const ora_prob *P, const double *u, double *w)
 int ora_run(const ora_prob *P, const double *u0, int64_t steps, double *uT)
 {
     if (check_prob(P) || steps < 0) return -1;
+    if (P->window == WIN_UPWIND) return run_q(P, P->c, P->nu, P->delta, u0, steps, uT);
     return run_d(P, P->c, P->nu, P->delta, u0, steps, uT);
 }
 
@@ -241,7 +269,7 @@ int ora_run_z(const ora_prob *P, double c_im, double nu_im, double delta_im,
               const double *u0_re, const double *u0_im, int64_t steps,
               double *uT_re, double *uT_im)
 {
-    if (check_prob(P) || steps < 0 || P->react != 0.0) return -1;
+    if (check_prob(P) || steps < 0 || P->react != 0.0 || P->window != WIN_CENTRED) return -1;
     const int64_t N = P->N;
     double complex *u0 = (double complex *)calloc(N, sizeof(double complex));
     double complex *uT = (double complex *)malloc(sizeof(double complex) * N);
@@ -265,7 +293,9 @@ int ora_run_z(const ora_prob *P, double c_im, double nu_im, double delta_im,
  * Dirichlet end nodes are not updated, so their entries of lam are unused. */
 int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, double *lam_out, double *grad)
 {
-    if (check_prob(P) || P->scheme >= SCH_ETD2RK || P->nonlin == NL_KDV || P->react != 0.0) return -1;
+    if (check_prob(P) || P->scheme >= SCH_ETD2RK || P->nonlin == NL_KDV || P->react != 0.0 ||
+        P->window != WIN_CENTRED)
+        return -1;
     const int n = P->n, p = scheme_p(P->scheme), W = (p + 1) * n;
     const int64_t N = P->N;
     const double gam = P->nl_coef;
@@ -279,7 +309,7 @@ int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, doub
     double *gbar = (double *)calloc(N, sizeof(double));
     all_weights_d(P, D1, D2, D3, P->c, P->nu, P->delta, u, w);
     if (frozen)
-        for (int64_t j = 0; j < N; ++j) g[j] = own_derivative_d(P, D1d, u, j);
+        for (int64_t j = 0; j < N; ++j) g[j] = own_derivative_d(P, D1d, u, j, 0.0); /* centred windows only */
 
     /* derivative of each node's harvested row along the three directions */
     const long double *dirs[3] = {D2, D1, D3};
@@ -289,7 +319,7 @@ int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, doub
 #pragma omp parallel for schedule(dynamic, 16) if (frozen)
     for (int64_t i = 0; i < N; ++i) {
         if (!frozen) continue;
-        const int r = (int)(-window_offset(i, N, n, P->bc));
+        const int r = (int)(-window_offset_a(i, N, n, P->bc, WIN_CENTRED, 0.0));
         long double L[64 * 64], dL[64 * 64];
         local_operator_d(n, D1, D2, D3, P->c + gam * u[i], P->nu, P->delta, 0.0, L);
         for (int d = 0; d < 3; ++d) {
@@ -299,7 +329,7 @@ int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, doub
     }
     if (!frozen) { /* stationary: one derivative per distinct harvest row */
         for (int64_t i = 0; i < N; ++i) {
-            const int r = (int)(-window_offset(i, N, n, P->bc));
+            const int r = (int)(-window_offset_a(i, N, n, P->bc, WIN_CENTRED, 0.0));
             if (!have_r[r]) {
                 long double L[64 * 64], dL[64 * 64];
                 local_operator_d(n, D1, D2, D3, P->c, P->nu, P->delta, 0.0, L);
@@ -318,7 +348,7 @@ int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, doub
     for (int64_t i = 0; i < N; ++i) {
         if (is_fixed_node(P, i)) continue;
         const double li = lam[i];
-        const int64_t o = window_offset(i, N, n, P->bc);
+        const int64_t o = window_offset_a(i, N, n, P->bc, WIN_CENTRED, 0.0);
         const double *wi = w + i * W;
         double dl[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < n; ++k) {
@@ -347,7 +377,7 @@ int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, doub
     }
     if (frozen) { /* g = own-stencil derivative of u: scatter gbar through D1 rows */
         for (int64_t m = 0; m < N; ++m) {
-            const int64_t o = window_offset(m, N, n, P->bc);
+            const int64_t o = window_offset_a(m, N, n, P->bc, WIN_CENTRED, 0.0);
             const int r = (int)(-o);
             for (int l = 0; l < n; ++l) lam_out[grid_index(m + o + l, N, P->bc)] += gbar[m] * D1d[r * n + l];
         }
