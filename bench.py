@@ -61,24 +61,26 @@ SCHEME_ID = {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}
 NONLIN_ID = {"none": 0, "burgers_frozen": 1, "kdv": 2, "allen_cahn": 3}
 
 
-def measured_traffic(kernels):
-    """HBM bytes per launch of the named kernels (summed), from the byte-counter
-    summaries under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a copy
-    probe).  None unless every kernel has a line whose recorded sha256 of the
-    kernel's sources still matches the sources in this tree."""
+def measured_traffic(kernels, workload):
+    """HBM bytes per launch of the named kernels (summed) on this workload, from
+    the byte-counter summaries under profiles/ (FETCH_SIZE and WRITE_SIZE
+    scaled by a copy probe).  Lines read
+      traffic-bytes-per-launch <kernel> <bytes> workload <name> sources-sha256 <hash> <files...>
+    None unless every kernel has a line for this workload whose recorded sha256
+    of the kernel's sources still matches the sources in this tree."""
     import glob
     import hashlib
     table = {}
     for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
         for line in open(f):
             t = line.split()
-            if len(t) >= 6 and t[0] == "traffic-bytes-per-launch" and t[3] == "sources-sha256":
-                table[t[1]] = (float(t[2]), t[4], t[5:])
+            if len(t) >= 8 and t[0] == "traffic-bytes-per-launch" and t[3] == "workload" and t[5] == "sources-sha256":
+                table[(t[1], t[4])] = (float(t[2]), t[6], t[7:])
     total = 0.0
     for k in kernels:
-        if k not in table:
+        if (k, workload) not in table:
             return None
-        val, digest, files = table[k]
+        val, digest, files = table[(k, workload)]
         h = hashlib.sha256()
         for rel in files:
             path = os.path.join(ROOT, rel)
@@ -106,6 +108,10 @@ def make_workload(name: str):
         p, u0 = workloads.burgers_etdrk4()
         return [p], [u0], ("the paper's Burgers run: periodic N=1048576 n=13, nu=0.03, stationary L = nu D2, "
                            "N = -u u_x, ETDRK4")
+    if name == "burgers_upwind":
+        p, u0 = workloads.burgers_upwind()
+        return [p], [u0], ("viscous Burgers N=65536 n=7 periodic on fully one-sided (upwind) stencils at "
+                           "CFL 3.5, frozen-velocity ETD1, weights rebuilt every step")
     if name == "advection_diffusion":
         p, u0 = workloads.advection_diffusion()
         return [p], [u0], "periodic advection-diffusion N=256 n=5 CFL 2, LINEAR"
@@ -177,7 +183,7 @@ def adjoint_roofline(problems, states, reps: int = 5):
     tf = flops / (fre_ms / 1e3) / 1e12
     kname = f"adj_frechet_kernel<{p0['n']},{m - p0['n']}>"
     return {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": tf / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname]), "kernel": kname,
+            "frac": tf / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname], "burgers_adjoint"), "kernel": kname,
             "avg_launch_us": fre_ms * 1e3 / max(1, launches), "flops_per_launch": flops / max(1, launches),
             "mean_squarings": mean_s, "rest_of_reverse_step_us": rest_ms * 1e3 / reps}
 
@@ -284,7 +290,7 @@ def main():
     prof = lmep.lmep_profile_last()
     roof = None
     extra = {"gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3}
-    apply_bytes = {"burgers": 128.0, "kdv": 16.0, "allen_cahn_batch": 16.0, "advection_diffusion": 16.0}
+    apply_bytes = {"burgers": 128.0, "burgers_upwind": 128.0, "kdv": 16.0, "allen_cahn_batch": 16.0, "advection_diffusion": 16.0}
     if frozen and prof["build_launches"] > 0 and prof["matrices"] > 0:
         p0 = problems[0]
         m = p0["n"] + {"linear": 0, "etd1": 1, "etd2rk": 2}[p0["scheme"]]
@@ -294,7 +300,7 @@ def main():
         fused = lmep.lmep_get_option(lmep.LMEP_OPT_FUSE_FROZEN) == 1
         kname = f"build_pade_kernel<{p0['n']},{m - p0['n']},{'true' if fused else 'false'}>"
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname]),
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname], args.workload),
                 "kernel": kname,
                 "avg_launch_us": prof["build_ms"] * 1e3 / prof["build_launches"],
                 "flops_per_launch": flops / prof["build_launches"],
@@ -327,7 +333,7 @@ def main():
             else:
                 names = ["apply_kernel"]
             roof = dict(extra["apply_alu"] if kb > 1 else extra["apply"],
-                        traffic=measured_traffic(names) if kb > 1 else None,
+                        traffic=measured_traffic(names, args.workload) if kb > 1 else None,
                         kernel=" + ".join(names), avg_launch_us=avg_us)
     out = {
         "metric": "node-steps/s (weight build+apply, FP64)",

@@ -54,9 +54,6 @@ typedef enum {
 
 enum { LMEP_BC_PERIODIC = 0, LMEP_BC_DIRICHLET = 1, LMEP_BC_NEUMANN = 2 };
 
-/* Time schemes (Sec. 3): LINEAR u+ = W0.u (p = 0 phi-blocks); ETD1 adds
- * W1.N (ETD-s with s = 1, p = 1); ETD2RK is the Cox-Matthews two-stage
- * scheme a = W0.u + W1.N(u), u+ = a + W2.(N(a) - N(u)) (p = 2). */
 /* Schemes (Sec. 3): LINEAR u+ = W0 u; ETD1 (ETD-s with s = 1); ETD2RK
  * (Cox-Matthews); ETDRK4 (the four-stage scheme of Sec. 3 with
  * alpha, beta, gamma built from phi1..phi3, stationary weights only,
@@ -71,6 +68,22 @@ enum { LMEP_LINEAR = 0, LMEP_ETD1 = 1, LMEP_ETD2RK = 2, LMEP_ETDRK4 = 3 };
  *  KDV             N = -(g/2) d/dx (u^2)  (conservative form of -g u u_x);
  *  ALLEN_CAHN      N = g (u - u^3). */
 enum { LMEP_NL_NONE = 0, LMEP_NL_BURGERS_FROZEN = 1, LMEP_NL_KDV = 2, LMEP_NL_ALLEN_CAHN = 3 };
+
+/* Stencil windows (step a1).  CENTRED: o = -(n-1)/2.  UPWIND: the fully
+ * one-sided stencils of Sec. 4.1, on the side the flow comes from: the window
+ * of node i ends at i (o = -(n-1)) when its advection speed a_i is positive,
+ * starts at i (o = 0) when a_i is negative, and is centred when a_i = 0, with
+ * a_i = c, or c + g u_i for BURGERS_FROZEN (each node its own side; the
+ * derivative in the remainder N_j uses node j's own side).  Either way a
+ * Dirichlet grid moves the window to the n nearest in-domain nodes.  A
+ * one-sided pure-advection update is stable for Courant numbers |a| dt / h in
+ * [(n-3)/2, (n+1)/2] (and at the integers, where it is an exact shift); in
+ * FP64 its edge-row exponentials lose accuracy as n and the Courant number
+ * grow (weights agree with the exact ones to ~1e-12 up to n = 9 at Courant
+ * 2.5, n = 7 throughout its stable band).  UPWIND is supported for LINEAR,
+ * ETD1 and ETD2RK with the one-step kernels; ETDRK4, LMEP_F_PERSISTENT and
+ * the reverse step return LMEP_ERR_UNSUPPORTED. */
+enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
 
 /* lmep_step flags */
 #define LMEP_F_GRAPH        0x1u  /* capture the step loop in a hipGraph and replay it          */
@@ -108,6 +121,7 @@ typedef struct {
     double  bc_right;   /* Dirichlet value held at node N-1                           */
     int64_t state_off;  /* offset (in doubles) of the state in packed state buffers   */
     int64_t weight_off; /* offset (in doubles) of the weights in the weight buffer    */
+    int32_t window;     /* LMEP_WIN_* (0 = centred)                                   */
 } lmep_problem;
 
 /* Number of doubles of harvested weights one instance needs (kinds = 1 + p =

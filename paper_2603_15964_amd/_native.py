@@ -23,6 +23,7 @@ LMEP_ERR_SCRATCH = -5
 LMEP_BC_PERIODIC, LMEP_BC_DIRICHLET, LMEP_BC_NEUMANN = 0, 1, 2
 LMEP_LINEAR, LMEP_ETD1, LMEP_ETD2RK, LMEP_ETDRK4 = 0, 1, 2, 3
 LMEP_NL_NONE, LMEP_NL_BURGERS_FROZEN, LMEP_NL_KDV, LMEP_NL_ALLEN_CAHN = 0, 1, 2, 3
+LMEP_WIN_CENTRED, LMEP_WIN_UPWIND = 0, 1
 LMEP_F_GRAPH, LMEP_F_PERSISTENT, LMEP_F_CHECK_FINITE, LMEP_F_PROFILE, LMEP_F_COUNT = 0x1, 0x2, 0x4, 0x8, 0x10
 
 OP_BUILD, OP_STEP, OP_ADJOINT = 0, 1, 2
@@ -31,6 +32,7 @@ BC_NAMES = {"periodic": LMEP_BC_PERIODIC, "dirichlet": LMEP_BC_DIRICHLET, "neuma
 SCHEME_NAMES = {"linear": LMEP_LINEAR, "etd1": LMEP_ETD1, "etd2rk": LMEP_ETD2RK, "etdrk4": LMEP_ETDRK4}
 NONLIN_NAMES = {"none": LMEP_NL_NONE, "burgers_frozen": LMEP_NL_BURGERS_FROZEN, "kdv": LMEP_NL_KDV,
                 "allen_cahn": LMEP_NL_ALLEN_CAHN}
+WINDOW_NAMES = {"centred": LMEP_WIN_CENTRED, "upwind": LMEP_WIN_UPWIND}
 
 
 class lmep_problem(ctypes.Structure):
@@ -42,6 +44,7 @@ class lmep_problem(ctypes.Structure):
         ("scheme", ctypes.c_int32), ("nonlin", ctypes.c_int32),
         ("nl_coef", ctypes.c_double), ("bc_left", ctypes.c_double), ("bc_right", ctypes.c_double),
         ("state_off", ctypes.c_int64), ("weight_off", ctypes.c_int64),
+        ("window", ctypes.c_int32),
     ]
 
 
@@ -109,7 +112,8 @@ def to_struct(p: dict, state_off: int = None, weight_off: int = None) -> lmep_pr
         SCHEME_NAMES[p["scheme"]], NONLIN_NAMES[p.get("nonlin", "none")], float(p.get("nl_coef", 0.0)),
         float(p.get("bc_left", 0.0)), float(p.get("bc_right", 0.0)),
         int(p.get("state_off", 0) if state_off is None else state_off),
-        int(p.get("weight_off", 0) if weight_off is None else weight_off))
+        int(p.get("weight_off", 0) if weight_off is None else weight_off),
+        WINDOW_NAMES[p.get("window", "centred")])
 
 
 def lmep_weight_count(prob: lmep_problem) -> int:

@@ -47,18 +47,21 @@ __device__ __forceinline__ int64_t source_position(int64_t j, int64_t N, int bc)
 }
 
 // N at unwrapped position j, from the LDS array v that starts at unwrapped
-// position base.  KdV and the frozen-velocity du/dx use j's own stencil.
+// position base.  KdV and the frozen-velocity du/dx use j's own stencil, whose
+// side for upwind windows follows j's advection speed (c, or c + g u_j).
 template <int NN, int NL>
 __device__ __forceinline__ double nonlinear_at(const double* __restrict__ v, int len, int64_t base, int64_t j,
-                                               int64_t N, int bc, const double* __restrict__ sD1, double g) {
-    constexpr int R = (NN - 1) / 2;
+                                               int64_t N, int bc, int window, double c,
+                                               const double* __restrict__ sD1, double g) {
     if constexpr (NL == NL_AC) {
         const double x = v[clampi((int)(j - base), 0, len - 1)];
         return g * (x - x * x * x);
     } else {
         int64_t jj = source_position(j, N, bc);
         if (bc == BC_DIRICHLET) jj = jj < 0 ? 0 : (jj > N - 1 ? N - 1 : jj);
-        const int64_t o = (bc == BC_DIRICHLET) ? window_offset(jj, N, NN, bc) : -(int64_t)R;
+        double a = c;
+        if constexpr (NL == NL_BURGERS) a += g * v[clampi((int)(jj - base), 0, len - 1)];
+        const int64_t o = window_offset(jj, N, NN, bc, window, a);
         const int rr = (int)(-o);
         const int b = clampi((int)(jj + o - base), 0, len - NN);
         double acc = 0.0;
@@ -131,7 +134,8 @@ __global__ __launch_bounds__(NT) void apply_kernel(const DevProb* __restrict__ p
 
     const int64_t nubase = t0 - NU_REACH;
     if constexpr (HAS_N) {
-        for (int q = tid; q < LNU; q += NT) sNu[q] = nonlinear_at<NN, NL>(su, LU, ubase, nubase + q, N, bc, sD1, g);
+        for (int q = tid; q < LNU; q += NT)
+            sNu[q] = nonlinear_at<NN, NL>(su, LU, ubase, nubase + q, N, bc, P.window, P.c, sD1, g);
         __syncthreads();
     }
 
@@ -150,11 +154,11 @@ __global__ __launch_bounds__(NT) void apply_kernel(const DevProb* __restrict__ p
             ii = map_index(i, N, bc);
         }
         const int64_t c = source_position(i, N, bc);  // where the stencil of node ii is read
-        const int64_t o = window_offset(ii, N, NN, bc);
+        const double ui = su[clampi((int)(c - ubase), 0, LU - 1)];
+        const int64_t o = window_offset(ii, N, NN, bc, P.window, NL == NL_BURGERS ? P.c + g * ui : P.c);
         const int r = (int)(-o);
         const int bu = clampi((int)(c + o - ubase), 0, LU - NN);
         const int bn = clampi((int)(c + o - nubase), 0, (HAS_N ? LNU : NN) - NN);
-        const double ui = su[clampi((int)(c - ubase), 0, LU - 1)];
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < NN; ++k) {
@@ -178,7 +182,8 @@ __global__ __launch_bounds__(NT) void apply_kernel(const DevProb* __restrict__ p
         for (int q = tid; q < LA; q += NT) sa[q] = stage_a(abase + q);
         __syncthreads();
         if constexpr (HAS_N) {
-            for (int q = tid; q < LA; q += NT) sNa[q] = nonlinear_at<NN, NL>(sa, LA, abase, abase + q, N, bc, sD1, g);
+            for (int q = tid; q < LA; q += NT)
+                sNa[q] = nonlinear_at<NN, NL>(sa, LA, abase, abase + q, N, bc, P.window, P.c, sD1, g);
             __syncthreads();
         }
         for (int q = tid; q < TILE; q += NT) {
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(NT) void apply_kernel(const DevProb* __restrict__ p
                 continue;
             }
             if constexpr (HAS_N) {
-                const int64_t o = window_offset(i, N, NN, bc);
+                const int64_t o = window_offset(i, N, NN, bc, P.window, P.c);
                 const int r = (int)(-o);
                 const int ba = clampi((int)(i + o - abase), 0, LA - NN);
                 const int bn = clampi((int)(i + o - nubase), 0, LNU - NN);

@@ -119,10 +119,10 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
     const int64_t local = item - P.item_begin;
     const bool frozen = P.frozen != 0;
     const int64_t node = frozen ? local : 0;
-    const int r = frozen ? (int)(-window_offset(node, P.N, NN, P.bc)) : (int)local;
     const double dt = P.dt;
     double ceff = P.c;
     if (frozen) ceff += P.nl_coef * u[P.state_off + node];
+    const int r = frozen ? (int)(-window_offset(node, P.N, NN, P.bc, P.window, ceff)) : (int)local;
 
     // Row `lane` of Mt: dt * L[k][lane] for k < n (column `lane` of the local
     // operator L = -c D1 + nu D2 - delta D3 + react I on the stencil).
@@ -195,18 +195,28 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
         if (lane < NN) {
             const double ih = 1.0 / P.h;
             double uj, d = 0.0;
-            if (node >= 2 * R && node + 2 * R <= N - 1) {
+            if (P.window == WIN_CENTRED && node >= 2 * R && node + 2 * R <= N - 1) {
                 // interior: the node's window and each window node's own window
                 // are centred and in the grid
                 const double* __restrict__ wj = us + (node - 2 * R + lane);
                 uj = wj[R];
 #pragma unroll
                 for (int l = 0; l < NN; ++l) d += (fd[fd_index(NN, 0, R, l)] * ih) * wj[l];
+            } else if (P.window == WIN_UPWIND && node >= 4 * R && node + 4 * R <= N - 1) {
+                // interior, one-sided: every window involved lies in the grid
+                // (no wrap, reflection or clamp); each lane picks its own side
+                const int64_t j = node - r + lane;
+                uj = us[j];
+                const double aj = P.c + P.nl_coef * uj;
+                const int oj = aj > 0.0 ? -(NN - 1) : (aj < 0.0 ? 0 : -R);
+                const double* __restrict__ wj = us + (j + oj);
+#pragma unroll
+                for (int l = 0; l < NN; ++l) d += (fd[fd_index(NN, 0, -oj, l)] * ih) * wj[l];
             } else {
                 const int64_t j = map_index(node - r + lane, N, bc);  // stencil position (mirror node for Neumann)
-                const int64_t oj = window_offset(j, N, NN, bc);
-                const int rj = (int)(-oj);
                 uj = us[j];
+                const int64_t oj = window_offset(j, N, NN, bc, P.window, P.c + P.nl_coef * uj);
+                const int rj = (int)(-oj);
 #pragma unroll
                 for (int l = 0; l < NN; ++l)
                     d += (fd[fd_index(NN, 0, rj, l)] * ih) * us[map_index(j + oj + l, N, bc)];

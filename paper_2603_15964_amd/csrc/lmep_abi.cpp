@@ -10,6 +10,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -19,6 +20,9 @@
 #include "lmep_internal.hpp"
 
 using namespace lmep;
+
+// The Python binding mirrors this layout field by field.
+static_assert(offsetof(lmep_problem, window) == 112 && sizeof(lmep_problem) == 120, "lmep_problem layout");
 
 namespace {
 
@@ -78,6 +82,10 @@ int check_problem(const lmep_problem& q, int k) {
         return fail(LMEP_ERR_UNSUPPORTED, "instance %d: n + p = %d exceeds %d", k, q.n + scheme_p(q.scheme), kMaxM);
     if (frozen(q) && q.scheme != LMEP_ETD1)
         return fail(LMEP_ERR_UNSUPPORTED, "instance %d: frozen-velocity Burgers needs ETD1", k);
+    if (q.window != LMEP_WIN_CENTRED && q.window != LMEP_WIN_UPWIND)
+        return fail(LMEP_ERR_ARG, "instance %d: unknown window %d", k, q.window);
+    if (q.window == LMEP_WIN_UPWIND && q.scheme == LMEP_ETDRK4)
+        return fail(LMEP_ERR_UNSUPPORTED, "instance %d: upwind windows cover LINEAR, ETD1 and ETD2RK", k);
     return LMEP_OK;
 }
 
@@ -183,6 +191,7 @@ DevProb to_dev(const lmep_problem& q, int index) {
     d.nl_coef = q.nl_coef;
     d.bc_left = q.bc_left;
     d.bc_right = q.bc_right;
+    d.window = q.window;
     return d;
 }
 
@@ -454,10 +463,13 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
         return fail(LMEP_ERR_ARG, "unknown flag bits 0x%x", flags);
     const bool multi = (flags & LMEP_F_PERSISTENT) != 0;
     if (multi)
-        for (int k = 0; k < count; ++k)
+        for (int k = 0; k < count; ++k) {
             if (frozen(prob[k]))
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs stationary weights (instance %d is "
                             "BURGERS_FROZEN)", k);
+            if (prob[k].window != LMEP_WIN_CENTRED)
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs centred windows (instance %d)", k);
+        }
     if ((flags & LMEP_F_GRAPH) && (flags & (LMEP_F_PROFILE | LMEP_F_COUNT)))
         return fail(LMEP_ERR_ARG, "LMEP_F_PROFILE / LMEP_F_COUNT cannot be combined with LMEP_F_GRAPH");
     const int64_t ext = state_extent(prob, count);
@@ -600,8 +612,10 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
     if (rc) return rc;
     for (int k = 0; k < count; ++k) {
         const lmep_problem& q = prob[k];
-        if (q.scheme == LMEP_ETD2RK || q.scheme == LMEP_ETDRK4 || q.nonlin == LMEP_NL_KDV)
-            return fail(LMEP_ERR_UNSUPPORTED, "instance %d: the reverse step covers LINEAR and ETD1 without KdV", k);
+        if (q.scheme == LMEP_ETD2RK || q.scheme == LMEP_ETDRK4 || q.nonlin == LMEP_NL_KDV ||
+            q.window != LMEP_WIN_CENTRED)
+            return fail(LMEP_ERR_UNSUPPORTED,
+                        "instance %d: the reverse step covers LINEAR and ETD1 without KdV, centred windows", k);
     }
     if (!d_u_k || !d_lambda_next || !d_lambda_k || !d_grad) return fail(LMEP_ERR_ARG, "NULL pointer argument");
     const int64_t ext = state_extent(prob, count);

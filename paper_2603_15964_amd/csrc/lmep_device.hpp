@@ -21,11 +21,15 @@
 namespace lmep {
 
 // ------------------------------------------------------------- step a1 ----
-// Stencil of node i: grid indices i+o .. i+o+n-1.  Centred (o = -(n-1)/2)
-// for periodic and Neumann grids; for Dirichlet grids the n nearest in-domain
-// nodes (edge rows next to the ends).  The harvested row is r = -o.
-__device__ __forceinline__ int64_t window_offset(int64_t i, int64_t N, int n, int bc) {
+// Stencil of node i: grid indices i+o .. i+o+n-1.  Centred (o = -(n-1)/2),
+// or for upwind windows fully one-sided against the node's advection speed a
+// (Sec. 4.1): o = -(n-1) for a > 0, o = 0 for a < 0, centred for a = 0.  On
+// Dirichlet grids the window is then moved to the n nearest in-domain nodes
+// (edge rows next to the ends).  The harvested row is r = -o.
+__device__ __forceinline__ int64_t window_offset(int64_t i, int64_t N, int n, int bc, int window = WIN_CENTRED,
+                                                 double a = 0.0) {
     int64_t o = -(int64_t)((n - 1) / 2);
+    if (window == WIN_UPWIND && a != 0.0) o = a > 0.0 ? -(int64_t)(n - 1) : 0;
     if (bc == BC_DIRICHLET) {
         o = o < -i ? -i : o;
         o = o > N - n - i ? N - n - i : o;

@@ -26,7 +26,8 @@ struct DevProb {
     int32_t n, bc, scheme, nonlin;
     int32_t p, frozen, index, harvest;  // harvest: what the build writes (HARVEST_*)
     double h, dt, c, nu, delta, react, nl_coef, bc_left, bc_right;
-    double pad2[3];
+    int32_t window, pad1;  // WIN_*
+    double pad2[2];
 };
 static_assert(sizeof(DevProb) == 160, "DevProb layout");
 
@@ -37,6 +38,7 @@ enum : int { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2, SCH_ETDRK4 = 3 };
 // dt gamma) and the half step (p = 1 at dt/2: kinds 0, 1).
 enum : int { HARVEST_PLAIN = 0, HARVEST_RK4_FULL = 1, HARVEST_RK4_HALF = 2 };
 enum : int { NL_NONE = 0, NL_BURGERS = 1, NL_KDV = 2, NL_AC = 3 };
+enum : int { WIN_CENTRED = 0, WIN_UPWIND = 1 };
 
 // Table of finite-difference weights on the centred integer stencil
 // x_k = k - (n-1)/2: fd[(n-3)/2][d][a][k] is the weight of node k for the

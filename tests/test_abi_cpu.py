@@ -123,3 +123,30 @@ def test_multistep_flag_and_option():
         assert lmep.lmep_get_option(opt) == 4
     finally:
         lmep.lmep_set_option(opt, 8)
+
+
+def test_window_field_checks():
+    """The window field: unknown values are ARG; upwind windows are refused
+    with ETDRK4, with multi-step launches and by the reverse step before any
+    device work.  The Python mirror has the C layout (window at byte 112)."""
+    assert lmep.lmep_problem.window.offset == 112 and ctypes.sizeof(lmep.lmep_problem) == 120
+    lib = lmep.library()
+    s = _structs()
+    s[0].window = 2
+    assert lib.lmep_build_weights(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), None, 0, None) == lmep.LMEP_ERR_ARG
+    assert "window" in lmep.lmep_last_error()
+    rk4 = dict(N=64, n=9, bc="periodic", h=0.1, dt=0.01, nu=0.1, scheme="etdrk4", nonlin="allen_cahn",
+               nl_coef=1.0, window="upwind")
+    assert lmep.lmep_weight_count(lmep.to_struct(dict(rk4, window="centred"))) == 6 * 9 * 9
+    s = lmep.problem_array([rk4])
+    rc = lib.lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 1, 0,
+                       ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_UNSUPPORTED, lmep.lmep_last_error()
+    s = lmep.problem_array([dict(rk4, scheme="etd1")])
+    rc = lib.lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 4,
+                       lmep.LMEP_F_PERSISTENT, ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_UNSUPPORTED and "centred" in lmep.lmep_last_error()
+    s = _structs(window="upwind")
+    rc = lib.lmep_adjoint_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20),
+                               ctypes.c_void_p(1 << 24), ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_UNSUPPORTED, lmep.lmep_last_error()

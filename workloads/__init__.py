@@ -8,7 +8,7 @@ it.  Every generator uses numpy's PCG64 with a fixed seed.
 Problems are plain dicts with the keys
 
     N, n, bc, h, dt, c, nu, delta, react, scheme, nonlin, nl_coef,
-    bc_left, bc_right
+    bc_left, bc_right, window
 
 describing  u_t = -c u_x + nu u_xx - delta u_xxx + react u + N(u)  on a uniform
 grid of N nodes with spacing h (Sec. 2: grid of N points, stencil size n,
@@ -161,5 +161,28 @@ def burgers_etdrk4(N: int = 2 ** 20, n: int = 13, nu: float = 0.03, mu: float = 
     return p, u0
 
 
+# --------------------------------------------- upwind windows (next row) --
+def burgers_upwind(N: int = 65536, n: int = 7, nu: float = 2.5e-3, cfl: float = 3.5, modes: int = 8,
+                   seed: int = BASE_SEED + 5):
+    """Viscous Burgers at high Courant number on fully one-sided stencils
+    (Sec. 4.1 runs them at CFL (n+1)/2 - sigma): periodic, h = 16 nu (cell
+    Peclet number 16, so the diffusion number cfl/16 stays inside the
+    one-sided rows' stable range), u0 = 1 + 0.1 p(x) / max|p| with p a sum of 8
+    sine modes, amplitudes N(0, 1/k^2), phases U[0, 2pi); dt = cfl h / mean(u0),
+    so every node's Courant number lies in [0.9, 1.1] * cfl, inside the stable
+    band [(n-3)/2, (n+1)/2].  Frozen-velocity ETD1 with window="upwind"."""
+    h = 16.0 * nu
+    length = N * h
+    x = h * np.arange(N)
+    g = rng(seed)
+    a = g.normal(0.0, 1.0, modes) / np.arange(1, modes + 1)
+    ph = g.uniform(0.0, 2.0 * math.pi, modes)
+    pert = sum(a[k - 1] * np.sin(2.0 * math.pi * k * x / length + ph[k - 1]) for k in range(1, modes + 1))
+    u0 = 1.0 + 0.1 * pert / float(np.max(np.abs(pert)))
+    p = make_problem(N=N, n=n, bc="periodic", h=h, dt=cfl * h / float(np.mean(u0)), nu=nu, scheme="etd1",
+                     nonlin="burgers_frozen", nl_coef=1.0, window="upwind")
+    return p, u0
+
+
 STEPS = {"advection_diffusion": 100, "burgers": 1000, "kdv": 2000, "allen_cahn_batch": 500,
-         "burgers_adjoint_batch": 500, "burgers_etdrk4": 1000}
+         "burgers_adjoint_batch": 500, "burgers_etdrk4": 1000, "burgers_upwind": 1000}
