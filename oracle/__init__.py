@@ -6,7 +6,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 plain dicts (see ``workloads``) with the keys
 
     N, n, bc, h, dt, c, nu, delta, react, scheme, nonlin, nl_coef,
-    bc_left, bc_right, window (optional: "centred" or "upwind")
+    bc_left, bc_right, window (optional: "centred" or "upwind"),
+    x (optional: node coordinates of a non-uniform grid, increasing; Dirichlet)
 
 using the string names ``bc in {"periodic", "dirichlet", "neumann"}``,
 ``scheme in {"linear", "etd1", "etd2rk", "etdrk4"}`` and
@@ -43,6 +44,7 @@ class _Prob(ctypes.Structure):
         ("scheme", ctypes.c_int32), ("nonlin", ctypes.c_int32),
         ("nl_coef", ctypes.c_double), ("bc_left", ctypes.c_double), ("bc_right", ctypes.c_double),
         ("window", ctypes.c_int32),
+        ("x", ctypes.c_void_p),
     ]
 
 
@@ -59,6 +61,7 @@ def _load():
         lib = ctypes.CDLL(_SO)
         P = ctypes.POINTER(_Prob)
         lib.ora_fd_matrices.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, _D]
+        lib.ora_fd_nodes.argtypes = [ctypes.c_int, _D, _D, _D, _D]
         lib.ora_window_offset.argtypes = [P, ctypes.c_int64, ctypes.c_double]
         lib.ora_window_offset.restype = ctypes.c_int64
         lib.ora_augmented_row.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_double, ctypes.c_int,
@@ -84,11 +87,19 @@ def _f64(a):
 
 
 def _prob(p: dict) -> _Prob:
-    return _Prob(int(p["N"]), int(p["n"]), BC[p["bc"]], float(p["h"]), float(p["dt"]),
-                 float(p.get("c", 0.0)), float(p.get("nu", 0.0)), float(p.get("delta", 0.0)),
-                 float(p.get("react", 0.0)), SCHEME[p["scheme"]], NONLIN[p.get("nonlin", "none")],
-                 float(p.get("nl_coef", 0.0)), float(p.get("bc_left", 0.0)), float(p.get("bc_right", 0.0)),
-                 WINDOW[p.get("window", "centred")])
+    x = p.get("x")
+    xa = None
+    if x is not None:
+        xa = _f64(x)
+        if xa.shape != (int(p["N"]),):
+            raise ValueError("x must hold N node coordinates")
+    pr = _Prob(int(p["N"]), int(p["n"]), BC[p["bc"]], float(p["h"]), float(p["dt"]),
+               float(p.get("c", 0.0)), float(p.get("nu", 0.0)), float(p.get("delta", 0.0)),
+               float(p.get("react", 0.0)), SCHEME[p["scheme"]], NONLIN[p.get("nonlin", "none")],
+               float(p.get("nl_coef", 0.0)), float(p.get("bc_left", 0.0)), float(p.get("bc_right", 0.0)),
+               WINDOW[p.get("window", "centred")], xa.ctypes.data if xa is not None else None)
+    pr._keep = xa  # the coordinates must outlive the call
+    return pr
 
 
 def fd_matrices(n: int, h: float = 1.0):
@@ -96,6 +107,17 @@ def fd_matrices(n: int, h: float = 1.0):
     D = [np.zeros((n, n)) for _ in range(3)]
     if _load().ora_fd_matrices(n, h, *[_ptr(d) for d in D]):
         raise ValueError("bad stencil")
+    return D
+
+
+def fd_nodes(x):
+    """Differentiation matrices (D1, D2, D3) on the given nodes (step a2 on a
+    non-uniform stencil)."""
+    x = _f64(x)
+    n = x.shape[0]
+    D = [np.zeros((n, n)) for _ in range(3)]
+    if _load().ora_fd_nodes(n, _ptr(x), _ptr(D[0]), _ptr(D[1]), _ptr(D[2])):
+        raise ValueError("bad nodes")
     return D
 
 

@@ -9,7 +9,8 @@
  *   a1  stencil window of each node (centred, or fully one-sided against the
  *       flow, Sec. 4.1; one-sided "edge rows" next to Dirichlet ends,
  *       Sec. 2.1 step 3; reflected for Neumann ends),
- *   a2  differentiation matrices on the stencil (Sec. 2.1 step 1),
+ *   a2  differentiation matrices on the stencil (Sec. 2.1 step 1), on the
+ *       node's own coordinates for non-uniform grids (Sec. 4.3.3),
  *   a3  local operator L = -c D1 + nu D2 - delta D3 + react I (Thm 2, Remark),
  *   a4  the paper's s n x s n augmented block matrix (Sec. 3.1 step 1),
  *   a5  its exponential by the terminating Taylor series (Remark on
@@ -46,6 +47,7 @@ typedef struct {
     double nl_coef;  /* coefficient g of the nonlinear term */
     double bc_left, bc_right; /* Dirichlet end values */
     int32_t window;  /* WIN_*: centred stencils, or fully one-sided against the flow */
+    const double *x; /* node coordinates of a non-uniform grid (increasing), or NULL: uniform, spacing h */
 } ora_prob;
 
 /* Highest phi-function a scheme needs (blocks of the augmented matrix minus one). */
@@ -122,14 +124,18 @@ static int is_fixed_node(const ora_prob *P, int64_t i)
  * built from these wide matrices and rounded to double once, at the end. */
 #define FDT long double
 #define FDFN fd_matrices_ld
+#define FDNODES fd_nodes_ld
 #include "lmep_oracle_fd.inc"
 #undef FDT
 #undef FDFN
+#undef FDNODES
 #define FDT __float128
 #define FDFN fd_matrices_q
+#define FDNODES fd_nodes_q
 #include "lmep_oracle_fd.inc"
 #undef FDT
 #undef FDFN
+#undef FDNODES
 
 /* The same matrices rounded to double (exported; also used for the
  * derivative terms of the nonlinearity, which are plain FP64 dot products). */
@@ -154,6 +160,7 @@ static __float128 absq_(__float128 x) { return x < 0 ? -x : x; }
 #define DW long double
 #define EPSW 0x1p-80L
 #define FD_WIDE fd_matrices_ld
+#define FD_NODES_WIDE fd_nodes_ld
 #define ABSW(x) fabsl(x)
 #define FN(name) name##_d
 #define RE(x) (x)
@@ -175,6 +182,7 @@ static __float128 absq_(__float128 x) { return x < 0 ? -x : x; }
 #undef DW
 #undef EPSW
 #undef FD_WIDE
+#undef FD_NODES_WIDE
 #undef ABSW
 #undef FN
 #undef RE
@@ -184,6 +192,7 @@ static __float128 absq_(__float128 x) { return x < 0 ? -x : x; }
 #define DW __float128
 #define EPSW ((__float128)0x1p-120)
 #define FD_WIDE fd_matrices_q
+#define FD_NODES_WIDE fd_nodes_q
 #define ABSW(x) absq_(x)
 #define FN(name) name##_q
 #define RE(x) (x)
@@ -194,6 +203,7 @@ static __float128 absq_(__float128 x) { return x < 0 ? -x : x; }
 #undef DW
 #undef EPSW
 #undef FD_WIDE
+#undef FD_NODES_WIDE
 #undef ABSW
 #undef FN
 #undef RE
@@ -205,6 +215,12 @@ static int check_prob(const ora_prob *P)
     if (P->bc == BC_NEUMANN && (P->n - 1) / 2 > P->N - 1) return -1;
     if (P->nonlin == NL_BURGERS_FROZEN && P->scheme != SCH_ETD1) return -1;
     if (P->window != WIN_CENTRED && P->window != WIN_UPWIND) return -1;
+    if (P->x) { /* non-uniform grids: Dirichlet ends, centred windows, pointwise N */
+        if (P->bc != BC_DIRICHLET || P->window != WIN_CENTRED) return -1;
+        if (P->nonlin != NL_NONE && P->nonlin != NL_ALLEN_CAHN) return -1;
+        for (int64_t j = 1; j < P->N; ++j)
+            if (!(P->x[j] > P->x[j - 1])) return -1;
+    }
     return 0;
 }
 
@@ -212,6 +228,21 @@ static int check_prob(const ora_prob *P)
 
 /* Stencil offset o of node i (integer step a1). */
 int64_t ora_window_offset(const ora_prob *P, int64_t i, double a) { return window_offset_p(P, i, a); }
+
+/* Differentiation matrices (rounded to double) on n given nodes. */
+int ora_fd_nodes(int n, const double *x, double *D1, double *D2, double *D3)
+{
+    long double xs[64], A1[64 * 64], A2[64 * 64], A3[64 * 64];
+    if (n < 1 || n > 63) return -1;
+    for (int a = 0; a < n; ++a) xs[a] = x[a];
+    if (fd_nodes_ld(n, xs, A1, A2, A3)) return -1;
+    for (int a = 0; a < n * n; ++a) {
+        D1[a] = (double)A1[a];
+        D2[a] = (double)A2[a];
+        D3[a] = (double)A3[a];
+    }
+    return 0;
+}
 
 /* Row r of the augmented exponential for a given local operator L (n x n,
  * row major): out = [W0 | W1 | W2 | W3] as in augmented_row (p + 1 parts). */
@@ -294,7 +325,7 @@ int ora_run_z(const ora_prob *P, double c_im, double nu_im, double delta_im,
 int ora_adjoint_step(const ora_prob *P, const double *u, const double *lam, double *lam_out, double *grad)
 {
     if (check_prob(P) || P->scheme >= SCH_ETD2RK || P->nonlin == NL_KDV || P->react != 0.0 ||
-        P->window != WIN_CENTRED)
+        P->window != WIN_CENTRED || P->x)
         return -1;
     const int n = P->n, p = scheme_p(P->scheme), W = (p + 1) * n;
     const int64_t N = P->N;

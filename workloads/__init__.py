@@ -33,7 +33,7 @@ def rng(seed: int) -> np.random.Generator:
 
 def make_problem(**kw) -> dict:
     p = dict(N=0, n=5, bc="periodic", h=1.0, dt=1.0, c=0.0, nu=0.0, delta=0.0, react=0.0,
-             scheme="linear", nonlin="none", nl_coef=0.0, bc_left=0.0, bc_right=0.0, window="centred")
+             scheme="linear", nonlin="none", nl_coef=0.0, bc_left=0.0, bc_right=0.0, window="centred", x=None)
     unknown = set(kw) - set(p)
     if unknown:
         raise KeyError(f"unknown problem keys {sorted(unknown)}")
