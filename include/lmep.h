@@ -122,14 +122,26 @@ typedef struct {
     int64_t state_off;  /* offset (in doubles) of the state in packed state buffers   */
     int64_t weight_off; /* offset (in doubles) of the weights in the weight buffer    */
     int32_t window;     /* LMEP_WIN_* (0 = centred)                                   */
+    const double* x;    /* NULL: uniform grid of spacing h.  Otherwise a DEVICE       */
+                        /* pointer to the N node coordinates of a non-uniform grid    */
+                        /* (strictly increasing; read by lmep_build_weights only, not */
+                        /* checked on the host; owned by the caller).  Every node     */
+                        /* then gets differentiation matrices on its own window's     */
+                        /* coordinates and its own exponential, harvested once        */
+                        /* (Sec. 4.3.3).  Supported: Dirichlet ends, centred windows, */
+                        /* LINEAR / ETD1 / ETD2RK, nonlinearity NONE or ALLEN_CAHN,   */
+                        /* odd n from 3 to 25 with n + p <= 32; anything else is      */
+                        /* LMEP_ERR_UNSUPPORTED, as are LMEP_F_PERSISTENT and the     */
+                        /* reverse step.  h is then unused.                          */
 } lmep_problem;
 
 /* Number of doubles of harvested weights one instance needs (kinds = 1 + p =
  * 1, 2, 3 for LINEAR, ETD1, ETD2RK; 6 for ETDRK4):
- *   weights rebuilt per node (BURGERS_FROZEN): kinds * n * N, layout
+ *   weights per node (BURGERS_FROZEN, rebuilt every step; non-uniform grids,
+ *       built once): kinds * n * N, layout
  *       [kind][k][i]  -- weight k of node i's stencil, kind 0 = W0 (row of
  *       e^{dt L}), 1 = W1 (row of dt phi1(dt L)), 2 = W2 (row of dt phi2(dt L));
- *   stationary operators: kinds * n * n, layout [kind][r][k] -- the harvest of
+ *   stationary operators on uniform grids: kinds * n * n, layout [kind][r][k] -- the harvest of
  *       stencil row r (every node harvests row r = -offset of its stencil).
  *       ETDRK4's kinds are rows of e^{L dt/2}, (dt/2) phi1(L dt/2), e^{L dt},
  *       dt alpha, dt beta and dt gamma with alpha = phi1 - 3 phi2 + 4 phi3,

@@ -49,9 +49,16 @@ class Batch:
         self.count = len(self.problems)
         so, wo = 0, 0
         self.state_off, self.weight_off, self.weight_len = [], [], []
+        self._coords = []  # device copies of non-uniform grids' coordinates
         structs = []
         for p in self.problems:
-            s = to_struct(p, so, wo)
+            x_ptr = None
+            if p.get("x") is not None:
+                xt = torch.as_tensor(np.asarray(p["x"], dtype=np.float64)).to(self.device)
+                assert xt.numel() == int(p["N"])
+                self._coords.append(xt)
+                x_ptr = xt.data_ptr()
+            s = to_struct(p, so, wo, x_ptr)
             wl = lmep_weight_count(s)
             structs.append(s)
             self.state_off.append(so)
@@ -92,12 +99,12 @@ class Batch:
         return [a[o:o + int(p["N"])].copy() for o, p in zip(self.state_off, self.problems)]
 
     def unpack_weights(self, w: torch.Tensor):
-        """Per instance: [kind, k, N] (frozen velocity) or [kind, r, k] (stationary)."""
+        """Per instance: [kind, k, N] (frozen velocity, non-uniform grid) or [kind, r, k] (stationary)."""
         a = w.detach().cpu().numpy()
         out = []
         for o, l, p in zip(self.weight_off, self.weight_len, self.problems):
             kinds, n = _KINDS[p["scheme"]], int(p["n"])
-            last = int(p["N"]) if p.get("nonlin") == "burgers_frozen" else n
+            last = int(p["N"]) if (p.get("nonlin") == "burgers_frozen" or p.get("x") is not None) else n
             out.append(a[o:o + l].reshape(kinds, n, last).copy())
         return out
 

@@ -45,6 +45,7 @@ class lmep_problem(ctypes.Structure):
         ("nl_coef", ctypes.c_double), ("bc_left", ctypes.c_double), ("bc_right", ctypes.c_double),
         ("state_off", ctypes.c_int64), ("weight_off", ctypes.c_int64),
         ("window", ctypes.c_int32),
+        ("x", ctypes.c_void_p),
     ]
 
 
@@ -105,15 +106,24 @@ def problem_array(problems):
     return arr
 
 
-def to_struct(p: dict, state_off: int = None, weight_off: int = None) -> lmep_problem:
-    return lmep_problem(
+def to_struct(p: dict, state_off: int = None, weight_off: int = None, x_ptr: int = None) -> lmep_problem:
+    """Problem dict -> C struct.  A non-uniform grid (key "x") needs the device
+    address of its coordinates in x_ptr; without one the host array's address
+    stands in (enough for the host-side counting and checks, never for a
+    build)."""
+    x = p.get("x")
+    if x is not None and x_ptr is None:
+        x_ptr = x.ctypes.data if hasattr(x, "ctypes") else int(x.data_ptr())
+    s = lmep_problem(
         int(p["N"]), int(p["n"]), BC_NAMES[p["bc"]], float(p["h"]), float(p["dt"]), float(p.get("c", 0.0)),
         float(p.get("nu", 0.0)), float(p.get("delta", 0.0)), float(p.get("react", 0.0)),
         SCHEME_NAMES[p["scheme"]], NONLIN_NAMES[p.get("nonlin", "none")], float(p.get("nl_coef", 0.0)),
         float(p.get("bc_left", 0.0)), float(p.get("bc_right", 0.0)),
         int(p.get("state_off", 0) if state_off is None else state_off),
         int(p.get("weight_off", 0) if weight_off is None else weight_off),
-        WINDOW_NAMES[p.get("window", "centred")])
+        WINDOW_NAMES[p.get("window", "centred")], x_ptr if x is not None else None)
+    s._keep = x
+    return s
 
 
 def lmep_weight_count(prob: lmep_problem) -> int:

@@ -22,7 +22,9 @@
 using namespace lmep;
 
 // The Python binding mirrors this layout field by field.
-static_assert(offsetof(lmep_problem, window) == 112 && sizeof(lmep_problem) == 120, "lmep_problem layout");
+static_assert(offsetof(lmep_problem, window) == 112 && offsetof(lmep_problem, x) == 120 &&
+                  sizeof(lmep_problem) == 128,
+              "lmep_problem layout");
 
 namespace {
 
@@ -53,10 +55,12 @@ int scheme_p(int scheme) {
 }
 int scheme_kinds(int scheme) { return scheme == LMEP_ETDRK4 ? 6 : 1 + scheme_p(scheme); }
 bool frozen(const lmep_problem& q) { return q.nonlin == LMEP_NL_BURGERS_FROZEN; }
+bool nonuniform(const lmep_problem& q) { return q.x != nullptr; }
+bool pernode(const lmep_problem& q) { return frozen(q) || nonuniform(q); }
 
 int64_t weight_count(const lmep_problem& q) {
     const int64_t kinds = scheme_kinds(q.scheme);
-    return frozen(q) ? kinds * q.n * q.N : kinds * q.n * q.n;
+    return pernode(q) ? kinds * q.n * q.N : kinds * q.n * q.n;
 }
 
 bool finite(double x) { return std::isfinite(x); }
@@ -64,8 +68,9 @@ bool finite(double x) { return std::isfinite(x); }
 // Checks of one instance (ERR_ARG for malformed input, ERR_UNSUPPORTED for a
 // well-formed combination the kernels do not implement).
 int check_problem(const lmep_problem& q, int k) {
-    if (q.n < 3 || q.n > kMaxN || (q.n % 2) == 0)
-        return fail(LMEP_ERR_ARG, "instance %d: stencil size n=%d must be odd, 3..%d", k, q.n, kMaxN);
+    const int nmax = nonuniform(q) ? kMaxNWide : kMaxN;
+    if (q.n < 3 || q.n > nmax || (q.n % 2) == 0)
+        return fail(LMEP_ERR_ARG, "instance %d: stencil size n=%d must be odd, 3..%d", k, q.n, nmax);
     if (q.N < q.n) return fail(LMEP_ERR_ARG, "instance %d: N=%lld < n=%d", k, (long long)q.N, q.n);
     if (!(q.h > 0) || !finite(q.h)) return fail(LMEP_ERR_ARG, "instance %d: grid spacing h must be > 0", k);
     if (!(q.dt > 0) || !finite(q.dt)) return fail(LMEP_ERR_ARG, "instance %d: dt must be > 0", k);
@@ -78,14 +83,20 @@ int check_problem(const lmep_problem& q, int k) {
     if (q.scheme == LMEP_LINEAR && q.nonlin != LMEP_NL_NONE)
         return fail(LMEP_ERR_ARG, "instance %d: LINEAR scheme with a nonlinear term", k);
     if (q.state_off < 0 || q.weight_off < 0) return fail(LMEP_ERR_ARG, "instance %d: negative offset", k);
-    if (q.n + scheme_p(q.scheme) > kMaxM)
-        return fail(LMEP_ERR_UNSUPPORTED, "instance %d: n + p = %d exceeds %d", k, q.n + scheme_p(q.scheme), kMaxM);
+    if (q.n + scheme_p(q.scheme) > (nonuniform(q) ? kMaxMWide : kMaxM))
+        return fail(LMEP_ERR_UNSUPPORTED, "instance %d: n + p = %d exceeds %d", k, q.n + scheme_p(q.scheme),
+                    nonuniform(q) ? kMaxMWide : kMaxM);
     if (frozen(q) && q.scheme != LMEP_ETD1)
         return fail(LMEP_ERR_UNSUPPORTED, "instance %d: frozen-velocity Burgers needs ETD1", k);
     if (q.window != LMEP_WIN_CENTRED && q.window != LMEP_WIN_UPWIND)
         return fail(LMEP_ERR_ARG, "instance %d: unknown window %d", k, q.window);
     if (q.window == LMEP_WIN_UPWIND && q.scheme == LMEP_ETDRK4)
         return fail(LMEP_ERR_UNSUPPORTED, "instance %d: upwind windows cover LINEAR, ETD1 and ETD2RK", k);
+    if (nonuniform(q) && (q.bc != LMEP_BC_DIRICHLET || q.window != LMEP_WIN_CENTRED || q.scheme == LMEP_ETDRK4 ||
+                          (q.nonlin != LMEP_NL_NONE && q.nonlin != LMEP_NL_ALLEN_CAHN)))
+        return fail(LMEP_ERR_UNSUPPORTED,
+                    "instance %d: non-uniform grids cover Dirichlet ends, centred windows, LINEAR / ETD1 / ETD2RK "
+                    "and pointwise (none / Allen-Cahn) nonlinearity", k);
     return LMEP_OK;
 }
 
@@ -133,6 +144,17 @@ int64_t total_tiles(const lmep_problem* prob, int32_t count, int tile) {
     return t;
 }
 
+// Upper bound on the apply tiles of a batch (non-uniform instances may take
+// the 64-node tile, the rest at least the 256-node one).
+int64_t max_apply_tiles(const lmep_problem* prob, int32_t count) {
+    int64_t t = 0;
+    for (int k = 0; k < count; ++k) {
+        const int tile = nonuniform(prob[k]) ? kApplyTileTiny : kApplyTileSmall;
+        t += (prob[k].N + tile - 1) / tile;
+    }
+    return t;
+}
+
 Layout layout(const lmep_problem* prob, int32_t count, int op) {
     Layout L;
     size_t off = 0;
@@ -143,7 +165,7 @@ Layout layout(const lmep_problem* prob, int32_t count, int op) {
     off += tab;
     if (op == 1) {
         L.tile_inst = off;
-        off += align256(sizeof(int) * (size_t)total_tiles(prob, count, kApplyTileSmall));
+        off += align256(sizeof(int) * (size_t)max_apply_tiles(prob, count));
         L.state = off;
         off += align256(sizeof(double) * (size_t)state_extent(prob, count));
     }
@@ -192,6 +214,7 @@ DevProb to_dev(const lmep_problem& q, int index) {
     d.bc_left = q.bc_left;
     d.bc_right = q.bc_right;
     d.window = q.window;
+    d.x = q.x;
     return d;
 }
 
@@ -199,7 +222,9 @@ DevProb to_dev(const lmep_problem& q, int index) {
 // one kernel variant.
 struct Group {
     int n = 0, p = 0, scheme = 0, nonlin = 0, tile = 0;
-    bool pernode = false;
+    bool pernode = false;    // weights stored per node (frozen velocity or non-uniform grid)
+    bool frozen = false;     // rebuilt every step (frozen velocity)
+    bool nonuniform = false; // non-uniform grid: wide build, per-node stationary weights
     bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
@@ -212,21 +237,23 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
     struct Part {
         int k, harvest;
     };
-    std::map<std::pair<int, int>, std::vector<Part>> by;
+    std::map<std::tuple<int, int, int>, std::vector<Part>> by;  // (n, p, non-uniform)
     for (int k = 0; k < count; ++k) {
         if (!want(prob[k])) continue;
+        const int nu = nonuniform(prob[k]) ? 1 : 0;
         if (prob[k].scheme == LMEP_ETDRK4) {
-            by[{prob[k].n, 3}].push_back({k, HARVEST_RK4_FULL});
-            by[{prob[k].n, 1}].push_back({k, HARVEST_RK4_HALF});
+            by[{prob[k].n, 3, nu}].push_back({k, HARVEST_RK4_FULL});
+            by[{prob[k].n, 1, nu}].push_back({k, HARVEST_RK4_HALF});
         } else {
-            by[{prob[k].n, scheme_p(prob[k].scheme)}].push_back({k, HARVEST_PLAIN});
+            by[{prob[k].n, scheme_p(prob[k].scheme), nu}].push_back({k, HARVEST_PLAIN});
         }
     }
     std::vector<Group> groups;
     for (auto& kv : by) {
         Group g;
-        g.n = kv.first.first;
-        g.p = kv.first.second;
+        g.n = std::get<0>(kv.first);
+        g.p = std::get<1>(kv.first);
+        g.nonuniform = std::get<2>(kv.first) != 0;
         g.first = (int)tab.size();
         int64_t items = 0;
         for (const Part& part : kv.second) {
@@ -235,7 +262,7 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             d.harvest = part.harvest;
             if (part.harvest == HARVEST_RK4_HALF) d.dt = 0.5 * prob[part.k].dt;
             d.item_begin = items;
-            items += frozen(prob[part.k]) ? prob[part.k].N : prob[part.k].n;
+            items += pernode(prob[part.k]) ? prob[part.k].N : prob[part.k].n;
             tab.push_back(d);
         }
         g.count = (int)kv.second.size();
@@ -249,20 +276,27 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
 // multi_kb > 0: tiles of the multi-step kernel advancing multi_kb steps per launch.
 std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab,
                               std::vector<int>& tile_inst, int multi_kb = 0) {
+    // weight kind: 0 stationary table, 1 frozen velocity, 2 non-uniform grid
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < count; ++k)
-        by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : 0}].push_back(k);
+        by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : (nonuniform(prob[k]) ? 2 : 0)}]
+            .push_back(k);
     std::vector<Group> groups;
     for (auto& kv : by) {
         Group g;
         std::tie(g.n, g.scheme, g.nonlin, std::ignore) = kv.first;
         g.pernode = std::get<3>(kv.first) != 0;
+        g.frozen = std::get<3>(kv.first) == 1;
+        g.nonuniform = std::get<3>(kv.first) == 2;
         g.first = (int)tab.size();
         int64_t nodes = 0;
         for (int k : kv.second) nodes += prob[k].N;
         g.stepk = multi_kb > 0 || g.scheme == LMEP_ETDRK4;
+        const int64_t avg = nodes / (int64_t)kv.second.size();
         g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb > 0 ? multi_kb : 1)
-                         : (nodes < kSmallGroupNodes ? kApplyTileSmall : kApplyTile);
+                         : (g.nonuniform && avg <= kApplyTileTiny)
+                               ? kApplyTileTiny
+                               : ((nodes < kSmallGroupNodes || avg <= kApplyTileSmall) ? kApplyTileSmall : kApplyTile);
         int64_t tiles = 0;
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
@@ -448,8 +482,12 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
     char* base = (char*)d_scratch;
     if ((rc = upload(btab, none, base + L.build_tab, nullptr, s))) return rc;
     const DevProb* dtab = (const DevProb*)(base + L.build_tab);
-    for (auto& g : groups)
-        HIP_TRY(launch_build(g.n, g.p, dtab + g.first, g.count, g.items, fd, d_u, d_w, nullptr, s));
+    for (auto& g : groups) {
+        if (g.nonuniform)
+            HIP_TRY(launch_build_wide(g.n, g.p, dtab + g.first, g.count, g.items, d_w, s));
+        else
+            HIP_TRY(launch_build(g.n, g.p, dtab + g.first, g.count, g.items, fd, d_u, d_w, nullptr, s));
+    }
     return LMEP_OK;
 }
 
@@ -469,6 +507,8 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
                             "BURGERS_FROZEN)", k);
             if (prob[k].window != LMEP_WIN_CENTRED)
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs centred windows (instance %d)", k);
+            if (nonuniform(prob[k]))
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs a uniform grid (instance %d)", k);
         }
     if ((flags & LMEP_F_GRAPH) && (flags & (LMEP_F_PROFILE | LMEP_F_COUNT)))
         return fail(LMEP_ERR_ARG, "LMEP_F_PROFILE / LMEP_F_COUNT cannot be combined with LMEP_F_GRAPH");
@@ -515,7 +555,7 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
 
     const bool fuse = t_fuse_frozen.load() != 0;
     bool apply_launched = false;  // any apply kernel besides the fused ones
-    for (auto& gr : agroups) apply_launched |= !(gr.pernode && fuse);
+    for (auto& gr : agroups) apply_launched |= !(gr.frozen && fuse);
     auto enqueue = [&]() -> int {
         // destinations alternate between the scratch state and d_u_out so that
         // the last step lands in d_u_out and no step works in place
@@ -534,10 +574,13 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
             if (apply_launched) HIP_TRY(timer.mark(false, s, true));
             int64_t tile0 = 0;
             for (auto& gr : agroups) {
-                const bool fused = gr.pernode && fuse;  // already advanced by its build kernel
+                const bool fused = gr.frozen && fuse;  // already advanced by its build kernel
                 if (!fused && gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
                                          dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
+                else if (gr.nonuniform)
+                    HIP_TRY(launch_apply_nonuniform(gr.n, gr.tile, gr.scheme, gr.nonlin, dat + gr.first, dti + tile0,
+                                                    gr.items, fd, d_w, src, dst, s));
                 else if (!fused)
                     HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first,
                                          dti + tile0, gr.items, fd, d_w, src, dst, s));
@@ -613,9 +656,10 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
     for (int k = 0; k < count; ++k) {
         const lmep_problem& q = prob[k];
         if (q.scheme == LMEP_ETD2RK || q.scheme == LMEP_ETDRK4 || q.nonlin == LMEP_NL_KDV ||
-            q.window != LMEP_WIN_CENTRED)
+            q.window != LMEP_WIN_CENTRED || nonuniform(q))
             return fail(LMEP_ERR_UNSUPPORTED,
-                        "instance %d: the reverse step covers LINEAR and ETD1 without KdV, centred windows", k);
+                        "instance %d: the reverse step covers LINEAR and ETD1 without KdV, centred windows, "
+                        "uniform grids", k);
     }
     if (!d_u_k || !d_lambda_next || !d_lambda_k || !d_grad) return fail(LMEP_ERR_ARG, "NULL pointer argument");
     const int64_t ext = state_extent(prob, count);

@@ -12,6 +12,8 @@ namespace lmep {
 constexpr int kMaxN = 15;     // largest stencil
 constexpr int kMaxM = 16;     // largest local matrix n + p (one 16-lane DPP row)
 constexpr int kNumN = 7;      // stencil sizes 3, 5, ..., 15
+constexpr int kMaxNWide = 25; // non-uniform grids: largest stencil
+constexpr int kMaxMWide = 32; // non-uniform grids: largest local matrix (LDS build)
 constexpr int kFdDerivs = 3;  // first, second and third derivative tables
 
 // Device-side record of one instance, filled by the host from lmep_problem.
@@ -27,7 +29,8 @@ struct DevProb {
     int32_t p, frozen, index, harvest;  // harvest: what the build writes (HARVEST_*)
     double h, dt, c, nu, delta, react, nl_coef, bc_left, bc_right;
     int32_t window, pad1;  // WIN_*
-    double pad2[2];
+    const double* x;       // node coordinates (non-uniform grids) or nullptr
+    double pad2[1];
 };
 static_assert(sizeof(DevProb) == 160, "DevProb layout");
 
@@ -61,6 +64,12 @@ hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t
                         const double* fd, const double* d_u, double* d_w, unsigned long long* stats,
                         hipStream_t stream, double* d_u_out = nullptr);
 
+// Stationary per-node weights of non-uniform grids (one node per wavefront,
+// matrices in LDS; p <= 2, n + p <= kMaxMWide).
+hipError_t launch_build_wide(int n, int p, const DevProb* d_probs, int nprob, int64_t items, double* d_w,
+                             hipStream_t stream);
+size_t build_wide_lds_bytes(int n, int p);
+
 // One time step over a group of instances sharing (n, scheme, nonlin,
 // per-node weights); ETD2RK's two stages run in one kernel.  d_tile_inst maps
 // each block (tile of `tile` nodes, 256 or 1024) to its instance in d_probs,
@@ -68,6 +77,11 @@ hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t
 hipError_t launch_apply(int n, int tile, int scheme, int nonlin, bool pernode, const DevProb* d_probs,
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
                         const double* d_u_in, double* d_u_out, hipStream_t stream);
+// The same for non-uniform grids (stationary per-node weights, n <= kMaxNWide,
+// nonlinearity none or Allen-Cahn).
+hipError_t launch_apply_nonuniform(int n, int tile, int scheme, int nonlin, const DevProb* d_probs,
+                                   const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                                   const double* d_u_in, double* d_u_out, hipStream_t stream);
 
 // Stationary weights, several steps per launch (stepk.hpp).  A block stages
 // kStepRegion consecutive positions of its instance, advances them `ksteps`
@@ -98,6 +112,7 @@ hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
                         const double* d_u_in, double* d_u_out, hipStream_t stream);
 
+constexpr int kApplyTileTiny = 64;     // nodes per apply block for small non-uniform instances
 constexpr int kApplyTileSmall = 256;   // nodes per apply block for groups with few nodes
 constexpr int kApplyTile = 1024;       // nodes per apply block otherwise
 constexpr int64_t kSmallGroupNodes = 1 << 20;  // groups below this many nodes use the small tile

@@ -129,7 +129,8 @@ def test_window_field_checks():
     """The window field: unknown values are ARG; upwind windows are refused
     with ETDRK4, with multi-step launches and by the reverse step before any
     device work.  The Python mirror has the C layout (window at byte 112)."""
-    assert lmep.lmep_problem.window.offset == 112 and ctypes.sizeof(lmep.lmep_problem) == 120
+    assert lmep.lmep_problem.window.offset == 112 and lmep.lmep_problem.x.offset == 120
+    assert ctypes.sizeof(lmep.lmep_problem) == 128
     lib = lmep.library()
     s = _structs()
     s[0].window = 2

@@ -116,6 +116,19 @@ def test_chebyshev_allen_cahn_run():
     assert np.sum(np.abs(np.abs(u) - 1.0) < 0.05) >= 50
 
 
+def test_paper_chebyshev_run_literal_coefficient():
+    """The run as printed (nu = eps = 0.01) to t = 70 at dt = 1e-4: the same
+    phase separation; at dt = 3e-4 the local scheme on this grid blows up."""
+    import workloads
+    p, u0 = workloads.allen_cahn_chebyshev()
+    u = oracle.run(p, u0, 700000)
+    assert u[0] == -1.0 and u[-1] == 1.0 and np.max(np.abs(u)) <= 1.02
+    assert np.sum(np.abs(np.abs(u) - 1.0) < 0.05) >= 40
+    q, _ = workloads.allen_cahn_chebyshev(dt=3e-4)
+    bad = oracle.run(q, u0, 7000)
+    assert not np.all(np.isfinite(bad)) or np.max(np.abs(bad)) > 10.0
+
+
 def test_chebyshev_etd1_first_order_in_time():
     T = 1.0
     ref = oracle.run(_paper_ac(T / 3200)[0], _paper_ac(0.01)[1], 3200)
