@@ -57,7 +57,9 @@ def stationary_flops(p: dict) -> float:
     return f
 
 
+PEAK_LDS_GBS = 256 * 128 * 2.4  # 128 B per clock per CU
 SCHEME_ID = {"linear": 0, "etd1": 1, "etd2rk": 2, "etdrk4": 3}
+KINDS = {"linear": 1, "etd1": 2, "etd2rk": 3, "etdrk4": 6}
 NONLIN_ID = {"none": 0, "burgers_frozen": 1, "kdv": 2, "allen_cahn": 3}
 
 
@@ -112,6 +114,13 @@ def make_workload(name: str):
         p, u0 = workloads.burgers_upwind()
         return [p], [u0], ("viscous Burgers N=65536 n=7 periodic on fully one-sided (upwind) stencils at "
                            "CFL 3.5, frozen-velocity ETD1, weights rebuilt every step")
+    if name == "allen_cahn_chebyshev_batch":
+        ps, us = workloads.allen_cahn_chebyshev_batch()
+        return ps, us, ("8192 Allen-Cahn instances on the paper's Chebyshev grid (N=64, n=21), nu ~ U[0.005,0.01], "
+                        "Dirichlet -1/1, ETD1, per-node stationary weights")
+    if name == "allen_cahn_chebyshev":
+        p, u0 = workloads.allen_cahn_chebyshev()
+        return [p], [u0], "the paper's Allen-Cahn run: Chebyshev N=64, n=21, nu=0.01, dt=1e-4, ETD1"
     if name == "advection_diffusion":
         p, u0 = workloads.advection_diffusion()
         return [p], [u0], "periodic advection-diffusion N=256 n=5 CFL 2, LINEAR"
@@ -305,12 +314,20 @@ def main():
                 "avg_launch_us": prof["build_ms"] * 1e3 / prof["build_launches"],
                 "flops_per_launch": flops / prof["build_launches"],
                 "mean_squarings": prof["squarings"] / max(1, prof["matrices"])}
+    nonuniform = any(p.get("x") is not None for p in problems)
     if prof["apply_launches"] > 0:
         apply_s = prof["apply_ms"] / 1e3
         avg_us = prof["apply_ms"] * 1e3 / prof["apply_launches"]
         # algorithmic HBM bytes: per node and launch, u in + u out (16 B), plus
-        # the per-node weights of the frozen-velocity path (read every step)
-        ab = apply_bytes.get(args.workload, 16.0) * node_steps / kb
+        # the per-node weights of the frozen-velocity path (read every step) or
+        # of a non-uniform grid (read once per launch)
+        if nonuniform:
+            per_node = sum(p["N"] * (16.0 + 8.0 * KINDS[p["scheme"]] * p["n"]) for p in problems) / batch.state_size
+            if args.persistent:  # whole instances per block: every step of the call in one launch
+                kb = args.steps
+            ab = per_node * node_steps / kb
+        else:
+            ab = apply_bytes.get(args.workload, 16.0) * node_steps / kb
         gbs = ab / apply_s / 1e9
         extra["apply"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                           "frac": gbs / PEAK_HBM_GBS, "avg_launch_us": avg_us, "steps_per_launch": kb,
@@ -325,14 +342,28 @@ def main():
             # per launch and the FP64 work of the steps bounds the kernel
             def kname(p):
                 nl = NONLIN_ID[p.get("nonlin", "none")] if p["scheme"] != "linear" else 0
+                if p.get("x") is not None:
+                    return f"resident_kernel<{p['n']},{SCHEME_ID[p['scheme']]},{nl}>"
                 if p["scheme"] == "etdrk4":
                     return f"stepk_rk4_kernel<{p['n']},{nl},{kb}>"
                 return f"stepk_kernel<{p['n']},{SCHEME_ID[p['scheme']]},{nl},{kb}>"
-            if kb > 1 or any(p["scheme"] == "etdrk4" for p in problems):
+            if kb > 1 or any(p["scheme"] == "etdrk4" for p in problems) or (nonuniform and args.persistent):
                 names = sorted({kname(p) for p in problems})
             else:
                 names = ["apply_kernel"]
-            roof = dict(extra["apply_alu"] if kb > 1 else extra["apply"],
+            if nonuniform and args.persistent:
+                # one block holds an instance: per node-step the kernel reads its
+                # window of u from LDS (N is formed from it), and for ETD2RK with
+                # a nonlinearity the windows of N(a) and N(u) as well
+                def lds_reads(p):
+                    has_n = p["scheme"] != "linear" and p.get("nonlin", "none") != "none"
+                    return p["n"] * (1 + (2 if has_n and p["scheme"] == "etd2rk" else 0))
+                lb = sum(p["N"] * 8.0 * lds_reads(p) for p in problems) * args.steps
+                gbs_lds = lb / apply_s / 1e9
+                extra["lds"] = {"bound": "lds", "achieved": gbs_lds, "peak": PEAK_LDS_GBS, "unit": "GB/s",
+                                "frac": gbs_lds / PEAK_LDS_GBS, "bytes_per_launch": lb / prof["apply_launches"]}
+            roof = dict(extra["lds"] if (nonuniform and args.persistent) else
+                        (extra["apply_alu"] if kb > 1 else extra["apply"]),
                         traffic=measured_traffic(names, args.workload) if kb > 1 else None,
                         kernel=" + ".join(names), avg_launch_us=avg_us)
     out = {

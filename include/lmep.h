@@ -93,7 +93,10 @@ enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
                                   /* HBM is read and written once per launch instead of once    */
                                   /* per step; same result bit for bit as the one-step path.    */
                                   /* Stationary weights only (LMEP_ERR_UNSUPPORTED if any       */
-                                  /* instance is BURGERS_FROZEN).                               */
+                                  /* instance is BURGERS_FROZEN).  Non-uniform instances of at  */
+                                  /* most 512 nodes are held whole by one block each (weights   */
+                                  /* in registers) for all n_steps (launches of up to 65536     */
+                                  /* steps); larger ones are LMEP_ERR_UNSUPPORTED.              */
 #define LMEP_F_CHECK_FINITE 0x4u  /* scan the result; LMEP_ERR_NONFINITE if any entry is not    */
                                   /* finite (synchronises the stream)                            */
 #define LMEP_F_PROFILE      0x8u  /* time the weight-build and apply kernels with HIP events    */
@@ -131,8 +134,8 @@ typedef struct {
                         /* (Sec. 4.3.3).  Supported: Dirichlet ends, centred windows, */
                         /* LINEAR / ETD1 / ETD2RK, nonlinearity NONE or ALLEN_CAHN,   */
                         /* odd n from 3 to 25 with n + p <= 32; anything else is      */
-                        /* LMEP_ERR_UNSUPPORTED, as are LMEP_F_PERSISTENT and the     */
-                        /* reverse step.  h is then unused.                          */
+                        /* LMEP_ERR_UNSUPPORTED, as is the reverse step (and          */
+                        /* LMEP_F_PERSISTENT for N > 512).  h is then unused.         */
 } lmep_problem;
 
 /* Number of doubles of harvested weights one instance needs (kinds = 1 + p =

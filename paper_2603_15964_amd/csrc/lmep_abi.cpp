@@ -225,6 +225,8 @@ struct Group {
     bool pernode = false;    // weights stored per node (frozen velocity or non-uniform grid)
     bool frozen = false;     // rebuilt every step (frozen velocity)
     bool nonuniform = false; // non-uniform grid: wide build, per-node stationary weights
+    bool resident = false;   // non-uniform, several steps per launch, one block per instance
+    int64_t max_nodes = 0;
     bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
@@ -291,7 +293,9 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         g.first = (int)tab.size();
         int64_t nodes = 0;
         for (int k : kv.second) nodes += prob[k].N;
-        g.stepk = multi_kb > 0 || g.scheme == LMEP_ETDRK4;
+        g.stepk = !g.nonuniform && (multi_kb > 0 || g.scheme == LMEP_ETDRK4);
+        g.resident = g.nonuniform && multi_kb > 0;
+        for (int k : kv.second) g.max_nodes = std::max(g.max_nodes, prob[k].N);
         const int64_t avg = nodes / (int64_t)kv.second.size();
         g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb > 0 ? multi_kb : 1)
                          : (g.nonuniform && avg <= kApplyTileTiny)
@@ -507,8 +511,9 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
                             "BURGERS_FROZEN)", k);
             if (prob[k].window != LMEP_WIN_CENTRED)
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs centred windows (instance %d)", k);
-            if (nonuniform(prob[k]))
-                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs a uniform grid (instance %d)", k);
+            if (nonuniform(prob[k]) && prob[k].N > kResidentMaxN)
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT on a non-uniform grid needs N <= %d "
+                            "(instance %d)", kResidentMaxN, k);
         }
     if ((flags & LMEP_F_GRAPH) && (flags & (LMEP_F_PROFILE | LMEP_F_COUNT)))
         return fail(LMEP_ERR_ARG, "LMEP_F_PROFILE / LMEP_F_COUNT cannot be combined with LMEP_F_GRAPH");
@@ -529,7 +534,12 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab);
     const int kb = multi ? t_steps_per_launch.load() : 1;
     auto agroups = plan_apply(prob, count, atab, tile_inst, multi ? kb : 0);
-    const int launches = (n_steps + kb - 1) / kb;  // apply launches per group
+    // resident groups (small non-uniform instances) advance all n_steps from
+    // d_u_in to d_u_out in the first iteration; when nothing else is in the
+    // batch that iteration is all there is
+    bool all_resident = bgroups.empty();
+    for (auto& gr : agroups) all_resident &= gr.resident;
+    const int launches = all_resident ? 1 : (n_steps + kb - 1) / kb;  // apply launches per group
     char* base = (char*)d_scratch;
     if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s, &tile_inst, base + L.tile_inst)))
         return rc;
@@ -578,6 +588,14 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
                 if (!fused && gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
                                          dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
+                else if (gr.resident) {
+                    // in place after the first chunk: a block reads its whole
+                    // instance before it writes any of it
+                    for (int done = 0; st == 0 && done < n_steps; done += kResidentMaxSteps)
+                        HIP_TRY(launch_resident(gr.n, gr.scheme, gr.nonlin, dat + gr.first, gr.count, gr.max_nodes,
+                                                d_w, done == 0 ? d_u_in : d_u_out, d_u_out,
+                                                std::min(kResidentMaxSteps, n_steps - done), s));
+                }
                 else if (gr.nonuniform)
                     HIP_TRY(launch_apply_nonuniform(gr.n, gr.tile, gr.scheme, gr.nonlin, dat + gr.first, dti + tile0,
                                                     gr.items, fd, d_w, src, dst, s));

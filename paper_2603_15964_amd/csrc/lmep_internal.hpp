@@ -14,6 +14,8 @@ constexpr int kMaxM = 16;     // largest local matrix n + p (one 16-lane DPP row
 constexpr int kNumN = 7;      // stencil sizes 3, 5, ..., 15
 constexpr int kMaxNWide = 25; // non-uniform grids: largest stencil
 constexpr int kMaxMWide = 32; // non-uniform grids: largest local matrix (LDS build)
+constexpr int kResidentMaxN = 512;  // non-uniform instances a multi-step block holds whole
+constexpr int kResidentMaxSteps = 1 << 16;  // steps of one such launch (longer runs: several)
 constexpr int kFdDerivs = 3;  // first, second and third derivative tables
 
 // Device-side record of one instance, filled by the host from lmep_problem.
@@ -77,6 +79,12 @@ size_t build_wide_lds_bytes(int n, int p);
 hipError_t launch_apply(int n, int tile, int scheme, int nonlin, bool pernode, const DevProb* d_probs,
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
                         const double* d_u_in, double* d_u_out, hipStream_t stream);
+// Several steps per launch for non-uniform instances of at most kResidentMaxN
+// nodes: one block per instance, the whole instance in the block (resident.hip).
+// max_nodes = the group's largest N.
+hipError_t launch_resident(int n, int scheme, int nonlin, const DevProb* d_probs, int count, int64_t max_nodes,
+                           const double* d_w, const double* d_u_in, double* d_u_out, int ksteps, hipStream_t stream);
+
 // The same for non-uniform grids (stationary per-node weights, n <= kMaxNWide,
 // nonlinearity none or Allen-Cahn).
 hipError_t launch_apply_nonuniform(int n, int tile, int scheme, int nonlin, const DevProb* d_probs,

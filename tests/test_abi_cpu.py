@@ -151,3 +151,30 @@ def test_window_field_checks():
     rc = lib.lmep_adjoint_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20),
                                ctypes.c_void_p(1 << 24), ctypes.c_void_p(256), 1 << 30, None)
     assert rc == lmep.LMEP_ERR_UNSUPPORTED, lmep.lmep_last_error()
+
+
+def test_nonuniform_checks():
+    """Non-uniform grids: per-node weight counts, refusals before any device
+    work (periodic ends, upwind windows, ETDRK4, KdV, the reverse step, and
+    multi-step launches beyond 512 nodes)."""
+    import workloads
+    lib = lmep.library()
+    p, _ = workloads.allen_cahn_chebyshev()
+    assert lmep.lmep_weight_count(lmep.to_struct(p)) == 2 * 21 * 64
+    big = dict(p, N=600, x=workloads.chebyshev(600))
+    for bad in (dict(bc="periodic"), dict(window="upwind"), dict(scheme="etdrk4"), dict(nonlin="kdv")):
+        s = lmep.problem_array([dict(p, **bad)])
+        rc = lib.lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 1, 0,
+                           ctypes.c_void_p(256), 1 << 30, None)
+        assert rc == lmep.LMEP_ERR_UNSUPPORTED, (bad, lmep.lmep_last_error())
+    s = lmep.problem_array([dict(p, n=27)])
+    assert lib.lmep_build_weights(s, 1, None, ctypes.c_void_p(8), ctypes.c_void_p(256), 1 << 30, None) == \
+        lmep.LMEP_ERR_ARG
+    s = lmep.problem_array([big])
+    rc = lib.lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), 4,
+                       lmep.LMEP_F_PERSISTENT, ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_UNSUPPORTED and "512" in lmep.lmep_last_error()
+    s = lmep.problem_array([p])
+    rc = lib.lmep_adjoint_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20),
+                               ctypes.c_void_p(1 << 24), ctypes.c_void_p(256), 1 << 30, None)
+    assert rc == lmep.LMEP_ERR_UNSUPPORTED

@@ -162,3 +162,49 @@ def test_full_size_chebyshev_batch_sample():
     got = _gpu_run(ps, us, 20)
     for k in (0, 1, 777, 4096, 8191):
         assert _rel(got[k], oracle.run(ps[k], us[k], 20)) <= 1e-12, k
+
+
+# ------------------------------------------- several steps per launch ----
+@pytest.mark.parametrize("kb", [1, 2, 8])
+@pytest.mark.parametrize("name,make", ONE_STEP, ids=[c[0] for c in ONE_STEP])
+def test_resident_equals_one_step_bitwise(name, make, kb):
+    """LMEP_F_PERSISTENT on non-uniform instances (each held whole by one
+    block, kb steps per launch) gives the one-step path's result bit for bit;
+    19 steps leave a remainder launch."""
+    _print_case("resident", name, kb)
+    p, u0 = make()
+    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
+    try:
+        res = _gpu_run([p], [u0], 19, flags=lmep.LMEP_F_PERSISTENT)[0]
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, 8)
+    one = _gpu_run([p], [u0], 19)[0]
+    assert np.array_equal(res, one)
+    assert _rel(res, oracle.run(p, u0, 19)) <= 1e-12
+
+
+def test_resident_batch_uneven_sizes_and_graph():
+    """Instances of 17 to 512 nodes in one resident launch, eager and under
+    graph capture, against the oracle."""
+    _print_case("resident uneven batch")
+    probs, states = [], []
+    # dt follows the smallest Chebyshev spacing (~ N^-2) squared: the local
+    # scheme's diffusion limit
+    for N, n in ((17, 5), (64, 21), (100, 13), (333, 25), (512, 9)):
+        x = workloads.chebyshev(N)
+        probs.append(make_problem(N=N, n=n, bc="dirichlet", h=2.0 / (N - 1), dt=1e-4 * (64.0 / N) ** 4,
+                                  nu=0.01, scheme="etd1", nonlin="allen_cahn", nl_coef=1.0, bc_left=-1.0,
+                                  bc_right=1.0, x=x))
+        states.append(0.53 * x + 0.47 * np.sin(-1.5 * np.pi * x))
+    eager = _gpu_run(probs, states, 30, flags=lmep.LMEP_F_PERSISTENT)
+    graph = _gpu_run(probs, states, 30, flags=lmep.LMEP_F_PERSISTENT | lmep.LMEP_F_GRAPH)
+    for p, u0, a, b in zip(probs, states, eager, graph):
+        assert np.array_equal(a, b)
+        assert _rel(a, oracle.run(p, u0, 30)) <= 1e-12, (p["N"], p["n"])
+
+
+def test_resident_paper_run_to_t7():
+    _print_case("resident paper run to t=7")
+    p, u0 = workloads.allen_cahn_chebyshev()
+    got = _gpu_run([p], [u0], 70000, flags=lmep.LMEP_F_PERSISTENT)[0]
+    assert _rel(got, oracle.run(p, u0, 70000)) <= 1e-10
