@@ -349,6 +349,10 @@ def main():
                 return f"stepk_kernel<{p['n']},{SCHEME_ID[p['scheme']]},{nl},{kb}>"
             if kb > 1 or any(p["scheme"] == "etdrk4" for p in problems) or (nonuniform and args.persistent):
                 names = sorted({kname(p) for p in problems})
+            elif nonuniform and all(p["N"] <= 64 for p in problems):
+                names = sorted({f"apply_kernel<{p['n']},{SCHEME_ID[p['scheme']]},"
+                                f"{NONLIN_ID[p.get('nonlin', 'none')] if p['scheme'] != 'linear' else 0},true,64>"
+                                for p in problems})
             else:
                 names = ["apply_kernel"]
             if nonuniform and args.persistent:
@@ -364,7 +368,7 @@ def main():
                                 "frac": gbs_lds / PEAK_LDS_GBS, "bytes_per_launch": lb / prof["apply_launches"]}
             roof = dict(extra["lds"] if (nonuniform and args.persistent) else
                         (extra["apply_alu"] if kb > 1 else extra["apply"]),
-                        traffic=measured_traffic(names, args.workload) if kb > 1 else None,
+                        traffic=measured_traffic(names, args.workload) if (kb > 1 or nonuniform) else None,
                         kernel=" + ".join(names), avg_launch_us=avg_us)
     out = {
         "metric": "node-steps/s (weight build+apply, FP64)",

@@ -49,15 +49,18 @@ class Batch:
         self.count = len(self.problems)
         so, wo = 0, 0
         self.state_off, self.weight_off, self.weight_len = [], [], []
-        self._coords = []  # device copies of non-uniform grids' coordinates
+        # coordinates of the non-uniform grids, packed into one device tensor
+        xs = [np.asarray(p["x"], dtype=np.float64) for p in self.problems if p.get("x") is not None]
+        for p, x in zip([p for p in self.problems if p.get("x") is not None], xs):
+            assert x.shape == (int(p["N"]),)
+        self._coords = torch.from_numpy(np.concatenate(xs)).to(self.device) if xs else None
+        xo = 0
         structs = []
         for p in self.problems:
             x_ptr = None
             if p.get("x") is not None:
-                xt = torch.as_tensor(np.asarray(p["x"], dtype=np.float64)).to(self.device)
-                assert xt.numel() == int(p["N"])
-                self._coords.append(xt)
-                x_ptr = xt.data_ptr()
+                x_ptr = self._coords.data_ptr() + 8 * xo
+                xo += int(p["N"])
             s = to_struct(p, so, wo, x_ptr)
             wl = lmep_weight_count(s)
             structs.append(s)
