@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--persistent", action="store_true",
                     help="stationary weights: advance several steps per launch (LMEP_F_PERSISTENT)")
     ap.add_argument("--steps-per-launch", type=int, default=8, choices=(1, 2, 4, 8))
+    ap.add_argument("--tune", action="store_true",
+                    help="let the autotuner pick fusion / steps per launch / apply tile (cached per GPU and shape)")
     ap.add_argument("--skip-count", action="store_true",
                     help="skip the squaring-count pass (its atomics would show up in a kernel trace)")
     args = ap.parse_args()
@@ -267,7 +269,18 @@ def main():
         batch.build_weights(w, u0)
     flags = lmep.LMEP_F_GRAPH if args.graph else 0
     kb = 1
-    if args.persistent:
+    tuned = None
+    if args.tune:
+        from paper_2603_15964_amd import tune as lt
+        tuned = lt.tune(batch, w, u0, steps=max(4, min(args.steps, 50)))
+        opts = dict(tuned.choice.options)
+        for o, v in opts.items():
+            lmep.lmep_set_option(o, v)
+        flags |= tuned.choice.flags
+        args.persistent = bool(tuned.choice.flags & lmep.LMEP_F_PERSISTENT)
+        if args.persistent:
+            kb = opts[lmep.LMEP_OPT_STEPS_PER_LAUNCH]
+    elif args.persistent:
         if frozen:
             raise SystemExit("--persistent needs stationary weights (this workload rebuilds them every step)")
         flags |= lmep.LMEP_F_PERSISTENT
@@ -384,7 +397,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "instances": batch.count, "nodes": batch.state_size,
-                   "graph": bool(args.graph), "steps_per_launch": kb},
+                   "graph": bool(args.graph), "steps_per_launch": kb,
+                   "tuned": (dict(tuned.choice.describe(), from_cache=tuned.from_cache) if tuned else None)},
         "roofline": roof,
         "detail": extra,
     }

@@ -218,11 +218,18 @@ const char* lmep_last_error(void);
  *                             two agree to rounding, not bit for bit (the
  *                             fused kernel sums a node's stencil terms as a
  *                             tree over the lanes).
+ *  LMEP_OPT_APPLY_TILE        nodes per block of the one-step apply kernel:
+ *                             0 (default) chooses from the group's size (64
+ *                             for small non-uniform instances, 256 for small
+ *                             groups, 1024 otherwise); 256 or 1024 force that
+ *                             tile for every one-step group (non-uniform
+ *                             groups also take 64).  Results do not depend on it.
  * lmep_set_option returns LMEP_OK or LMEP_ERR_ARG (unknown option or value);
  * lmep_get_option returns the value or LMEP_ERR_ARG. */
 #define LMEP_OPT_STEPS_PER_LAUNCH 1
 #define LMEP_OPT_PROFILE_ADJOINT 2
 #define LMEP_OPT_FUSE_FROZEN 3
+#define LMEP_OPT_APPLY_TILE 4
 int lmep_set_option(int32_t option, int32_t value);
 int32_t lmep_get_option(int32_t option);
 

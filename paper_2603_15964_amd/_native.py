@@ -82,6 +82,7 @@ EXPORTED = ("lmep_weight_count", "lmep_scratch_bytes", "lmep_build_weights", "lm
 LMEP_OPT_STEPS_PER_LAUNCH = 1
 LMEP_OPT_PROFILE_ADJOINT = 2
 LMEP_OPT_FUSE_FROZEN = 3
+LMEP_OPT_APPLY_TILE = 4
 
 
 def library() -> ctypes.CDLL:

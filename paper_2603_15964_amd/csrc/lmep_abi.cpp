@@ -35,6 +35,7 @@ thread_local int64_t t_prof_matrices = 0, t_prof_squarings = 0;
 std::atomic<int> t_steps_per_launch{8};  // LMEP_OPT_STEPS_PER_LAUNCH, process-wide
 std::atomic<int> t_profile_adjoint{0};   // LMEP_OPT_PROFILE_ADJOINT, process-wide
 std::atomic<int> t_fuse_frozen{1};       // LMEP_OPT_FUSE_FROZEN, process-wide
+std::atomic<int> t_apply_tile{0};        // LMEP_OPT_APPLY_TILE, process-wide (0 = by size)
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -297,10 +298,13 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         g.resident = g.nonuniform && multi_kb > 0;
         for (int k : kv.second) g.max_nodes = std::max(g.max_nodes, prob[k].N);
         const int64_t avg = nodes / (int64_t)kv.second.size();
+        const int forced = t_apply_tile.load();  // 0, 64 (non-uniform groups only), 256 or 1024
         g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb > 0 ? multi_kb : 1)
-                         : (g.nonuniform && avg <= kApplyTileTiny)
-                               ? kApplyTileTiny
-                               : ((nodes < kSmallGroupNodes || avg <= kApplyTileSmall) ? kApplyTileSmall : kApplyTile);
+                 : (forced != 0 && (forced != kApplyTileTiny || g.nonuniform))
+                     ? forced
+                     : (g.nonuniform && avg <= kApplyTileTiny)
+                           ? kApplyTileTiny
+                           : ((nodes < kSmallGroupNodes || avg <= kApplyTileSmall) ? kApplyTileSmall : kApplyTile);
         int64_t tiles = 0;
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
@@ -448,6 +452,12 @@ int lmep_set_option(int32_t option, int32_t value) {
         (option == LMEP_OPT_PROFILE_ADJOINT ? t_profile_adjoint : t_fuse_frozen).store(value);
         return LMEP_OK;
     }
+    if (option == LMEP_OPT_APPLY_TILE) {
+        if (value != 0 && value != 64 && value != kApplyTileSmall && value != kApplyTile)
+            return fail(LMEP_ERR_ARG, "apply tile must be 0, 64, %d or %d, got %d", kApplyTileSmall, kApplyTile, value);
+        t_apply_tile.store(value);
+        return LMEP_OK;
+    }
     return fail(LMEP_ERR_ARG, "unknown option %d", option);
 }
 
@@ -455,6 +465,7 @@ int32_t lmep_get_option(int32_t option) {
     if (option == LMEP_OPT_STEPS_PER_LAUNCH) return t_steps_per_launch.load();
     if (option == LMEP_OPT_PROFILE_ADJOINT) return t_profile_adjoint.load();
     if (option == LMEP_OPT_FUSE_FROZEN) return t_fuse_frozen.load();
+    if (option == LMEP_OPT_APPLY_TILE) return t_apply_tile.load();
     return fail(LMEP_ERR_ARG, "unknown option %d", option);
 }
 

@@ -1,0 +1,191 @@
+"""Autotuner for the launch configuration of a batch.
+
+For a batch of instances it times the launch choices the library offers and
+keeps the fastest one whose result agrees with the default path:
+
+* frozen-velocity instances: the fused build-and-apply kernel or the
+  build-then-apply pair (LMEP_OPT_FUSE_FROZEN);
+* stationary instances: one step per launch, or LMEP_F_PERSISTENT with 1, 2,
+  4 or 8 steps per launch (LMEP_OPT_STEPS_PER_LAUNCH; non-uniform instances
+  held whole by a block run every step in one launch);
+* one-step launches: the apply tile, chosen by size or forced to 256 / 1024
+  nodes (LMEP_OPT_APPLY_TILE).
+
+Choices are cached in a JSON file keyed by the GPU architecture and a
+signature of the batch (per kernel group: stencil size, scheme, nonlinearity,
+boundary, window, grid kind, and the instance count and node count rounded to
+powers of two), so a later run with the same shape reuses the choice without
+timing.  The timing itself is a callable, so the search logic runs without a
+GPU in tests.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import dataclass, field
+
+from ._native import (LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH,
+                      lmep_get_option, lmep_set_option)
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2603_15964_amd", "tune.json")
+_OPTIONS = (LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_APPLY_TILE)
+
+
+@dataclass(frozen=True)
+class Choice:
+    """One launch configuration: lmep_step flags plus option values."""
+    flags: int = 0
+    options: tuple = ()  # ((option, value), ...)
+
+    def as_dict(self):
+        return {"flags": self.flags, "options": [list(o) for o in self.options]}
+
+    @staticmethod
+    def from_dict(d):
+        return Choice(int(d["flags"]), tuple((int(a), int(b)) for a, b in d["options"]))
+
+    def describe(self):
+        names = {LMEP_OPT_FUSE_FROZEN: "fuse_frozen", LMEP_OPT_STEPS_PER_LAUNCH: "steps_per_launch",
+                 LMEP_OPT_APPLY_TILE: "apply_tile"}
+        d = {names[a]: b for a, b in self.options}
+        d["persistent"] = bool(self.flags & LMEP_F_PERSISTENT)
+        return d
+
+
+@dataclass
+class Result:
+    choice: Choice
+    ms_per_step: float
+    from_cache: bool
+    timings: dict = field(default_factory=dict)  # describe() string -> ms per step
+
+
+def _bucket(x: int) -> int:
+    return 1 << max(0, int(math.ceil(math.log2(max(1, x)))))
+
+
+def signature(problems) -> str:
+    """Shape of a batch as the planner sees it (group keys and size classes)."""
+    groups = {}
+    for p in problems:
+        key = (int(p["n"]), p["scheme"], p.get("nonlin", "none"), p["bc"], p.get("window", "centred"),
+               "nonuniform" if p.get("x") is not None else "uniform")
+        cnt, nodes, nmax = groups.get(key, (0, 0, 0))
+        groups[key] = (cnt + 1, nodes + int(p["N"]), max(nmax, int(p["N"])))
+    parts = []
+    for key in sorted(groups):
+        cnt, nodes, nmax = groups[key]
+        parts.append("/".join(map(str, key)) + f":{_bucket(cnt)}x{_bucket(nodes)}:{_bucket(nmax)}")
+    return ";".join(parts)
+
+
+def candidates(problems):
+    """Every configuration the library accepts for this batch."""
+    frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
+    persistent_ok = not frozen and all(p.get("window", "centred") == "centred" for p in problems) and \
+        all(p.get("x") is None or int(p["N"]) <= 512 for p in problems)
+    nonuniform = any(p.get("x") is not None for p in problems)
+    tiles = (0, 256, 1024) + ((64,) if nonuniform else ())
+    out = []
+    fuses = (1, 0) if frozen else (1,)
+    for fuse in fuses:
+        for tile in tiles:
+            out.append(Choice(0, ((LMEP_OPT_FUSE_FROZEN, fuse), (LMEP_OPT_STEPS_PER_LAUNCH, 8),
+                                  (LMEP_OPT_APPLY_TILE, tile))))
+    if persistent_ok:
+        kbs = (8,) if (nonuniform and all(p.get("x") is not None for p in problems)) else (1, 2, 4, 8)
+        for kb in kbs:
+            out.append(Choice(LMEP_F_PERSISTENT, ((LMEP_OPT_FUSE_FROZEN, 1), (LMEP_OPT_STEPS_PER_LAUNCH, kb),
+                                                  (LMEP_OPT_APPLY_TILE, 0))))
+    return out
+
+
+class _Options:
+    """Set a choice's options for the duration of a block, then restore."""
+
+    def __init__(self, choice: Choice):
+        self.choice = choice
+
+    def __enter__(self):
+        self.saved = [(o, lmep_get_option(o)) for o in _OPTIONS]
+        for o, v in self.choice.options:
+            lmep_set_option(o, v)
+        return self.choice.flags
+
+    def __exit__(self, *exc):
+        for o, v in self.saved:
+            lmep_set_option(o, v)
+        return False
+
+
+def use(choice: Choice):
+    """Context manager: `with use(choice) as flags: batch.step(..., flags)`."""
+    return _Options(choice)
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path, data):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def search(problems, measure, arch: str, cache_path: str = DEFAULT_CACHE, refresh: bool = False,
+           agree=None) -> Result:
+    """Pick the fastest candidate.  measure(choice) -> (ms_per_step, result);
+    agree(result, reference) -> bool rejects a candidate whose result differs
+    from the first (default) candidate's."""
+    key = f"{arch}|{signature(problems)}"
+    cache = _load_cache(cache_path) if cache_path else {}
+    if not refresh and key in cache:
+        ent = cache[key]
+        return Result(Choice.from_dict(ent["choice"]), float(ent["ms_per_step"]), True, ent.get("timings", {}))
+    best, best_ms, ref, timings = None, math.inf, None, {}
+    for c in candidates(problems):
+        ms, res = measure(c)
+        timings[json.dumps(c.describe(), sort_keys=True)] = ms
+        if ref is None:
+            ref = res
+        elif agree is not None and not agree(res, ref):
+            continue
+        if ms < best_ms:
+            best, best_ms = c, ms
+    if cache_path:
+        cache[key] = {"choice": best.as_dict(), "ms_per_step": best_ms, "timings": timings}
+        _store_cache(cache_path, cache)
+    return Result(best, best_ms, False, timings)
+
+
+def tune(batch, w, u0, steps: int = 20, cache_path: str = DEFAULT_CACHE, refresh: bool = False,
+         rtol: float = 1e-12) -> Result:
+    """Time every candidate on `steps` steps of this batch from u0 (weights w
+    built) with HIP events on the current stream; candidates must agree with
+    the default configuration to rtol relative to the state's max norm."""
+    import torch
+
+    def measure(c):
+        with use(c) as flags:
+            out = batch.step(w, u0, steps, flags)  # warm-up (plans, code objects)
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record()
+            out = batch.step(w, u0, steps, flags, u_out=out)
+            stop.record()
+            torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps, out.clone()
+
+    def agree(a, b):
+        scale = float(torch.max(torch.abs(b)))
+        return bool(torch.all(torch.isfinite(a))) and float(torch.max(torch.abs(a - b))) <= rtol * max(scale, 1e-300)
+
+    arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
+    return search(batch.problems, measure, arch, cache_path, refresh, agree)

@@ -1,0 +1,74 @@
+"""The autotuner's search logic without a GPU: batch signatures, the candidate
+set the library accepts, selection of the fastest agreeing candidate, and the
+JSON cache."""
+from __future__ import annotations
+
+import json
+
+import numpy as np
+
+import workloads
+from paper_2603_15964_amd import tune
+from paper_2603_15964_amd._native import (LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE, LMEP_OPT_FUSE_FROZEN,
+                                          LMEP_OPT_STEPS_PER_LAUNCH)
+
+
+def _opts(c):
+    return dict(c.options)
+
+
+def test_signature_groups_and_size_classes():
+    ps, _ = workloads.allen_cahn_batch(count=40, n_min=512, n_max=2000)
+    s1 = tune.signature(ps)
+    assert s1 == tune.signature(list(reversed(ps)))  # order does not matter
+    assert len(s1.split(";")) == len({(p["n"], p["bc"]) for p in ps})
+    p, _ = workloads.burgers(N=5000)
+    q, _ = workloads.burgers(N=7000)
+    assert tune.signature([p]) == tune.signature([q])  # same power-of-two class
+    r, _ = workloads.burgers(N=9000)
+    assert tune.signature([p]) != tune.signature([r])
+
+
+def test_candidates_follow_what_the_library_accepts():
+    frozen = [workloads.burgers(N=1000)[0]]
+    c = tune.candidates(frozen)
+    assert {_opts(x)[LMEP_OPT_FUSE_FROZEN] for x in c} == {0, 1}
+    assert not any(x.flags & LMEP_F_PERSISTENT for x in c)
+    stat = [workloads.kdv(N=4096)[0]]
+    kbs = {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in tune.candidates(stat) if x.flags & LMEP_F_PERSISTENT}
+    assert kbs == {1, 2, 4, 8}
+    upwind = [workloads.burgers_upwind(N=1000)[0]]
+    assert not any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(upwind))
+    cheb = [workloads.allen_cahn_chebyshev()[0]]
+    cc = tune.candidates(cheb)
+    assert sum(1 for x in cc if x.flags & LMEP_F_PERSISTENT) == 1
+    assert 64 in {_opts(x)[LMEP_OPT_APPLY_TILE] for x in cc}
+    big = [dict(cheb[0], N=600, x=workloads.chebyshev(600))]
+    assert not any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(big))
+
+
+def test_search_picks_fastest_agreeing_and_caches(tmp_path):
+    ps = [workloads.kdv(N=4096)[0]]
+    cands = tune.candidates(ps)
+    times = {c: 10.0 - i for i, c in enumerate(cands)}  # the last is fastest ...
+    bad = cands[-1]                                       # ... but disagrees
+    calls = []
+
+    def measure(c):
+        calls.append(c)
+        return times[c], (np.ones(3) * (2.0 if c == bad else 1.0))
+
+    def agree(a, b):
+        return np.array_equal(a, b)
+
+    path = str(tmp_path / "tune.json")
+    r = tune.search(ps, measure, "gfx950", path, agree=agree)
+    assert not r.from_cache and r.choice == cands[-2] and len(calls) == len(cands)
+    data = json.load(open(path))
+    assert len(data) == 1 and list(data)[0].startswith("gfx950|")
+    r2 = tune.search(ps, measure, "gfx950", path, agree=agree)
+    assert r2.from_cache and r2.choice == r.choice and len(calls) == len(cands)
+    r3 = tune.search(ps, measure, "gfx950", path, refresh=True, agree=agree)
+    assert not r3.from_cache and len(calls) == 2 * len(cands)
+    r4 = tune.search(ps, measure, "gfx942", path, agree=agree)  # another architecture: its own entry
+    assert not r4.from_cache and len(json.load(open(path))) == 2
