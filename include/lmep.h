@@ -79,8 +79,12 @@ enum { LMEP_NL_NONE = 0, LMEP_NL_BURGERS_FROZEN = 1, LMEP_NL_KDV = 2, LMEP_NL_AL
  * one-sided pure-advection update is stable for Courant numbers |a| dt / h in
  * [(n-3)/2, (n+1)/2] (and at the integers, where it is an exact shift); in
  * FP64 its edge-row exponentials lose accuracy as n and the Courant number
- * grow (weights agree with the exact ones to ~1e-12 up to n = 9 at Courant
- * 2.5, n = 7 throughout its stable band).  UPWIND is supported for LINEAR,
+ * grow.  Stationary tables are balanced (a power-of-two diagonal similarity)
+ * before the exponential: their rows agree with the exact ones to ~1e-12 up
+ * to n = 9 (Courant <= 3.5 with diffusion), 5e-11 / 1e-9 / 5e-8 at n = 11 /
+ * 13 / 15.
+ * Frozen-velocity weights (rebuilt every step) are not balanced: ~1e-12 for
+ * n = 7 across its band.  UPWIND is supported for LINEAR,
  * ETD1 and ETD2RK with the one-step kernels; ETDRK4, LMEP_F_PERSISTENT and
  * the reverse step return LMEP_ERR_UNSUPPORTED. */
 enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };

@@ -85,6 +85,45 @@ __device__ __forceinline__ double column(const double (&X)[M], int col) {
     return v;
 }
 
+// Power-of-two balancing of a row matrix (lane i holds row i): B = D^-1 A D
+// with D = diag(d) chosen to equalise each row's and column's off-diagonal
+// 1-norms (Parlett and Reinsch 1969; LAPACK's gebal without permutations).
+// Scaling by powers of two is exact and exp(A) = D exp(B) D^-1.  Returns this
+// lane's d.  Used for the stationary tables of one-sided windows, whose edge
+// rows make the local matrix badly scaled: there it cuts the squarings and
+// the FP64 error of the harvested row by one to three orders of magnitude.
+template <int M>
+__device__ __forceinline__ double balance_rows(double (&A)[M], int lane) {
+    double d = 1.0;
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        bool changed = false;
+        sfor<M>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            const double c = row_sum16(lane != I ? fabs(A[I]) : 0.0);  // column I, off-diagonal
+            double rs = 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) rs += (j != lane) ? fabs(A[j]) : 0.0;
+            const double r = bcast<I>(rs);  // row I, off-diagonal
+            if (c != 0.0 && r != 0.0) {
+                double f = 1.0, cc = c;
+                while (cc < 0.5 * r) { f *= 2.0; cc *= 4.0; }
+                while (cc >= 2.0 * r) { f *= 0.5; cc *= 0.25; }
+                if ((cc + r) / f < 0.95 * (c + r)) {
+                    changed = true;
+                    if (lane == I) {
+#pragma unroll
+                        for (int j = 0; j < M; ++j) A[j] /= f;
+                        d *= f;
+                    }
+                    A[I] *= f;
+                }
+            }
+        });
+        if (!changed) break;
+    }
+    return d;
+}
+
 // (X * X)[:, col] given the column v = X[:, col] distributed over the lanes.
 template <int M>
 __device__ __forceinline__ double square_column(const double (&X)[M], double v) {
@@ -141,6 +180,11 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
     if constexpr (PP >= 1) A[NN] = (lane == r) ? dt : 0.0;
     if constexpr (PP >= 2) A[NN + 1] = (lane == NN) ? dt : 0.0;
     if constexpr (PP >= 3) A[NN + 2] = (lane == NN + 1) ? dt : 0.0;
+    // balancing costs about as much as the exponential here, so it is kept to
+    // stationary tables (built once); frozen-velocity one-sided windows are
+    // stable only for small n, where the unbalanced FP64 rows are accurate
+    const bool balanced = P.window == WIN_UPWIND && !frozen;
+    const double dbal = balanced ? balance_rows(A, lane) : 1.0;
 
     double rs = 0.0;
 #pragma unroll
@@ -180,6 +224,12 @@ __global__ __launch_bounds__(256) void build_pade_kernel(const DevProb* __restri
         if constexpr (PP >= 1) w1 = square_column(X, w1);
         if constexpr (PP >= 2) w2 = square_column(X, w2);
         if constexpr (PP >= 3) w3 = square_column(X, w3);
+    }
+    if (balanced) {  // entry (k, j) of exp(Mt) is d_k exp(B)[k][j] / d_j
+        w0 *= dbal / __shfl(dbal, r, 16);
+        if constexpr (PP >= 1) w1 *= dbal / bcast<NN>(dbal);
+        if constexpr (PP >= 2) w2 *= dbal / bcast<NN + 1>(dbal);
+        if constexpr (PP >= 3) w3 *= dbal / bcast<NN + 2>(dbal);
     }
 
     if (stats && lane == 0) {  // profiling only: matrices built and squarings done

@@ -3,10 +3,11 @@ oracle (which carries these windows in binary128).
 
 Tolerances.  Harvested rows: 1e-12 relative per row, and one step: 1e-13
 relative, where FP64 scaling-and-squaring reaches them on one-sided rows:
-n <= 7 across the stable band [(n-3)/2, (n+1)/2], n = 9 up to Courant 2.5.
-Beyond that the one-sided rows' exponentials are too ill-conditioned for FP64
-(their series cancel by up to 1e10 for n = 15); there the test checks the
-documented error envelope instead.  Multi-step runs: 1e-10.
+n <= 7 across the stable band [(n-3)/2, (n+1)/2], n = 9 up to Courant 3.5
+(stationary tables are balanced before the exponential).  Beyond that the
+one-sided rows' exponentials are too ill-conditioned for FP64 (their series
+cancel by up to 1e10 for n = 15); there the test checks the documented error
+envelope instead.  Multi-step runs: 1e-10.
 """
 from __future__ import annotations
 
@@ -60,7 +61,7 @@ def _gpu_run(problems, states, steps, flags=0):
 
 
 # ------------------------------------------------------------ harvest ----
-ACCURATE = [(3, 2.0), (5, 2.5), (5, 3.0), (7, 2.0), (7, 3.5), (7, 4.0), (9, 2.5)]
+ACCURATE = [(3, 2.0), (5, 2.5), (5, 3.0), (7, 2.0), (7, 3.5), (7, 4.0), (9, 2.5), (9, 3.5)]
 
 
 @pytest.mark.parametrize("n,cfl", ACCURATE)
@@ -81,7 +82,8 @@ def test_upwind_harvest_rows(n, cfl, scheme):
             assert err <= 1e-12, (sgn, kind, err)
 
 
-ENVELOPE = {9: 1e-9, 11: 1e-7, 13: 1e-4, 15: 1e-3}
+# measured on MI355X (balanced tables): 1.4e-12, 4.7e-11, 8.1e-10, 4.9e-8
+ENVELOPE = {9: 2e-11, 11: 1e-9, 13: 2e-8, 15: 1e-6}
 
 
 @pytest.mark.parametrize("n", sorted(ENVELOPE))
