@@ -131,6 +131,34 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def plain_forward(problems, states, steps, max_instances=None):
+    """The plain path the batched and adjoint paths are compared with: the
+    single-instance forward, each instance on its own (one lmep_step call per
+    instance, per-step eager launches, default tiles), one after another.
+    Weights of stationary instances are built before the clock starts.
+    Returns (node-steps/s, instances timed)."""
+    import torch
+    import paper_2603_15964_amd as lmep
+    k = len(problems) if max_instances is None else min(len(problems), max_instances)
+    runs = []
+    for p, u in zip(problems[:k], states[:k]):
+        b = lmep.Batch([p], device="cuda:0")
+        w = b.empty_weights()
+        u0 = b.pack([u])
+        if p.get("nonlin") != "burgers_frozen":
+            b.build_weights(w, u0)
+        runs.append((b, w, u0, b.empty_state()))
+    for b, w, u0, out in runs:  # warm-up: plans, code objects
+        b.step(w, u0, 1, 0, u_out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, w, u0, out in runs:
+        b.step(w, u0, steps, 0, u_out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return sum(int(p["N"]) for p in problems[:k]) * steps / el, k
+
+
 def bench_adjoint(problems, states, steps, every=50):
     """Forward with checkpoints + reverse through lmep_adjoint_step; returns
     (seconds, node-steps) with node-steps = nodes x steps."""
@@ -258,6 +286,10 @@ def main():
                "config": {"workload": desc, "instances": len(problems), "nodes": sum(p["N"] for p in problems),
                           "checkpoint_every": 50},
                "roofline": adjoint_roofline(problems, states)}
+        pv, pk = plain_forward(problems, states, min(args.steps, 50))
+        out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,
+                        "kind": "single-instance forward only, instances one at a time, per-step eager launches",
+                        "ratio": out["value"] / pv}
         print(json.dumps(out), flush=True)
         return
     batch = lmep.Batch(problems, device=dev)
@@ -402,6 +434,11 @@ def main():
         "roofline": roof,
         "detail": extra,
     }
+    if len(problems) > 1:
+        pv, pk = plain_forward(problems, states, min(args.steps, 20))
+        out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,
+                        "kind": "single-instance forward, instances one at a time, per-step eager launches",
+                        "ratio": value / pv}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problems[0], states[0])
     print(json.dumps(out), flush=True)
