@@ -244,13 +244,13 @@ __global__ __launch_bounds__(kWaveThreads) void build_wide_kernel(const DevProb*
     }
     __syncthreads();
 
-    // s squarings, alternating between W2 and W1
-    double* X = W2;
-    double* Y = W1;
+    // s squarings, alternating between W2 and W1 (chosen by parity, so the
+    // pointers stay plain offsets into lds and keep their address space)
     for (int q = 0; q < s; ++q) {
-        mm(X, X, Y, m, ld, lane);
-        double* t = X; X = Y; Y = t;
+        if (q & 1) mm(W1, W1, W2, m, ld, lane);
+        else mm(W2, W2, W1, m, ld, lane);
     }
+    const double* X = lds + ((s & 1) ? 4 : 5) * sz;  // W1 or W2
     // exp(Mt) = D exp(B) D^-1: entry (k, j) is dsc[k] X[k][j] / dsc[j]
     if (lane < n) {
         double* __restrict__ wb = w + P.weight_off;

@@ -211,12 +211,15 @@ __global__ __launch_bounds__(NT) void stepk_rk4_kernel(const DevProb* __restrict
         __syncthreads();
     };
 
-    double* buf[S::NBUF];
+    // the arrays rotate as offsets into lds, not as stored pointers: pointers
+    // kept in an array and reassigned across steps lose their LDS address
+    // space and turn every access into a flat one
+    int bo[S::NBUF];
 #pragma unroll
-    for (int b = 0; b < S::NBUF; ++b) buf[b] = lds + b * LP;
+    for (int b = 0; b < S::NBUF; ++b) bo[b] = b * LP;
 
     for (int st = 0; st < ksteps; ++st) {
-        double* U = buf[0];
+        double* U = lds + bo[0];
         if constexpr (!S::HAS_N) {
             // no nonlinearity: u+ = E u
             double o[V];
@@ -224,13 +227,13 @@ __global__ __launch_bounds__(NT) void stepk_rk4_kernel(const DevProb* __restrict
             for (int v = 0; v < V; ++v) o[v] = 0.0;
             add_term(o, 2, [&](int s) { return U[s]; });
 #pragma unroll
-            for (int v = 0; v < V; ++v) buf[1][oslot(v)] = o[v];
-            finish(buf[1], [&](int rr, int k, int s) { return swk(2, rr, k) * U[s]; });
-            double* t = buf[0];
-            buf[0] = buf[1];
-            buf[1] = t;
+            for (int v = 0; v < V; ++v) lds[bo[1] + oslot(v)] = o[v];
+            finish(lds + bo[1], [&](int rr, int k, int s) { return swk(2, rr, k) * U[s]; });
+            const int t = bo[0];
+            bo[0] = bo[1];
+            bo[1] = t;
         } else if constexpr (!S::DERIV) {
-            double *A1 = buf[1], *A2 = buf[2], *A3 = buf[3];
+            double *A1 = lds + bo[1], *A2 = lds + bo[2], *A3 = lds + bo[3];
             // a = E2 u + P2 N(u)
             half_stage(U, [&](int s) { return nval(U[s]); }, A1);
             finish(A1, [&](int rr, int k, int s) { return swk(0, rr, k) * U[s] + swk(1, rr, k) * nval(U[s]); });
@@ -260,12 +263,13 @@ __global__ __launch_bounds__(NT) void stepk_rk4_kernel(const DevProb* __restrict
                 return swk(2, rr, k) * U[s] + swk(3, rr, k) * nval(U[s]) + swk(4, rr, k) * A1[s] +
                        swk(5, rr, k) * nval(A3[s]);
             });
-            buf[0] = A2;
-            buf[1] = U;
-            buf[2] = A1;
-            buf[3] = A3;
+            const int o0 = bo[0], o1 = bo[1], o2 = bo[2], o3 = bo[3];
+            bo[0] = o2;  // u+ (in A2)
+            bo[1] = o0;  // old u
+            bo[2] = o1;  // A1
+            bo[3] = o3;  // A3
         } else {
-            double *NU = buf[1], *A1 = buf[2], *NA = buf[3], *B1 = buf[4], *NB = buf[5];
+            double *NU = lds + bo[1], *A1 = lds + bo[2], *NA = lds + bo[3], *B1 = lds + bo[4], *NB = lds + bo[5];
             deriv_N(U, NU);
             finish_N(U, NU);
             // a = E2 u + P2 N(u)
@@ -299,15 +303,16 @@ __global__ __launch_bounds__(NT) void stepk_rk4_kernel(const DevProb* __restrict
             finish(NB, [&](int rr, int k, int s) {
                 return swk(2, rr, k) * U[s] + swk(3, rr, k) * NU[s] + swk(4, rr, k) * NA[s] + swk(5, rr, k) * A1[s];
             });
-            buf[0] = NB;
-            buf[5] = U;
+            const int o0 = bo[0];
+            bo[0] = bo[5];  // u+ (in N(b))
+            bo[5] = o0;
         }
     }
 
     double* __restrict__ out = u_out + P.state_off;
     for (int q = tid; q < S::TILE; q += NT) {
         const int64_t i = t0 + q;
-        if (i < N) out[i] = buf[0][phys(q + S::HALO)];
+        if (i < N) out[i] = lds[bo[0] + phys(q + S::HALO)];
     }
 }
 
