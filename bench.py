@@ -34,6 +34,24 @@ def pade_flops(m: int, matrices: int, squarings: int) -> float:
     return matrices * (2.0 * 6 * m ** 3 + 8.0 * m ** 3 / 3.0) + squarings * 2.0 * m ** 3
 
 
+def taylor_flops(n: int, fused: bool) -> float:
+    """Algorithmic flops of one node of the finite-Taylor build (multiply-add =
+    2), in the unshifted, dispersion-free case: the moment recursion (orders
+    1..n-1, order k+1 having k+1 entries, one multiply and, from order 2 on, one
+    multiply-add each, plus the scaled diffusion coefficient per order), the
+    two moment sums per order (exponential and phi1), the contraction with the
+    table rows (2 n multiply-adds per order), the dt scaling of W1, and with
+    fusion the derivative at the node (n multiplies + n multiply-adds) and the
+    stencil sum W0.u + W1.N with N_j = -g (u_j - u_i) d_j (7 per position)."""
+    rec = 1.5 * n * (n - 1) + n - 3
+    sums = 1.5 * (n - 1) * (n - 2) + (n - 1)
+    con = 4.0 * n * (n - 1)
+    f = rec + sums + con + n
+    if fused:
+        f += 3.0 * n + 7.0 * n
+    return f
+
+
 def stationary_flops(p: dict) -> float:
     """Algorithmic flops of one node-step of the banded apply with stationary
     weights (multiply-add = 2): W0.u (+ W1.N) over the n-window, N itself
@@ -124,6 +142,11 @@ def make_workload(name: str):
     if name == "advection_diffusion":
         p, u0 = workloads.advection_diffusion()
         return [p], [u0], "periodic advection-diffusion N=256 n=5 CFL 2, LINEAR"
+    if name == "burgers_batch":
+        p, pt, u0s = workloads.burgers_adjoint_batch()
+        return ([p] * len(u0s), u0s,
+                "64 Burgers trajectories N=262144 n=9 Dirichlet (the adjoint workload's forward), frozen-velocity "
+                "ETD1, weights rebuilt every step")
     if name == "burgers_adjoint":
         p, pt, u0s = workloads.burgers_adjoint_batch()
         return ([p] * len(u0s), u0s,
@@ -255,6 +278,9 @@ def main():
     ap.add_argument("--steps-per-launch", type=int, default=8, choices=(1, 2, 4, 8))
     ap.add_argument("--tune", action="store_true",
                     help="let the autotuner pick fusion / steps per launch / apply tile (cached per GPU and shape)")
+    ap.add_argument("--exp-method", choices=("auto", "pade"), default="auto",
+                    help="exponential of the frozen-velocity rebuild: finite Taylor series where it applies (auto) "
+                         "or Pade scaling-and-squaring everywhere")
     ap.add_argument("--skip-count", action="store_true",
                     help="skip the squaring-count pass (its atomics would show up in a kernel trace)")
     args = ap.parse_args()
@@ -276,6 +302,8 @@ def main():
 
     problems, states, desc = make_workload(args.workload)
     dev = "cuda:0"
+    lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD,
+                         lmep.LMEP_EXP_PADE if args.exp_method == "pade" else lmep.LMEP_EXP_AUTO)
     if args.workload == "burgers_adjoint":
         bench_adjoint(problems, states, max(1, args.warmup), every=max(1, args.warmup))  # warm-up
         secs, node_steps = bench_adjoint(problems, states, args.steps)
@@ -345,14 +373,19 @@ def main():
     roof = None
     extra = {"gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3}
     apply_bytes = {"burgers": 128.0, "burgers_upwind": 128.0, "kdv": 16.0, "allen_cahn_batch": 16.0, "advection_diffusion": 16.0}
+    taylor = frozen and args.exp_method == "auto" and all(p.get("react", 0.0) == 0.0 for p in problems)
     if frozen and prof["build_launches"] > 0 and prof["matrices"] > 0:
         p0 = problems[0]
         m = p0["n"] + {"linear": 0, "etd1": 1, "etd2rk": 2}[p0["scheme"]]
-        flops = pade_flops(m, prof["matrices"], prof["squarings"])
+        fused = lmep.lmep_get_option(lmep.LMEP_OPT_FUSE_FROZEN) == 1
+        if taylor:
+            flops = taylor_flops(p0["n"], fused) * prof["matrices"]
+            kname = f"build_taylor_kernel<{p0['n']},{'true' if fused else 'false'}>"
+        else:
+            flops = pade_flops(m, prof["matrices"], prof["squarings"])
+            kname = f"build_pade_kernel<{p0['n']},{m - p0['n']},{'true' if fused else 'false'}>"
         build_s = prof["build_ms"] / 1e3
         achieved = flops / build_s / 1e12
-        fused = lmep.lmep_get_option(lmep.LMEP_OPT_FUSE_FROZEN) == 1
-        kname = f"build_pade_kernel<{p0['n']},{m - p0['n']},{'true' if fused else 'false'}>"
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname], args.workload),
                 "kernel": kname,
@@ -430,10 +463,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "instances": batch.count, "nodes": batch.state_size,
                    "graph": bool(args.graph), "steps_per_launch": kb,
+                   "exponential": ("finite Taylor" if taylor else "Pade") if frozen else "Pade (weights built once)",
                    "tuned": (dict(tuned.choice.describe(), from_cache=tuned.from_cache) if tuned else None)},
         "roofline": roof,
         "detail": extra,
     }
+    if taylor:
+        # the same steps through the Pade build, for comparison
+        lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_PADE)
+        batch.step(w, ua, 2, flags, u_out=ub)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        batch.step(w, ua, args.steps, flags, u_out=ub)
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t1
+        lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_AUTO)
+        out["pade_path"] = {"value": node_steps / pw, "unit": "node-steps/s",
+                            "kind": "same steps, frozen-velocity weights by Pade scaling-and-squaring",
+                            "ratio": value / (node_steps / pw)}
     if len(problems) > 1:
         pv, pk = plain_forward(problems, states, min(args.steps, 20))
         out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,

@@ -162,8 +162,12 @@ size_t lmep_scratch_bytes(const lmep_problem* prob, int32_t count, int32_t op);
 
 /* Build the harvested weights of `count` instances into d_w (steps a1-a6:
  * stencil, local operator, augmented matrix, FP64 Pade scaling-and-squaring
- * exponential per local matrix, harvest).  d_u is read only for
- * BURGERS_FROZEN instances (their frozen velocity) and may be NULL otherwise. */
+ * exponential per local matrix, harvest).  BURGERS_FROZEN instances on uniform
+ * grids with react = 0 take, by default, the same exponential as an exact
+ * finite Taylor series instead (the local operator is a polynomial in the
+ * nilpotent first-derivative matrix of the window, Sec. 2.1 / Sec. 3.1; see
+ * LMEP_OPT_EXP_METHOD).  d_u is read only for BURGERS_FROZEN instances (their
+ * frozen velocity) and may be NULL otherwise. */
 int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_u,
                        double* d_w, void* d_scratch, size_t scratch_bytes, void* hip_stream);
 
@@ -194,7 +198,8 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
  * launches, from HIP events recorded around each launch on the call's stream),
  * and, from the last LMEP_F_COUNT call, the number of local matrices
  * exponentiated and the total number of squarings their scaling-and-squaring
- * took.  Any pointer may be NULL. */
+ * took (a node built by the finite Taylor series counts as one matrix with no
+ * squarings).  Any pointer may be NULL. */
 int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_ms,
                       int32_t* apply_launches, int64_t* matrices, int64_t* squarings);
 
@@ -228,12 +233,31 @@ const char* lmep_last_error(void);
  *                             groups, 1024 otherwise); 256 or 1024 force that
  *                             tile for every one-step group (non-uniform
  *                             groups also take 64).  Results do not depend on it.
+ *  LMEP_OPT_EXP_METHOD        how the per-step weights of BURGERS_FROZEN
+ *                             instances are exponentiated.  LMEP_EXP_AUTO
+ *                             (default): on a uniform grid with react = 0 the
+ *                             window operator dt L is a polynomial of degree
+ *                             <= 3 in the window's first-derivative matrix D,
+ *                             and D^n = 0, so e^{dt L} and dt phi1(dt L) are
+ *                             exact polynomials of degree n - 1 in D; their
+ *                             harvested rows are formed from the moments of
+ *                             the polynomial (one thread per node, O(n^2)
+ *                             work) with no Pade approximant or squaring.
+ *                             The expansion is taken about the window node
+ *                             nearest the middle of the node's translation
+ *                             range, which keeps its FP64 error at or below
+ *                             the Pade path's.  Other instances: Pade.
+ *                             LMEP_EXP_PADE: Pade scaling-and-squaring for
+ *                             every instance.  The two agree to rounding.
  * lmep_set_option returns LMEP_OK or LMEP_ERR_ARG (unknown option or value);
  * lmep_get_option returns the value or LMEP_ERR_ARG. */
 #define LMEP_OPT_STEPS_PER_LAUNCH 1
 #define LMEP_OPT_PROFILE_ADJOINT 2
 #define LMEP_OPT_FUSE_FROZEN 3
 #define LMEP_OPT_APPLY_TILE 4
+#define LMEP_OPT_EXP_METHOD 5
+#define LMEP_EXP_AUTO 0
+#define LMEP_EXP_PADE 1
 int lmep_set_option(int32_t option, int32_t value);
 int32_t lmep_get_option(int32_t option);
 

@@ -1,0 +1,258 @@
+// Frozen-velocity weight build by a finite Taylor series (steps a3-a6 for the
+// frozen-velocity Burgers operator under ETD1; with FUSE also a7-a8).
+//
+// Why a finite series is exact.  On a uniform grid the window's derivative
+// matrices are those of its interpolating polynomial (Sec. 2.1): with D the
+// first-derivative matrix on unit spacing, D^(2) = D^2, D^(3) = D^3, and
+// D^n = 0 because n derivatives annihilate a polynomial of degree n - 1.  So
+// dt L = q(D) with q(x) = a x + b x^2 + e x^3 (a = -c dt/h, b = nu dt/h^2,
+// e = -delta dt/h^3; no reaction term), every function of dt L is a
+// polynomial of degree n - 1 in D, and the augmented matrix of Sec. 3.1 is
+// nilpotent as well: its exponential is a finite sum, no Pade approximant and
+// no squarings are needed.  With
+//     e^{theta q(x)} = sum_k M_k(theta) x^k / k!,
+//     M_0 = 1,  M_{k+1} = theta a M_k + 2 theta b k M_{k-1} + 3 theta e k (k-1) M_{k-2}
+// (from d/dx e^{theta q} = theta q' e^{theta q}), the harvested rows are
+//     row r of e^{dt L}        = sum_k M_k(1) T_k[r],
+//     row r of dt phi1(dt L)   = dt sum_k (int_0^1 M_k(theta) dtheta) T_k[r],
+// where T_k[r][j] = (D^k)[r][j] / k! is the coefficient of y^k in l_j(x_r + y)
+// for the window's Lagrange basis polynomial l_j (a per-device table).  M_k is
+// a polynomial in theta, M_k = sum_m mu[k][m] theta^m, so the integral is
+// sum_m mu[k][m] / (m + 1).  This is O(n^2) work per node against the
+// O(n^3 log) of a Pade exponential of the (n+1) x (n+1) augmented matrix.
+//
+// Conditioning.  e^{theta a D} translates a polynomial by theta a, so the
+// sums above add large terms of both signs when |a| spans several nodes.  As
+// e^{s D} is an exact translation by s, the same weights follow from the
+// expansion about node r' = r + s with theta a replaced by theta a - s in the
+// moment recursion:
+//     mu[k+1][m] = a mu[k][m-1] - s mu[k][m] + 2 b k mu[k-1][m-1] + 3 e k (k-1) mu[k-2][m-1],
+// taking T_k[r'] in place of T_k[r].  s is the integer nearest a / 2 (the
+// middle of the translation range [0, a] that theta sweeps), kept inside the
+// window.  Within a wavefront whose nodes share the harvest row (every
+// interior wavefront), one row and one shift serve all lanes, so the table row
+// is read through the scalar unit; other wavefronts use per-lane rows.
+//
+// Layout: one thread per node, kTaylorTile consecutive nodes of one instance
+// per block.  With FUSE the block first stages u and the frozen-velocity
+// derivative (du/dx)_j (from each position's own window, as in the Pade
+// kernel's fused step) for its nodes and a halo of n - 1 positions on each side
+// in LDS; each node then forms u+_i = sum_j W0[j] u_j + W1[j] N_j with
+// N_j = -g (u_j - u_i) (du/dx)_j over its window, and the weights never leave
+// registers.  Without FUSE the weights are written in the per-node layout.
+#include "lmep_device.hpp"
+
+namespace lmep {
+namespace {
+
+// Weights of one node from table row T (T[k * kMaxN + j] = T_k[r'][j]).
+// SHIFT: s != 0; DISP: e != 0.
+template <int NN, bool SHIFT, bool DISP>
+__device__ __forceinline__ void taylor_weights(double a, double b, double e, double s,
+                                               const double* __restrict__ T, double (&W0)[NN], double (&W1)[NN]) {
+    double m2[NN], m1[NN], m0[NN];  // mu[k-2][.], mu[k-1][.], mu[k][.]
+#pragma unroll
+    for (int m = 0; m < NN; ++m) {
+        m2[m] = 0.0;
+        m1[m] = 0.0;
+        m0[m] = 0.0;
+    }
+    m0[0] = 1.0;
+#pragma unroll
+    for (int j = 0; j < NN; ++j) {  // order 0: M_0 = 1, its integral 1
+        const double t = T[j];
+        W0[j] = t;
+        W1[j] = t;
+    }
+#pragma unroll
+    for (int k = 0; k + 1 < NN; ++k) {
+        const double bk = (double)(2 * k) * b;
+        const double ek = (double)(3 * k * (k - 1)) * e;
+        double nx[NN];
+#pragma unroll
+        for (int m = 0; m < NN; ++m) {
+            double v = 0.0;
+            if (m <= k + 1) {
+                if (SHIFT && m <= k) v = -s * m0[m];
+                if (m >= 1) {
+                    v = fma(a, m0[m - 1], v);
+                    if (k >= 1) v = fma(bk, m1[m - 1], v);
+                    if (DISP && k >= 2) v = fma(ek, m2[m - 1], v);
+                }
+            }
+            nx[m] = v;
+        }
+        double E = -0.0, F = -0.0;  // -0.0: the first sum term needs no add
+#pragma unroll
+        for (int m = 0; m < NN; ++m) {
+            m2[m] = m1[m];
+            m1[m] = m0[m];
+            m0[m] = nx[m];
+            if (m <= k + 1 && (SHIFT || m >= 1)) {
+                E += nx[m];
+                F = fma(nx[m], 1.0 / (double)(m + 1), F);
+            }
+        }
+        const double* __restrict__ Tk = T + (k + 1) * kMaxN;
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            const double t = Tk[j];
+            W0[j] = fma(E, t, W0[j]);
+            W1[j] = fma(F, t, W1[j]);
+        }
+    }
+}
+
+template <int NN, bool SHIFT>
+__device__ __forceinline__ void taylor_weights_d(bool disp, double a, double b, double e, double s,
+                                                 const double* __restrict__ T, double (&W0)[NN], double (&W1)[NN]) {
+    if (disp)
+        taylor_weights<NN, SHIFT, true>(a, b, e, s, T, W0, W1);
+    else
+        taylor_weights<NN, SHIFT, false>(a, b, e, s, T, W0, W1);
+}
+
+template <int NN, bool FUSE>
+__global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb* __restrict__ probs, int nprob,
+                                                                   const double* __restrict__ fd,
+                                                                   const double* __restrict__ taylor,
+                                                                   const double* __restrict__ u,
+                                                                   double* __restrict__ w,
+                                                                   unsigned long long* __restrict__ stats,
+                                                                   double* __restrict__ u_out) {
+    constexpr int R = (NN - 1) / 2;
+    constexpr int H = NN - 1;  // staged halo: a one-sided window reaches n - 1 positions
+    constexpr int S = kTaylorTile + 2 * H;
+    __shared__ double su[FUSE ? S : 1], sd[FUSE ? S : 1];
+
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_instance(probs, nprob, tile)];
+    const int64_t N = P.N;
+    const int64_t node0 = (tile - P.item_begin) * kTaylorTile;
+    const int bc = P.bc;
+    const double* __restrict__ us = u + P.state_off;
+    const double ih = 1.0 / P.h, g = P.nl_coef;
+    const int tid = threadIdx.x;
+    if (stats && tid == 0) atomicAdd(stats, (unsigned long long)(N - node0 < kTaylorTile ? N - node0 : kTaylorTile));
+
+    if constexpr (FUSE) {
+        // positions node0 - H .. min(node0 + tile, N) - 1 + H; on Dirichlet grids
+        // only those inside the grid (windows never leave it)
+        const int64_t vend = (node0 + kTaylorTile < N ? node0 + kTaylorTile : N) + H;
+        for (int sl = tid; sl < S; sl += kTaylorTile) {
+            const int64_t v = node0 - H + sl;
+            double uv = 0.0, dv = 0.0;
+            if (v < vend && (bc != BC_DIRICHLET || (v >= 0 && v < N))) {
+                const int64_t j = map_index(v, N, bc);
+                uv = us[j];
+                const int64_t oj = window_offset(j, N, NN, bc, P.window, P.c + g * uv);
+                if (oj == -R && j >= R && j + R <= N - 1) {
+#pragma unroll
+                    for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, R, l)] * ih) * us[j - R + l];
+                } else if (j + oj >= 0 && j + oj + NN - 1 <= N - 1) {
+                    const int rj = (int)(-oj);
+#pragma unroll
+                    for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, rj, l)] * ih) * us[j + oj + l];
+                } else {
+                    const int rj = (int)(-oj);
+#pragma unroll
+                    for (int l = 0; l < NN; ++l)
+                        dv += (fd[fd_index(NN, 0, rj, l)] * ih) * us[map_index(j + oj + l, N, bc)];
+                }
+            }
+            su[sl] = uv;
+            sd[sl] = dv;
+        }
+        __syncthreads();
+    }
+
+    const int64_t node = node0 + tid;
+    const bool active = node < N;
+    // lane 0 holds the wavefront's first node: past the end, so is every lane
+    if (__builtin_amdgcn_readfirstlane(active ? 1 : 0) == 0) return;
+    const int64_t nd = active ? node : N - 1;  // idle lanes repeat the last node; their results are dropped
+    const double ui = FUSE ? su[tid + H] : us[nd];
+    const double ceff = P.c + g * ui;
+    const int r = (int)(-window_offset(nd, N, NN, bc, P.window, ceff));
+    const double dt = P.dt;
+    const double a = -ceff * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
+    const bool disp = P.delta != 0.0;
+    const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
+    const int sh = (int)rint(half);
+
+    double W0[NN], W1[NN];
+    const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
+    const int r0 = __builtin_amdgcn_readfirstlane(r);
+    if (__ballot(active && r != r0) == 0) {
+        const int s0 = __builtin_amdgcn_readfirstlane(sh);
+        int rp = r0 + s0;
+        rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
+        const double* __restrict__ T = tb + rp * (kMaxN * kMaxN);
+        if (rp == r0)
+            taylor_weights_d<NN, false>(disp, a, b, e, 0.0, T, W0, W1);
+        else
+            taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp - r0), T, W0, W1);
+    } else {
+        int rp = r + sh;
+        rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
+        taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp - r), tb + rp * (kMaxN * kMaxN), W0, W1);
+    }
+#pragma unroll
+    for (int j = 0; j < NN; ++j) W1[j] *= dt;
+
+    if constexpr (FUSE) {
+        const int base = tid + H - r;  // slot of window position 0
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            const double uj = su[base + j];
+            const double Nj = -g * (uj - ui) * sd[base + j];
+            acc = fma(W0[j], uj, acc);
+            acc = fma(W1[j], Nj, acc);
+        }
+        if (active) {
+            const bool fixed = bc == BC_DIRICHLET && (node == 0 || node == N - 1);
+            u_out[P.state_off + node] = fixed ? (node == 0 ? P.bc_left : P.bc_right) : acc;
+        }
+    } else if (active) {
+        double* __restrict__ wb = w + P.weight_off;
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            wb[(int64_t)j * N + node] = W0[j];
+            wb[(int64_t)(NN + j) * N + node] = W1[j];
+        }
+    }
+}
+
+template <int NN>
+hipError_t go_taylor(const DevProb* d_probs, int nprob, int64_t tiles, const double* fd, const double* taylor,
+                     const double* d_u, double* d_w, unsigned long long* stats, double* d_u_out, hipStream_t stream) {
+    if (d_u_out)
+        hipLaunchKernelGGL((build_taylor_kernel<NN, true>), dim3((unsigned)tiles), dim3(kTaylorTile), 0, stream,
+                           d_probs, nprob, fd, taylor, d_u, d_w, stats, d_u_out);
+    else
+        hipLaunchKernelGGL((build_taylor_kernel<NN, false>), dim3((unsigned)tiles), dim3(kTaylorTile), 0, stream,
+                           d_probs, nprob, fd, taylor, d_u, d_w, stats, d_u_out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd,
+                               const double* taylor, const double* d_u, double* d_w, unsigned long long* stats,
+                               hipStream_t stream, double* d_u_out) {
+    if (tiles <= 0) return hipSuccess;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    switch (n) {
+        case 3: return go_taylor<3>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 5: return go_taylor<5>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 7: return go_taylor<7>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 9: return go_taylor<9>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 11: return go_taylor<11>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 13: return go_taylor<13>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 15: return go_taylor<15>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lmep

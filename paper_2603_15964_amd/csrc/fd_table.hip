@@ -5,6 +5,11 @@
 // size serves every node: weights on the centred integer nodes
 // x_k = k - (n-1)/2, scaled by h^-d where they are used.  The table is a
 // static device array filled once per device by fd_table_kernel.
+//
+// A second table serves the finite-Taylor build (build_taylor.hip): the
+// derivatives of every order 0..n-1 of the window's Lagrange basis
+// polynomials at each window node, divided by the order's factorial, i.e. the
+// rows of D1^k / k! (D1 the unit-spacing first-derivative matrix).
 #include <mutex>
 
 #include "lmep_device.hpp"
@@ -13,17 +18,19 @@ namespace lmep {
 namespace {
 
 __device__ double g_fd_table[kFdTableDoubles];
+__device__ double g_taylor_table[kTaylorTableDoubles];
 
 // Fornberg (1988), "Generation of finite difference formulas on arbitrarily
 // spaced grids": weights c[j][d] of node j for the d-th derivative at z,
-// built up one node at a time; derivatives up to order 3.
-__device__ void fornberg_weights(int n, double z, const double* x, double (*c)[4]) {
+// built up one node at a time; derivatives up to order MD.
+template <int MD>
+__device__ void fornberg_weights(int n, double z, const double* x, double (*c)[MD + 1]) {
     for (int j = 0; j < n; ++j)
-        for (int d = 0; d < 4; ++d) c[j][d] = 0.0;
+        for (int d = 0; d <= MD; ++d) c[j][d] = 0.0;
     c[0][0] = 1.0;
     double c1 = 1.0, c4 = x[0] - z;
     for (int i = 1; i < n; ++i) {
-        const int mn = i < 3 ? i : 3;
+        const int mn = i < MD ? i : MD;
         double c2 = 1.0;
         const double c5 = c4;
         c4 = x[i] - z;
@@ -51,13 +58,34 @@ __global__ void fd_table_kernel(double* __restrict__ tab) {
     double x[kMaxN];
     for (int k = 0; k < n; ++k) x[k] = (double)k - 0.5 * (double)(n - 1);
     double c[kMaxN][4];
-    fornberg_weights(n, x[a], x, c);
+    fornberg_weights<3>(n, x[a], x, c);
     for (int d = 0; d < kFdDerivs; ++d)
         for (int k = 0; k < n; ++k) tab[fd_index(n, d, a, k)] = c[k][d + 1];
 }
 
+// One thread per (stencil size, expansion node a): entry (a, k, j) is the
+// k-th derivative of basis polynomial j at node a over k! -- the coefficient
+// of y^k in l_j(x_a + y).
+__global__ void taylor_table_kernel(double* __restrict__ tab) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kNumN * kMaxN) return;
+    const int n = 3 + 2 * (t / kMaxN);
+    const int a = t % kMaxN;
+    if (a >= n) return;
+    double x[kMaxN];
+    for (int k = 0; k < n; ++k) x[k] = (double)k - 0.5 * (double)(n - 1);
+    double c[kMaxN][kMaxN];
+    fornberg_weights<kMaxN - 1>(n, x[a], x, c);
+    double fact = 1.0;
+    for (int d = 0; d < n; ++d) {
+        if (d > 1) fact *= (double)d;
+        for (int j = 0; j < n; ++j) tab[taylor_index(n, a, d, j)] = c[j][d] / fact;
+    }
+}
+
 std::mutex g_mu;
 const double* g_ptr[64] = {};
+const double* g_taylor_ptr[64] = {};
 
 }  // namespace
 
@@ -76,6 +104,24 @@ hipError_t fd_table_init(const double** d_table_out) {
         g_ptr[dev] = (const double*)p;
     }
     *d_table_out = g_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t taylor_table_init(const double** d_table_out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_taylor_ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_taylor_table))) != hipSuccess) return e;
+        hipLaunchKernelGGL(taylor_table_kernel, dim3(1), dim3(kNumN * kMaxN), 0, nullptr, (double*)p);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+        g_taylor_ptr[dev] = (const double*)p;
+    }
+    *d_table_out = g_taylor_ptr[dev];
     return hipSuccess;
 }
 

@@ -36,6 +36,7 @@ std::atomic<int> t_steps_per_launch{8};  // LMEP_OPT_STEPS_PER_LAUNCH, process-w
 std::atomic<int> t_profile_adjoint{0};   // LMEP_OPT_PROFILE_ADJOINT, process-wide
 std::atomic<int> t_fuse_frozen{1};       // LMEP_OPT_FUSE_FROZEN, process-wide
 std::atomic<int> t_apply_tile{0};        // LMEP_OPT_APPLY_TILE, process-wide (0 = by size)
+std::atomic<int> t_exp_method{LMEP_EXP_AUTO};  // LMEP_OPT_EXP_METHOD, process-wide
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -58,6 +59,12 @@ int scheme_kinds(int scheme) { return scheme == LMEP_ETDRK4 ? 6 : 1 + scheme_p(s
 bool frozen(const lmep_problem& q) { return q.nonlin == LMEP_NL_BURGERS_FROZEN; }
 bool nonuniform(const lmep_problem& q) { return q.x != nullptr; }
 bool pernode(const lmep_problem& q) { return frozen(q) || nonuniform(q); }
+// Frozen-velocity instances whose weights the finite-Taylor kernel builds: a
+// polynomial operator in the first-derivative matrix (uniform grid, no
+// reaction term), unless LMEP_OPT_EXP_METHOD asks for Pade.
+bool taylor(const lmep_problem& q) {
+    return frozen(q) && !nonuniform(q) && q.react == 0.0 && t_exp_method.load() == LMEP_EXP_AUTO;
+}
 
 int64_t weight_count(const lmep_problem& q) {
     const int64_t kinds = scheme_kinds(q.scheme);
@@ -223,6 +230,7 @@ DevProb to_dev(const lmep_problem& q, int index) {
 // one kernel variant.
 struct Group {
     int n = 0, p = 0, scheme = 0, nonlin = 0, tile = 0;
+    bool taylor = false;     // build by finite Taylor series (items = kTaylorTile-node tiles)
     bool pernode = false;    // weights stored per node (frozen velocity or non-uniform grid)
     bool frozen = false;     // rebuilt every step (frozen velocity)
     bool nonuniform = false; // non-uniform grid: wide build, per-node stationary weights
@@ -240,15 +248,16 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
     struct Part {
         int k, harvest;
     };
-    std::map<std::tuple<int, int, int>, std::vector<Part>> by;  // (n, p, non-uniform)
+    // (n, p, kind): kind 0 Pade on a uniform grid, 1 non-uniform grid, 2 finite Taylor
+    std::map<std::tuple<int, int, int>, std::vector<Part>> by;
     for (int k = 0; k < count; ++k) {
         if (!want(prob[k])) continue;
-        const int nu = nonuniform(prob[k]) ? 1 : 0;
+        const int kind = nonuniform(prob[k]) ? 1 : (taylor(prob[k]) ? 2 : 0);
         if (prob[k].scheme == LMEP_ETDRK4) {
-            by[{prob[k].n, 3, nu}].push_back({k, HARVEST_RK4_FULL});
-            by[{prob[k].n, 1, nu}].push_back({k, HARVEST_RK4_HALF});
+            by[{prob[k].n, 3, kind}].push_back({k, HARVEST_RK4_FULL});
+            by[{prob[k].n, 1, kind}].push_back({k, HARVEST_RK4_HALF});
         } else {
-            by[{prob[k].n, scheme_p(prob[k].scheme), nu}].push_back({k, HARVEST_PLAIN});
+            by[{prob[k].n, scheme_p(prob[k].scheme), kind}].push_back({k, HARVEST_PLAIN});
         }
     }
     std::vector<Group> groups;
@@ -256,7 +265,8 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         Group g;
         g.n = std::get<0>(kv.first);
         g.p = std::get<1>(kv.first);
-        g.nonuniform = std::get<2>(kv.first) != 0;
+        g.nonuniform = std::get<2>(kv.first) == 1;
+        g.taylor = std::get<2>(kv.first) == 2;
         g.first = (int)tab.size();
         int64_t items = 0;
         for (const Part& part : kv.second) {
@@ -265,7 +275,8 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             d.harvest = part.harvest;
             if (part.harvest == HARVEST_RK4_HALF) d.dt = 0.5 * prob[part.k].dt;
             d.item_begin = items;
-            items += pernode(prob[part.k]) ? prob[part.k].N : prob[part.k].n;
+            items += g.taylor ? (prob[part.k].N + kTaylorTile - 1) / kTaylorTile
+                              : (pernode(prob[part.k]) ? prob[part.k].N : prob[part.k].n);
             tab.push_back(d);
         }
         g.count = (int)kv.second.size();
@@ -452,6 +463,13 @@ int lmep_set_option(int32_t option, int32_t value) {
         (option == LMEP_OPT_PROFILE_ADJOINT ? t_profile_adjoint : t_fuse_frozen).store(value);
         return LMEP_OK;
     }
+    if (option == LMEP_OPT_EXP_METHOD) {
+        if (value != LMEP_EXP_AUTO && value != LMEP_EXP_PADE)
+            return fail(LMEP_ERR_ARG, "exponential method must be LMEP_EXP_AUTO (0) or LMEP_EXP_PADE (1), got %d",
+                        value);
+        t_exp_method.store(value);
+        return LMEP_OK;
+    }
     if (option == LMEP_OPT_APPLY_TILE) {
         if (value != 0 && value != 64 && value != kApplyTileSmall && value != kApplyTile)
             return fail(LMEP_ERR_ARG, "apply tile must be 0, 64, %d or %d, got %d", kApplyTileSmall, kApplyTile, value);
@@ -466,6 +484,7 @@ int32_t lmep_get_option(int32_t option) {
     if (option == LMEP_OPT_PROFILE_ADJOINT) return t_profile_adjoint.load();
     if (option == LMEP_OPT_FUSE_FROZEN) return t_fuse_frozen.load();
     if (option == LMEP_OPT_APPLY_TILE) return t_apply_tile.load();
+    if (option == LMEP_OPT_EXP_METHOD) return t_exp_method.load();
     return fail(LMEP_ERR_ARG, "unknown option %d", option);
 }
 
@@ -493,13 +512,17 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
     const double* fd = nullptr;
     HIP_TRY(fd_table_init(&fd));
     std::vector<DevProb> btab, none;
+    const double* tay = nullptr;
     auto groups = plan_build(prob, count, [](const lmep_problem&) { return true; }, btab);
     char* base = (char*)d_scratch;
     if ((rc = upload(btab, none, base + L.build_tab, nullptr, s))) return rc;
     const DevProb* dtab = (const DevProb*)(base + L.build_tab);
     for (auto& g : groups) {
+        if (g.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
         if (g.nonuniform)
             HIP_TRY(launch_build_wide(g.n, g.p, dtab + g.first, g.count, g.items, d_w, s));
+        else if (g.taylor)
+            HIP_TRY(launch_build_taylor(g.n, dtab + g.first, g.count, g.items, fd, tay, d_u, d_w, nullptr, s));
         else
             HIP_TRY(launch_build(g.n, g.p, dtab + g.first, g.count, g.items, fd, d_u, d_w, nullptr, s));
     }
@@ -543,6 +566,9 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     std::vector<DevProb> btab, atab;
     std::vector<int> tile_inst;
     auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab);
+    const double* tay = nullptr;
+    for (auto& gr : bgroups)
+        if (gr.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
     const int kb = multi ? t_steps_per_launch.load() : 1;
     auto agroups = plan_apply(prob, count, atab, tile_inst, multi ? kb : 0);
     // resident groups (small non-uniform instances) advance all n_steps from
@@ -587,9 +613,14 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
                 // frozen-velocity groups: weights rebuilt, and with fusion applied
                 // in the same kernel (their apply groups are then skipped)
                 HIP_TRY(timer.mark(true, s, true));
-                for (auto& gr : bgroups)
-                    HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters, s,
-                                         fuse ? dst : nullptr));
+                for (auto& gr : bgroups) {
+                    if (gr.taylor)
+                        HIP_TRY(launch_build_taylor(gr.n, dbt + gr.first, gr.count, gr.items, fd, tay, src, d_w,
+                                                    counters, s, fuse ? dst : nullptr));
+                    else
+                        HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters,
+                                             s, fuse ? dst : nullptr));
+                }
                 HIP_TRY(timer.mark(true, s, false));
             }
             if (apply_launched) HIP_TRY(timer.mark(false, s, true));

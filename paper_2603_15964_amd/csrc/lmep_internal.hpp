@@ -53,9 +53,18 @@ __host__ __device__ inline int fd_index(int n, int d, int a, int k) {
     return ((((n - 3) / 2) * kFdDerivs + d) * kMaxN + a) * kMaxN + k;
 }
 
+// Table of the finite-Taylor build: taylor[(n-3)/2][a][k][j] = k-th derivative
+// of the window's Lagrange basis polynomial j at node a of the centred integer
+// stencil, divided by k! (row a of D1^k / k!).
+constexpr int kTaylorTableDoubles = kNumN * kMaxN * kMaxN * kMaxN;
+__host__ __device__ inline int taylor_index(int n, int a, int k, int j) {
+    return ((((n - 3) / 2) * kMaxN + a) * kMaxN + k) * kMaxN + j;
+}
+
 // ---------------------------------------------------------------- launchers
-// Fill the per-device stencil table (blocking; once per device).
+// Fill the per-device stencil tables (blocking; once per device).
 hipError_t fd_table_init(const double** d_table_out);
+hipError_t taylor_table_init(const double** d_table_out);
 
 // Build weights for one group of instances sharing (n, p).  items = total
 // matrices of the group.  stats (nullable, profiling): stats[0] += matrices
@@ -65,6 +74,15 @@ hipError_t fd_table_init(const double** d_table_out);
 hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t items,
                         const double* fd, const double* d_u, double* d_w, unsigned long long* stats,
                         hipStream_t stream, double* d_u_out = nullptr);
+
+// Frozen-velocity ETD1 weights by the finite Taylor series of the exponential
+// (react = 0, uniform grid): one thread per node, blocks of kTaylorTile nodes
+// of one instance; items = tiles, item_begin = the instance's first tile.
+// With d_u_out the step is fused as in launch_build.  stats[0] += nodes built.
+constexpr int kTaylorTile = 256;
+hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd,
+                               const double* taylor, const double* d_u, double* d_w, unsigned long long* stats,
+                               hipStream_t stream, double* d_u_out = nullptr);
 
 // Stationary per-node weights of non-uniform grids (one node per wavefront,
 // matrices in LDS; p <= 2, n + p <= kMaxMWide).

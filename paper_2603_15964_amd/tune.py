@@ -4,7 +4,8 @@ For a batch of instances it times the launch choices the library offers and
 keeps the fastest one whose result agrees with the default path:
 
 * frozen-velocity instances: the fused build-and-apply kernel or the
-  build-then-apply pair (LMEP_OPT_FUSE_FROZEN);
+  build-then-apply pair (LMEP_OPT_FUSE_FROZEN), each with the finite-Taylor
+  or the Pade exponential (LMEP_OPT_EXP_METHOD);
 * stationary instances: one step per launch, or LMEP_F_PERSISTENT with 1, 2,
   4 or 8 steps per launch (LMEP_OPT_STEPS_PER_LAUNCH; non-uniform instances
   held whole by a block run every step in one launch);
@@ -25,11 +26,11 @@ import math
 import os
 from dataclasses import dataclass, field
 
-from ._native import (LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH,
-                      lmep_get_option, lmep_set_option)
+from ._native import (LMEP_EXP_AUTO, LMEP_EXP_PADE, LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE, LMEP_OPT_EXP_METHOD,
+                      LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, lmep_get_option, lmep_set_option)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2603_15964_amd", "tune.json")
-_OPTIONS = (LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_APPLY_TILE)
+_OPTIONS = (LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_APPLY_TILE, LMEP_OPT_EXP_METHOD)
 
 
 @dataclass(frozen=True)
@@ -47,7 +48,7 @@ class Choice:
 
     def describe(self):
         names = {LMEP_OPT_FUSE_FROZEN: "fuse_frozen", LMEP_OPT_STEPS_PER_LAUNCH: "steps_per_launch",
-                 LMEP_OPT_APPLY_TILE: "apply_tile"}
+                 LMEP_OPT_APPLY_TILE: "apply_tile", LMEP_OPT_EXP_METHOD: "exp_method"}
         d = {names[a]: b for a, b in self.options}
         d["persistent"] = bool(self.flags & LMEP_F_PERSISTENT)
         return d
@@ -89,15 +90,17 @@ def candidates(problems):
     tiles = (0, 256, 1024) + ((64,) if nonuniform else ())
     out = []
     fuses = (1, 0) if frozen else (1,)
-    for fuse in fuses:
-        for tile in tiles:
-            out.append(Choice(0, ((LMEP_OPT_FUSE_FROZEN, fuse), (LMEP_OPT_STEPS_PER_LAUNCH, 8),
-                                  (LMEP_OPT_APPLY_TILE, tile))))
+    methods = (LMEP_EXP_AUTO, LMEP_EXP_PADE) if frozen else (LMEP_EXP_AUTO,)
+    for method in methods:
+        for fuse in fuses:
+            for tile in tiles:
+                out.append(Choice(0, ((LMEP_OPT_FUSE_FROZEN, fuse), (LMEP_OPT_STEPS_PER_LAUNCH, 8),
+                                      (LMEP_OPT_APPLY_TILE, tile), (LMEP_OPT_EXP_METHOD, method))))
     if persistent_ok:
         kbs = (8,) if (nonuniform and all(p.get("x") is not None for p in problems)) else (1, 2, 4, 8)
         for kb in kbs:
             out.append(Choice(LMEP_F_PERSISTENT, ((LMEP_OPT_FUSE_FROZEN, 1), (LMEP_OPT_STEPS_PER_LAUNCH, kb),
-                                                  (LMEP_OPT_APPLY_TILE, 0))))
+                                                  (LMEP_OPT_APPLY_TILE, 0), (LMEP_OPT_EXP_METHOD, LMEP_EXP_AUTO))))
     return out
 
 

@@ -125,6 +125,21 @@ def test_multistep_flag_and_option():
         lmep.lmep_set_option(opt, 8)
 
 
+def test_exp_method_option():
+    """LMEP_OPT_EXP_METHOD takes LMEP_EXP_AUTO (default) or LMEP_EXP_PADE."""
+    opt = lmep.LMEP_OPT_EXP_METHOD
+    assert lmep.lmep_get_option(opt) == lmep.LMEP_EXP_AUTO
+    for bad in (-1, 2, 7):
+        with pytest.raises(lmep.LmepError):
+            lmep.lmep_set_option(opt, bad)
+    try:
+        lmep.lmep_set_option(opt, lmep.LMEP_EXP_PADE)
+        assert lmep.lmep_get_option(opt) == lmep.LMEP_EXP_PADE
+    finally:
+        lmep.lmep_set_option(opt, lmep.LMEP_EXP_AUTO)
+    assert lmep.lmep_get_option(opt) == lmep.LMEP_EXP_AUTO
+
+
 def test_window_field_checks():
     """The window field: unknown values are ARG; upwind windows are refused
     with ETDRK4, with multi-step launches and by the reverse step before any

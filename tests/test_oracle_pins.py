@@ -450,3 +450,25 @@ def test_windows_are_in_domain_and_harvest_own_row():
             assert o == want
         pp = dict(p, bc="periodic")
         assert all(oracle.window_offset(pp, i) == -(n - 1) // 2 for i in range(N))
+
+
+# ------------------------------------------------------- nilpotent D ----
+@pytest.mark.parametrize("n", [3, 5, 7, 9, 11, 13, 15])
+def test_window_operator_is_polynomial_in_nilpotent_first_derivative(n):
+    """The stencil's derivative matrices are those of the degree n - 1
+    interpolant (Sec. 2.1 step 1): D2 = D1^2, D3 = D1^3 and D1^n = 0, so every
+    local operator -c D1 + nu D2 - delta D3 is a polynomial in a nilpotent
+    matrix and its exponential a finite Taylor sum (the premise of the
+    finite-Taylor weight build for frozen-velocity instances)."""
+    h = 0.61
+    D1, D2, D3 = oracle.fd_matrices(n, h)
+    s1 = np.max(np.abs(D1))
+    assert np.max(np.abs(D1 @ D1 - D2)) <= 1e-13 * s1 ** 2 * n
+    assert np.max(np.abs(D1 @ D1 @ D1 - D3)) <= 1e-13 * s1 ** 3 * n ** 2
+    P = np.eye(n)
+    for _ in range(n):
+        P = P @ D1
+    assert np.max(np.abs(P)) <= 1e-12 * s1 ** n * n ** (n - 1)
+    # and the degree n - 1 power does not vanish (index exactly n)
+    Q = np.linalg.matrix_power(D1 * h, n - 1)
+    assert np.max(np.abs(Q)) >= 0.5

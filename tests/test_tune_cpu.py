@@ -9,8 +9,8 @@ import numpy as np
 
 import workloads
 from paper_2603_15964_amd import tune
-from paper_2603_15964_amd._native import (LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE, LMEP_OPT_FUSE_FROZEN,
-                                          LMEP_OPT_STEPS_PER_LAUNCH)
+from paper_2603_15964_amd._native import (LMEP_EXP_AUTO, LMEP_EXP_PADE, LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE,
+                                          LMEP_OPT_EXP_METHOD, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH)
 
 
 def _opts(c):
@@ -33,8 +33,11 @@ def test_candidates_follow_what_the_library_accepts():
     frozen = [workloads.burgers(N=1000)[0]]
     c = tune.candidates(frozen)
     assert {_opts(x)[LMEP_OPT_FUSE_FROZEN] for x in c} == {0, 1}
+    assert {_opts(x)[LMEP_OPT_EXP_METHOD] for x in c} == {LMEP_EXP_AUTO, LMEP_EXP_PADE}
+    assert _opts(c[0])[LMEP_OPT_EXP_METHOD] == LMEP_EXP_AUTO  # the default comes first (reference result)
     assert not any(x.flags & LMEP_F_PERSISTENT for x in c)
     stat = [workloads.kdv(N=4096)[0]]
+    assert {_opts(x)[LMEP_OPT_EXP_METHOD] for x in tune.candidates(stat)} == {LMEP_EXP_AUTO}
     kbs = {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in tune.candidates(stat) if x.flags & LMEP_F_PERSISTENT}
     assert kbs == {1, 2, 4, 8}
     upwind = [workloads.burgers_upwind(N=1000)[0]]
