@@ -271,6 +271,8 @@ def main():
     ap.add_argument("--workload", default="burgers")
     ap.add_argument("--graph", action="store_true", help="replay the step loop from a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain single-instance comparison runs (and the Pade comparison run)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates byte counters)")
     ap.add_argument("--persistent", action="store_true",
@@ -314,10 +316,11 @@ def main():
                "config": {"workload": desc, "instances": len(problems), "nodes": sum(p["N"] for p in problems),
                           "checkpoint_every": 50},
                "roofline": adjoint_roofline(problems, states)}
-        pv, pk = plain_forward(problems, states, min(args.steps, 50))
-        out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,
-                        "kind": "single-instance forward only, instances one at a time, per-step eager launches",
-                        "ratio": out["value"] / pv}
+        if not args.no_plain:
+            pv, pk = plain_forward(problems, states, min(args.steps, 50))
+            out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,
+                            "kind": "single-instance forward only, instances one at a time, per-step eager launches",
+                            "ratio": out["value"] / pv}
         print(json.dumps(out), flush=True)
         return
     batch = lmep.Batch(problems, device=dev)
@@ -468,7 +471,7 @@ def main():
         "roofline": roof,
         "detail": extra,
     }
-    if taylor:
+    if taylor and not args.no_plain:
         # the same steps through the Pade build, for comparison
         lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_PADE)
         batch.step(w, ua, 2, flags, u_out=ub)
@@ -481,7 +484,7 @@ def main():
         out["pade_path"] = {"value": node_steps / pw, "unit": "node-steps/s",
                             "kind": "same steps, frozen-velocity weights by Pade scaling-and-squaring",
                             "ratio": value / (node_steps / pw)}
-    if len(problems) > 1:
+    if len(problems) > 1 and not args.no_plain:
         pv, pk = plain_forward(problems, states, min(args.steps, 20))
         out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,
                         "kind": "single-instance forward, instances one at a time, per-step eager launches",
