@@ -211,11 +211,33 @@ def pair_pade_flops(m: int, squarings: float) -> float:
     return 36.0 * m ** 3 + (2.0 / 3.0 + 6.0) * m ** 3 + 6.0 * m ** 3 * squarings
 
 
+def adj_taylor_flops(n: int, p: int) -> float:
+    """Algorithmic flops of one node of the finite-Taylor reverse-step kernel
+    (2 per multiply-add; unshifted): the moment recursion with its diffusion
+    and dispersion terms (orders 1..n-1, order K having K entries: one
+    multiply, then a multiply-add each from order 2 and from order 3, plus two
+    coefficient multiplies per order), the three moment sums per order
+    (M(1), its integral and its first moment: 5K - 3), the contractions per
+    order with the table row (W0 and tau, and for ETD1 W1 and nu: 2n each),
+    the three derivative terms per order (5 each, 2.5 for LINEAR), the
+    window's N values (3 per position, ETD1), and the scaled outputs."""
+    orders = range(1, n)
+    rec = sum(K + (2 * K if K >= 2 else 0) + (2 * K if K >= 3 else 0) + 2 for K in orders)
+    sums = sum(5 * K - 3 for K in orders)
+    con = (n - 1) * (2 * n) * (4 if p >= 1 else 2)
+    der = (n - 1) * 3 * (5 if p >= 1 else 2.5)
+    nval = 3 * n if p >= 1 else 0
+    out = (n if p >= 1 else 0) + 9
+    return float(rec + sums + con + der + nval + out)
+
+
 def adjoint_roofline(problems, states, reps: int = 5):
-    """Roofline of the Frechet kernel of the reverse step: HIP events around
-    that kernel (LMEP_OPT_PROFILE_ADJOINT) over `reps` reverse steps at u0,
-    and its squarings from a counting forward step at the same state (the
-    pair's scaling is chosen from the same local matrix)."""
+    """Roofline of the per-node kernel of the reverse step (finite Taylor
+    series, or the Frechet derivative by the block-triangular Pade exponential
+    with LMEP_EXP_PADE): HIP events around that kernel
+    (LMEP_OPT_PROFILE_ADJOINT) over `reps` reverse steps at u0; for Pade its
+    squarings come from a counting forward step at the same state (the pair's
+    scaling is chosen from the same local matrix)."""
     import torch
     import paper_2603_15964_amd as lmep
     batch = lmep.Batch(problems, device="cuda:0")
@@ -239,9 +261,16 @@ def adjoint_roofline(problems, states, reps: int = 5):
         lmep.lmep_set_option(lmep.LMEP_OPT_PROFILE_ADJOINT, 0)
     p0 = problems[0]
     m = p0["n"] + {"linear": 0, "etd1": 1}[p0["scheme"]]
-    flops = batch.state_size * pair_pade_flops(m, mean_s) * reps
+    taylor = (lmep.lmep_get_option(lmep.LMEP_OPT_EXP_METHOD) == lmep.LMEP_EXP_AUTO and
+              all(p.get("react", 0.0) == 0.0 for p in problems))
+    if taylor:
+        flops = batch.state_size * adj_taylor_flops(p0["n"], m - p0["n"]) * reps
+        kname = f"adj_taylor_kernel<{p0['n']},{m - p0['n']}>"
+        mean_s = 0.0
+    else:
+        flops = batch.state_size * pair_pade_flops(m, mean_s) * reps
+        kname = f"adj_frechet_kernel<{p0['n']},{m - p0['n']}>"
     tf = flops / (fre_ms / 1e3) / 1e12
-    kname = f"adj_frechet_kernel<{p0['n']},{m - p0['n']}>"
     return {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": tf / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname], "burgers_adjoint"), "kernel": kname,
             "avg_launch_us": fre_ms * 1e3 / max(1, launches), "flops_per_launch": flops / max(1, launches),

@@ -186,7 +186,10 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
  * d_grad[3 * k + {0, 1, 2}] = (d loss/d nu, d loss/d c, d loss/d delta) of
  * instance k.  The weights' dependence on the parameters and on the frozen
  * velocity is taken from the Frechet derivative of each local exponential,
- * read off the block-triangular exponential [[A, E], [0, A]] (FP64 Pade).
+ * read off the block-triangular exponential [[A, E], [0, A]] (FP64 Pade), or,
+ * for instances without a reaction term under LMEP_EXP_AUTO, from the
+ * derivatives of the exact finite Taylor series of the same exponential (the
+ * moments of its symbol shifted by one to three orders).
  * Entries of lambda at Dirichlet end nodes are ignored (those nodes are not
  * updated).  Summation order is fixed, so results are bitwise reproducible. */
 int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u_k,

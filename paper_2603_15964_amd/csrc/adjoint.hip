@@ -22,6 +22,8 @@
 // Kernels (all deterministic, no atomics):
 //   adj_prep     du/dx at every node from its own stencil (frozen velocity)
 //   adj_frechet  per node: W0, W1 of E_i and the three contractions of F_i
+//                (or adj_taylor_kernel, the same from the finite Taylor series,
+//                adjoint_taylor.hip)
 //   adj_ghat     ghat_m = sum_i lam_i W1_i[k] (-g)(u_m - u_i) over stencils S_i
 //                containing m (adjoint of du/dx at m)
 //   adj_lambda   lam_k by the transposed banded apply (gather over the
@@ -484,15 +486,19 @@ hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
                        a.g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (a.frechet_begin && (e = hipEventRecord(a.frechet_begin, s)) != hipSuccess) return e;
-    switch (a.n) {
-        case 3: e = frechet_n<3>(a, s); break;
-        case 5: e = frechet_n<5>(a, s); break;
-        case 7: e = frechet_n<7>(a, s); break;
-        case 9: e = frechet_n<9>(a, s); break;
-        case 11: e = frechet_n<11>(a, s); break;
-        case 13: e = frechet_n<13>(a, s); break;
-        case 15: e = frechet_n<15>(a, s); break;
-        default: return hipErrorInvalidValue;
+    if (a.taylor) {
+        e = launch_adj_taylor(a, s);
+    } else {
+        switch (a.n) {
+            case 3: e = frechet_n<3>(a, s); break;
+            case 5: e = frechet_n<5>(a, s); break;
+            case 7: e = frechet_n<7>(a, s); break;
+            case 9: e = frechet_n<9>(a, s); break;
+            case 11: e = frechet_n<11>(a, s); break;
+            case 13: e = frechet_n<13>(a, s); break;
+            case 15: e = frechet_n<15>(a, s); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     if (e != hipSuccess) return e;
     if (a.frechet_end && (e = hipEventRecord(a.frechet_end, s)) != hipSuccess) return e;

@@ -734,18 +734,26 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
     const double* fd = nullptr;
     HIP_TRY(fd_table_init(&fd));
 
-    // groups by (n, p): a node table and a tile table with the same instance order
-    std::map<std::pair<int, int>, std::vector<int>> by;
-    for (int k = 0; k < count; ++k) by[{prob[k].n, scheme_p(prob[k].scheme)}].push_back(k);
+    // groups by (n, p, method): a node table and a tile table with the same
+    // instance order; instances without a reaction term take the finite
+    // Taylor series unless LMEP_OPT_EXP_METHOD asks for Pade
+    const bool auto_method = t_exp_method.load() == LMEP_EXP_AUTO;
+    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    for (int k = 0; k < count; ++k)
+        by[{prob[k].n, scheme_p(prob[k].scheme), (auto_method && prob[k].react == 0.0) ? 1 : 0}].push_back(k);
     std::vector<DevProb> ntab, ttab;
     struct G {
         int n, p, first, cnt;
         int64_t nodes, tiles;
+        bool taylor;
     };
     std::vector<G> groups;
+    const double* tay = nullptr;
     int64_t tile_base = 0;
     for (auto& kv : by) {
-        G g{kv.first.first, kv.first.second, (int)ntab.size(), (int)kv.second.size(), 0, 0};
+        G g{std::get<0>(kv.first), std::get<1>(kv.first), (int)ntab.size(), (int)kv.second.size(), 0, 0,
+            std::get<2>(kv.first) == 1};
+        if (g.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
             d.item_begin = g.nodes;
@@ -790,6 +798,7 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
         a.ws_stride = L.ws_stride;
         a.dparam = (double*)(base + L.dparam);
         a.part = (double*)(base + L.part) + 3 * part_base;
+        a.taylor = g.taylor ? tay : nullptr;
         if (timer.on) {
             a.frechet_begin = timer.build[timer.nb].first;
             a.frechet_end = timer.build[timer.nb].second;

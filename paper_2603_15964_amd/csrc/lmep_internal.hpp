@@ -165,9 +165,11 @@ struct AdjointLaunch {
     int ws_stride = 0;
     double* dparam = nullptr;
     double* part = nullptr;
+    const double* taylor = nullptr;  // set: per-node part by the finite Taylor series (adjoint_taylor.hip)
     hipEvent_t frechet_begin = nullptr, frechet_end = nullptr;  // recorded around the Frechet kernel if set
 };
 hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t stream);
+hipError_t launch_adj_taylor(const AdjointLaunch& a, hipStream_t stream);
 
 // Finite check: writes 1 into *d_flag if any of the count doubles is not finite.
 hipError_t launch_check_finite(const double* d_x, int64_t count, int* d_flag, hipStream_t stream);

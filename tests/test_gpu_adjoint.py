@@ -1,7 +1,9 @@
 """GPU parity of the reverse step and of the checkpointed gradient.
 
-The reverse step (lmep_adjoint_step, Frechet derivatives from the
-block-triangular Pade exponential + transposed banded apply) is compared
+The reverse step (lmep_adjoint_step: per-node weights and parameter
+derivatives from the finite Taylor series by default, or from the Frechet
+derivative of the block-triangular Pade exponential, + transposed banded
+apply) is compared
 with the oracle's adjoint (forward-mode directional derivatives from a
 terminating series, scatter form), which is itself pinned by complex-step
 derivatives.  Tolerance 1e-10 relative (FP64), per gradient component.
@@ -158,3 +160,58 @@ def test_profiled_reverse_step_is_unchanged():
     torch.cuda.synchronize()
     assert torch.equal(ref_lam, got_lam) and torch.equal(ref_g, got_g)
     assert prof["build_launches"] == 1 and prof["build_ms"] > 0.0 and prof["apply_ms"] >= 0.0
+
+
+def _reverse(probs, us, lams):
+    b = lmep.Batch(probs, device=DEV)
+    lk, gr = b.adjoint_step(b.pack(us), b.pack(lams))
+    torch.cuda.synchronize()
+    return b.unpack(lk), gr.cpu().numpy().reshape(-1, 3)
+
+
+@pytest.mark.parametrize("name,p", CASES, ids=[c[0] for c in CASES])
+def test_taylor_and_pade_reverse_steps_agree(name, p):
+    """The reverse step's per-node part by the finite Taylor series (default)
+    and by the block-triangular Pade exponential (LMEP_EXP_PADE) agree to
+    1e-12 in lambda and per gradient component."""
+    _case("taylor vs pade reverse", name)
+    u = _state(p, 3)
+    lam = np.random.default_rng(4).normal(size=p["N"])
+    lt, gt = _reverse([p], [u], [lam])
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_EXP_METHOD)
+    lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_PADE)
+    try:
+        lp, gp = _reverse([p], [u], [lam])
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, saved)
+    assert _rel(lt[0], lp[0]) <= 1e-12
+    for k in range(3):
+        scale = max(abs(gp[0][k]), 1e-12 * np.max(np.abs(gp[0])), 1e-300)
+        assert abs(gt[0][k] - gp[0][k]) <= 1e-12 * scale, (k, gt[0][k], gp[0][k])
+
+
+def test_reaction_term_reverse_step_takes_pade():
+    """An instance with a reaction term (no finite Taylor form) batched with
+    Taylor ones: the Taylor instances match the oracle, the reaction-term
+    instance equals its own Pade reverse step bit for bit (the oracle's
+    reverse step covers no reaction term, so that instance is checked
+    against the Pade path only)."""
+    _case("reverse step with reaction term")
+    probs = [CASES[0][1], dict(CASES[4][1], react=-0.2), CASES[2][1]]
+    us = [_state(p, 30 + k) for k, p in enumerate(probs)]
+    lams = [np.random.default_rng(40 + k).normal(size=p["N"]) for k, p in enumerate(probs)]
+    got, gr = _reverse(probs, us, lams)
+    for k in (0, 2):
+        want, wg = oracle.adjoint_step(probs[k], us[k], lams[k])
+        assert _rel(got[k], want) <= 1e-10, k
+        for c in range(3):
+            scale = max(abs(wg[c]), 1e-12 * np.max(np.abs(wg)), 1e-300)
+            assert abs(gr[k][c] - wg[c]) <= 1e-10 * scale, (k, c)
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_EXP_METHOD)
+    lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_PADE)
+    try:
+        lp, gp = _reverse([probs[1]], [us[1]], [lams[1]])
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, saved)
+    assert np.array_equal(got[1], lp[0])
+    assert np.array_equal(gr[1], gp[0])
