@@ -305,7 +305,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates byte counters)")
     ap.add_argument("--persistent", action="store_true",
-                    help="stationary weights: advance several steps per launch (LMEP_F_PERSISTENT)")
+                    help="advance several steps per launch (LMEP_F_PERSISTENT)")
+    ap.add_argument("--launch", choices=("auto", "one-step", "persistent"), default="auto",
+                    help="auto: several steps per launch for frozen-velocity workloads the multi-step kernel covers "
+                         "whose batch is under 2^20 nodes (too small to fill the GPU in one step), one step "
+                         "otherwise; --persistent is the same as --launch persistent")
     ap.add_argument("--steps-per-launch", type=int, default=8, choices=(1, 2, 4, 8))
     ap.add_argument("--tune", action="store_true",
                     help="let the autotuner pick fusion / steps per launch / apply tile (cached per GPU and shape)")
@@ -333,6 +337,14 @@ def main():
 
     problems, states, desc = make_workload(args.workload)
     dev = "cuda:0"
+    if args.launch == "persistent":
+        args.persistent = True
+    elif args.launch == "auto" and not args.persistent and not args.tune:
+        frozen_all = all(p.get("nonlin") == "burgers_frozen" for p in problems)
+        covered = all(p.get("window", "centred") == "centred" and p["bc"] != "neumann" and
+                      p.get("react", 0.0) == 0.0 for p in problems)
+        small = sum(int(p["N"]) for p in problems) < (1 << 20)
+        args.persistent = frozen_all and covered and small and args.exp_method == "auto"
     lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD,
                          lmep.LMEP_EXP_PADE if args.exp_method == "pade" else lmep.LMEP_EXP_AUTO)
     if args.workload == "burgers_adjoint":
@@ -373,8 +385,6 @@ def main():
         if args.persistent:
             kb = opts[lmep.LMEP_OPT_STEPS_PER_LAUNCH]
     elif args.persistent:
-        if frozen:
-            raise SystemExit("--persistent needs stationary weights (this workload rebuilds them every step)")
         flags |= lmep.LMEP_F_PERSISTENT
         kb = args.steps_per_launch
         lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
@@ -410,7 +420,11 @@ def main():
         p0 = problems[0]
         m = p0["n"] + {"linear": 0, "etd1": 1, "etd2rk": 2}[p0["scheme"]]
         fused = lmep.lmep_get_option(lmep.LMEP_OPT_FUSE_FROZEN) == 1
-        if taylor:
+        if taylor and args.persistent:
+            # node-steps of the launches (the halo each block recomputes is not counted)
+            flops = taylor_flops(p0["n"], True) * prof["matrices"]
+            kname = f"taylor_stepk_kernel<{p0['n']}>"
+        elif taylor:
             flops = taylor_flops(p0["n"], fused) * prof["matrices"]
             kname = f"build_taylor_kernel<{p0['n']},{'true' if fused else 'false'}>"
         else:
@@ -503,10 +517,11 @@ def main():
     if taylor and not args.no_plain:
         # the same steps through the Pade build, for comparison
         lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_PADE)
-        batch.step(w, ua, 2, flags, u_out=ub)
+        pflags = flags & ~lmep.LMEP_F_PERSISTENT  # the Pade build runs one step per launch
+        batch.step(w, ua, 2, pflags, u_out=ub)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        batch.step(w, ua, args.steps, flags, u_out=ub)
+        batch.step(w, ua, args.steps, pflags, u_out=ub)
         torch.cuda.synchronize()
         pw = time.perf_counter() - t1
         lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_AUTO)

@@ -8,7 +8,7 @@
 // (a = -c dt/h, b = nu dt/h^2, e = -delta dt/h^3) and the moments
 // e^{theta q} = sum_k M_k(theta) x^k / k!, the rows are
 //     W0 = sum_k M_k(1) T_k[r'],   W1 = dt sum_k (int_0^1 M_k) T_k[r']
-// (expanded about node r' = r + s, s the integer nearest a/2).  Differentiating
+// (expanded about node r' = r + s, s the integer nearest a/2, per node).  Differentiating
 // e^{theta q} by a, b or e multiplies it by theta x, theta x^2 or theta x^3,
 // which shifts the moments:
 //     dM_k/da = theta k M_{k-1},  dM_k/db = theta k (k-1) M_{k-2},
@@ -161,19 +161,16 @@ __global__ __launch_bounds__(T) void adj_taylor_kernel(const DevProb* __restrict
     const int sh = (int)rint(half);
     const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
     double W0[NN], W1[NN], Ga, Gb, Ge;
-    const int r0 = __builtin_amdgcn_readfirstlane(r);
-    if (__ballot(active && r != r0) == 0) {
-        const int s0 = __builtin_amdgcn_readfirstlane(sh);
-        int rp = r0 + s0;
-        rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
-        const double* __restrict__ Tr = tb + rp * (kMaxN * kMaxN);
-        if (rp == r0)
+    int rp = r + sh;
+    rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
+    const int r0 = __builtin_amdgcn_readfirstlane(r), rp0 = __builtin_amdgcn_readfirstlane(rp);
+    if (__ballot(active && (r != r0 || rp != rp0)) == 0) {  // one expansion row for the wavefront
+        const double* __restrict__ Tr = tb + rp0 * (kMaxN * kMaxN);
+        if (rp0 == r0)
             adj_taylor_node<NN, PP, false>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
         else
-            adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp - r0), dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
+            adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp0 - r0), dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
     } else {
-        int rp = r + sh;
-        rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
         adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp - r), dt, tb + rp * (kMaxN * kMaxN), U, V, W0, W1, Ga,
                                       Gb, Ge);
     }

@@ -29,9 +29,10 @@
 //     mu[k+1][m] = a mu[k][m-1] - s mu[k][m] + 2 b k mu[k-1][m-1] + 3 e k (k-1) mu[k-2][m-1],
 // taking T_k[r'] in place of T_k[r].  s is the integer nearest a / 2 (the
 // middle of the translation range [0, a] that theta sweeps), kept inside the
-// window.  Within a wavefront whose nodes share the harvest row (every
-// interior wavefront), one row and one shift serve all lanes, so the table row
-// is read through the scalar unit; other wavefronts use per-lane rows.
+// window; each node picks its own, so its result does not depend on which
+// wavefront it falls in.  When every lane of a wavefront expands about the
+// same row (every interior wavefront while |a| < 1, and most of them beyond),
+// the table row is read through the scalar unit; otherwise per lane.
 //
 // Layout: one thread per node, kTaylorTile consecutive nodes of one instance
 // per block.  With FUSE the block first stages u and the frozen-velocity
@@ -112,6 +113,28 @@ __device__ __forceinline__ void taylor_weights_d(bool disp, double a, double b, 
         taylor_weights<NN, SHIFT, false>(a, b, e, s, T, W0, W1);
 }
 
+// Weights of this lane's node (harvest row r, shift sh) with the expansion
+// row r + sh read through the scalar unit when the wavefront's active lanes
+// share it.  Lanes with the same (r, sh) get the same values either way.
+template <int NN>
+__device__ __forceinline__ void node_weights(bool active, int r, int sh, bool disp, double a, double b, double e,
+                                             const double* __restrict__ taylor, double (&W0)[NN],
+                                             double (&W1)[NN]) {
+    const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
+    int rp = r + sh;
+    rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
+    const int r0 = __builtin_amdgcn_readfirstlane(r), rp0 = __builtin_amdgcn_readfirstlane(rp);
+    if (__ballot(active && (r != r0 || rp != rp0)) == 0) {
+        const double* __restrict__ T = tb + rp0 * (kMaxN * kMaxN);
+        if (rp0 == r0)
+            taylor_weights_d<NN, false>(disp, a, b, e, 0.0, T, W0, W1);
+        else
+            taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp0 - r0), T, W0, W1);
+    } else {
+        taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp - r), tb + rp * (kMaxN * kMaxN), W0, W1);
+    }
+}
+
 template <int NN, bool FUSE>
 __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb* __restrict__ probs, int nprob,
                                                                    const double* __restrict__ fd,
@@ -181,22 +204,7 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
     const int sh = (int)rint(half);
 
     double W0[NN], W1[NN];
-    const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
-    const int r0 = __builtin_amdgcn_readfirstlane(r);
-    if (__ballot(active && r != r0) == 0) {
-        const int s0 = __builtin_amdgcn_readfirstlane(sh);
-        int rp = r0 + s0;
-        rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
-        const double* __restrict__ T = tb + rp * (kMaxN * kMaxN);
-        if (rp == r0)
-            taylor_weights_d<NN, false>(disp, a, b, e, 0.0, T, W0, W1);
-        else
-            taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp - r0), T, W0, W1);
-    } else {
-        int rp = r + sh;
-        rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
-        taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp - r), tb + rp * (kMaxN * kMaxN), W0, W1);
-    }
+    node_weights<NN>(active, r, sh, disp, a, b, e, taylor, W0, W1);
 #pragma unroll
     for (int j = 0; j < NN; ++j) W1[j] *= dt;
 
@@ -224,6 +232,120 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
     }
 }
 
+// Several frozen-velocity steps per launch (LMEP_F_PERSISTENT; centred
+// windows on Dirichlet or periodic grids).  A block stages reg <=
+// kTaylorRegion consecutive positions of its instance in LDS, advances them
+// ksteps <= kb steps there and writes the middle reg - 2 kb (n - 1) of them.
+// Each step spoils n - 1 positions at each open end of the valid range (a
+// node's window reaches (n-1)/2 positions and the frozen-velocity derivative
+// at a window position another (n-1)/2); at a Dirichlet end inside the region
+// the windows are clamped and nothing is spoilt.  Every node is formed by the
+// same expressions in the same order as in the one-step kernel (derivative
+// from the position's own window, weights of the node, stencil sum), so the
+// two paths agree bit for bit.
+template <int NN>
+__global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb* __restrict__ probs, int nprob,
+                                                                   int kb, int ksteps, int reg,
+                                                                   const double* __restrict__ fd,
+                                                                   const double* __restrict__ taylor,
+                                                                   const double* __restrict__ u_in,
+                                                                   double* __restrict__ u_out,
+                                                                   unsigned long long* __restrict__ stats) {
+    constexpr int R = (NN - 1) / 2;
+    constexpr int H = NN - 1;
+    constexpr int MAXR = kTaylorRegion;
+    __shared__ double lds[3 * MAXR];  // current u, next u, derivative: addressed by offsets
+    const int REG = reg;
+    const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const DevProb& P = probs[find_instance(probs, nprob, tile)];
+    const int64_t N = P.N;
+    const int halo = kb * H;
+    const int tw = REG - 2 * halo;  // nodes written per block
+    const int bc = P.bc;
+    const bool dir = bc == BC_DIRICHLET;
+    const int64_t own = (tile - P.item_begin) * tw;  // first node this block is responsible for
+    // On a Dirichlet grid the last block is moved back to end at node N - 1
+    // (it rewrites part of its neighbour's tile with the same values): a node
+    // next to an end has its window shifted inwards by up to (n-1)/2, and the
+    // derivatives at that window reach (n-1)/2 further, so a short last region
+    // would not hold what its nodes depend on.
+    const int64_t first = (dir && N >= tw && own > N - tw) ? N - tw : own;
+    const int64_t v0 = first - halo;  // grid position of slot 0
+    const double* __restrict__ us = u_in + P.state_off;
+    const double ih = 1.0 / P.h, g = P.nl_coef, dt = P.dt;
+    const bool disp = P.delta != 0.0;
+    const int tid = threadIdx.x;
+    if (stats && tid == 0) {
+        const int64_t wn = N - own < tw ? N - own : tw;
+        atomicAdd(stats, (unsigned long long)(wn * ksteps));
+    }
+    // slots holding grid nodes: on Dirichlet grids the part of the region inside the grid
+    const int g_lo = dir ? (int)(v0 < 0 ? -v0 : 0) : 0;
+    const int g_hi = dir ? (int)(N - v0 < REG ? N - v0 : REG) : REG;
+    int cu = 0, cn = MAXR;
+    const int cd = 2 * MAXR;
+    for (int t = tid; t < REG; t += kTaylorTile)
+        lds[cu + t] = (t >= g_lo && t < g_hi) ? us[map_index(v0 + t, N, bc)] : 0.0;
+    __syncthreads();
+    int lo = g_lo, hi = g_hi;  // slots whose current u is valid
+    for (int st = 0; st < ksteps; ++st) {
+        const bool lend = dir && v0 + lo == 0, rend = dir && v0 + hi == N;  // grid ends: nothing spoilt
+        const int nlo = lend ? lo : lo + H, nhi = rend ? hi : hi - H;      // slots updated this step
+        const int dlo = lend ? lo : lo + R, dhi = rend ? hi : hi - R;      // slots whose derivative they read
+        for (int t = dlo + tid; t < dhi; t += kTaylorTile) {
+            const int64_t j = map_index(v0 + t, N, bc);
+            const int oj = (int)window_offset(j, N, NN, bc);
+            const int rj = -oj;
+            double dv = 0.0;
+#pragma unroll
+            for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, rj, l)] * ih) * lds[cu + t + oj + l];
+            lds[cd + t] = dv;
+        }
+        __syncthreads();
+        for (int base = 0; base < REG; base += kTaylorTile) {
+            const int t = base + tid;
+            const bool active = t >= nlo && t < nhi;
+            if (__ballot(active) == 0) continue;  // the whole wavefront idles (uniform)
+            const int te = active ? t : nlo;     // idle lanes repeat a valid slot; their results are dropped
+            const int64_t i = map_index(v0 + te, N, bc);
+            const double ui = lds[cu + te];
+            const double ceff = P.c + g * ui;
+            const int o = (int)window_offset(i, N, NN, bc);
+            const int r = -o;
+            const double a = -ceff * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
+            const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
+            const int sh = (int)rint(half);
+            double W0[NN], W1[NN];
+            node_weights<NN>(active, r, sh, disp, a, b, e, taylor, W0, W1);
+#pragma unroll
+            for (int j = 0; j < NN; ++j) W1[j] *= dt;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < NN; ++j) {
+                const double uj = lds[cu + te + o + j];
+                const double Nj = -g * (uj - ui) * lds[cd + te + o + j];
+                acc = fma(W0[j], uj, acc);
+                acc = fma(W1[j], Nj, acc);
+            }
+            if (active) {
+                const bool fixed = dir && (i == 0 || i == N - 1);
+                lds[cn + t] = fixed ? (i == 0 ? P.bc_left : P.bc_right) : acc;
+            }
+        }
+        __syncthreads();
+        const int tmp = cu;
+        cu = cn;
+        cn = tmp;
+        lo = nlo;
+        hi = nhi;
+    }
+    double* __restrict__ uo = u_out + P.state_off;
+    for (int t = halo + tid; t < halo + tw; t += kTaylorTile) {
+        const int64_t node = v0 + t;
+        if (node < N) uo[node] = lds[cu + t];
+    }
+}
+
 template <int NN>
 hipError_t go_taylor(const DevProb* d_probs, int nprob, int64_t tiles, const double* fd, const double* taylor,
                      const double* d_u, double* d_w, unsigned long long* stats, double* d_u_out, hipStream_t stream) {
@@ -237,6 +359,26 @@ hipError_t go_taylor(const DevProb* d_probs, int nprob, int64_t tiles, const dou
 }
 
 }  // namespace
+
+hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb* d_probs, int nprob, int64_t tiles,
+                               const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
+                               unsigned long long* stats, hipStream_t stream) {
+    if (tiles <= 0) return hipSuccess;
+    if (tiles > 0x7fffffff || kb < 1 || kb > 8 || ksteps < 1 || ksteps > kb || reg < kTaylorTile ||
+        reg > kTaylorRegion || reg % kTaylorTile != 0 || taylor_stepk_tile(n, kb, reg) < 1)
+        return hipErrorInvalidValue;
+#define LMEP_TSK_CASE(NN)                                                                                         \
+    case NN:                                                                                                      \
+        hipLaunchKernelGGL((taylor_stepk_kernel<NN>), dim3((unsigned)tiles), dim3(kTaylorTile), 0, stream, d_probs, \
+                           nprob, kb, ksteps, reg, fd, taylor, d_u_in, d_u_out, stats);                           \
+        return hipGetLastError();
+    switch (n) {
+        LMEP_TSK_CASE(3) LMEP_TSK_CASE(5) LMEP_TSK_CASE(7) LMEP_TSK_CASE(9) LMEP_TSK_CASE(11) LMEP_TSK_CASE(13)
+        LMEP_TSK_CASE(15)
+        default: return hipErrorInvalidValue;
+    }
+#undef LMEP_TSK_CASE
+}
 
 hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd,
                                const double* taylor, const double* d_u, double* d_w, unsigned long long* stats,

@@ -230,6 +230,7 @@ DevProb to_dev(const lmep_problem& q, int index) {
 // one kernel variant.
 struct Group {
     int n = 0, p = 0, scheme = 0, nonlin = 0, tile = 0;
+    int reg = 0;             // multi-step finite-Taylor groups: staged positions per block
     bool taylor = false;     // build by finite Taylor series (items = kTaylorTile-node tiles)
     bool pernode = false;    // weights stored per node (frozen velocity or non-uniform grid)
     bool frozen = false;     // rebuilt every step (frozen velocity)
@@ -241,9 +242,12 @@ struct Group {
     int64_t items = 0;         // matrices (build) or tiles (apply)
 };
 
-// Build groups: keyed by (n, p).  Instances selected by `want`.
+// Build groups: keyed by (n, p).  Instances selected by `want`.  frozen_kb > 0:
+// finite-Taylor groups advance frozen_kb steps per launch (tiles of
+// taylor_stepk_tile(n, frozen_kb) nodes instead of kTaylorTile).
 template <class Want>
-std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want, std::vector<DevProb>& tab) {
+std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want, std::vector<DevProb>& tab,
+                              int frozen_kb = 0) {
     // one build part per exponential: ETDRK4 needs two (p = 3 at dt, p = 1 at dt/2)
     struct Part {
         int k, harvest;
@@ -267,6 +271,15 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         g.p = std::get<1>(kv.first);
         g.nonuniform = std::get<2>(kv.first) == 1;
         g.taylor = std::get<2>(kv.first) == 2;
+        if (g.taylor && frozen_kb > 0) {
+            // half-size regions for groups of under 2^20 nodes, whose blocks would
+            // otherwise not reach every CU, unless the halo would eat most of it
+            int64_t nodes = 0;
+            for (const Part& part : kv.second) nodes += prob[part.k].N;
+            g.reg = (nodes < kSmallGroupNodes && taylor_stepk_tile(g.n, frozen_kb, kTaylorRegion / 2) >= 128)
+                        ? kTaylorRegion / 2
+                        : kTaylorRegion;
+        }
         g.first = (int)tab.size();
         int64_t items = 0;
         for (const Part& part : kv.second) {
@@ -275,7 +288,8 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             d.harvest = part.harvest;
             if (part.harvest == HARVEST_RK4_HALF) d.dt = 0.5 * prob[part.k].dt;
             d.item_begin = items;
-            items += g.taylor ? (prob[part.k].N + kTaylorTile - 1) / kTaylorTile
+            const int64_t tt = frozen_kb > 0 ? taylor_stepk_tile(g.n, frozen_kb, g.reg) : kTaylorTile;
+            items += g.taylor ? (prob[part.k].N + tt - 1) / tt
                               : (pernode(prob[part.k]) ? prob[part.k].N : prob[part.k].n);
             tab.push_back(d);
         }
@@ -540,9 +554,9 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     const bool multi = (flags & LMEP_F_PERSISTENT) != 0;
     if (multi)
         for (int k = 0; k < count; ++k) {
-            if (frozen(prob[k]))
-                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs stationary weights (instance %d is "
-                            "BURGERS_FROZEN)", k);
+            if (frozen(prob[k]) && (!taylor(prob[k]) || prob[k].bc == LMEP_BC_NEUMANN))
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with BURGERS_FROZEN (instance %d) needs the "
+                            "finite-Taylor build (react = 0, LMEP_EXP_AUTO) on a Dirichlet or periodic grid", k);
             if (prob[k].window != LMEP_WIN_CENTRED)
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs centred windows (instance %d)", k);
             if (nonuniform(prob[k]) && prob[k].N > kResidentMaxN)
@@ -565,11 +579,11 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
 
     std::vector<DevProb> btab, atab;
     std::vector<int> tile_inst;
-    auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab);
+    const int kb = multi ? t_steps_per_launch.load() : 1;
+    auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab, multi ? kb : 0);
     const double* tay = nullptr;
     for (auto& gr : bgroups)
         if (gr.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
-    const int kb = multi ? t_steps_per_launch.load() : 1;
     auto agroups = plan_apply(prob, count, atab, tile_inst, multi ? kb : 0);
     // resident groups (small non-uniform instances) advance all n_steps from
     // d_u_in to d_u_out in the first iteration; when nothing else is in the
@@ -600,7 +614,8 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     }
 
-    const bool fuse = t_fuse_frozen.load() != 0;
+    // frozen-velocity groups under LMEP_F_PERSISTENT always take the fused multi-step kernel
+    const bool fuse = t_fuse_frozen.load() != 0 || multi;
     bool apply_launched = false;  // any apply kernel besides the fused ones
     for (auto& gr : agroups) apply_launched |= !(gr.frozen && fuse);
     auto enqueue = [&]() -> int {
@@ -614,7 +629,10 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
                 // in the same kernel (their apply groups are then skipped)
                 HIP_TRY(timer.mark(true, s, true));
                 for (auto& gr : bgroups) {
-                    if (gr.taylor)
+                    if (gr.taylor && multi)
+                        HIP_TRY(launch_taylor_stepk(gr.n, kb, std::min(kb, n_steps - st * kb), gr.reg, dbt + gr.first,
+                                                    gr.count, gr.items, fd, tay, src, dst, counters, s));
+                    else if (gr.taylor)
                         HIP_TRY(launch_build_taylor(gr.n, dbt + gr.first, gr.count, gr.items, fd, tay, src, d_w,
                                                     counters, s, fuse ? dst : nullptr));
                     else

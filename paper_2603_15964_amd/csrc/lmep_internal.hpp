@@ -83,6 +83,16 @@ constexpr int kTaylorTile = 256;
 hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd,
                                const double* taylor, const double* d_u, double* d_w, unsigned long long* stats,
                                hipStream_t stream, double* d_u_out = nullptr);
+// The same fused step, ksteps <= kb steps per launch (centred windows,
+// Dirichlet or periodic): a block stages `reg` positions (kTaylorRegion, or
+// half of it for groups too small to fill the GPU otherwise) and writes
+// taylor_stepk_tile(n, kb, reg) nodes; items = tiles of that size per instance.
+constexpr int kTaylorRegion = 512;
+__host__ __device__ constexpr int taylor_stepk_tile(int n, int kb, int reg) { return reg - 2 * kb * (n - 1); }
+static_assert(taylor_stepk_tile(15, 8, kTaylorRegion) >= 256, "halo too wide for the staged region");
+hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb* d_probs, int nprob, int64_t tiles,
+                               const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
+                               unsigned long long* stats, hipStream_t stream);
 
 // Stationary per-node weights of non-uniform grids (one node per wavefront,
 // matrices in LDS; p <= 2, n + p <= kMaxMWide).

@@ -6,9 +6,10 @@ keeps the fastest one whose result agrees with the default path:
 * frozen-velocity instances: the fused build-and-apply kernel or the
   build-then-apply pair (LMEP_OPT_FUSE_FROZEN), each with the finite-Taylor
   or the Pade exponential (LMEP_OPT_EXP_METHOD);
-* stationary instances: one step per launch, or LMEP_F_PERSISTENT with 1, 2,
-  4 or 8 steps per launch (LMEP_OPT_STEPS_PER_LAUNCH; non-uniform instances
-  held whole by a block run every step in one launch);
+* one step per launch, or LMEP_F_PERSISTENT with 1, 2, 4 or 8 steps per
+  launch (LMEP_OPT_STEPS_PER_LAUNCH; non-uniform instances held whole by a
+  block run every step in one launch; frozen-velocity instances through the
+  finite-Taylor multi-step kernel);
 * one-step launches: the apply tile, chosen by size or forced to 256 / 1024
   nodes (LMEP_OPT_APPLY_TILE).
 
@@ -84,8 +85,13 @@ def signature(problems) -> str:
 def candidates(problems):
     """Every configuration the library accepts for this batch."""
     frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
-    persistent_ok = not frozen and all(p.get("window", "centred") == "centred" for p in problems) and \
-        all(p.get("x") is None or int(p["N"]) <= 512 for p in problems)
+    # several steps per launch: centred windows; non-uniform instances held whole by a
+    # block; frozen velocity through the finite-Taylor multi-step kernel (no reaction
+    # term, Dirichlet or periodic)
+    persistent_ok = all(p.get("window", "centred") == "centred" for p in problems) and \
+        all(p.get("x") is None or int(p["N"]) <= 512 for p in problems) and \
+        all(p.get("nonlin") != "burgers_frozen" or (p["bc"] != "neumann" and p.get("react", 0.0) == 0.0)
+            for p in problems)
     nonuniform = any(p.get("x") is not None for p in problems)
     tiles = (0, 256, 1024) + ((64,) if nonuniform else ())
     out = []

@@ -103,12 +103,23 @@ def test_weight_counts_and_batch_packing():
 
 
 def test_multistep_flag_and_option():
-    """LMEP_F_PERSISTENT is refused for frozen-velocity weights before any
-    device work; the steps-per-launch option accepts 1, 2, 4 and 8 only."""
-    s = _structs()  # frozen-velocity Burgers
-    rc = lmep.library().lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 5,
-                                  lmep.LMEP_F_PERSISTENT, ctypes.c_void_p(256), 1 << 30, None)
-    assert rc == lmep.LMEP_ERR_UNSUPPORTED, lmep.lmep_last_error()
+    """LMEP_F_PERSISTENT is refused before any device work for frozen-velocity
+    instances the multi-step finite-Taylor kernel does not cover (Neumann
+    grids, a reaction term, the Pade method); the steps-per-launch option
+    accepts 1, 2, 4 and 8 only."""
+    lib = lmep.library()
+    for over in (dict(bc="neumann"), dict(react=0.5)):
+        s = _structs(**over)  # frozen-velocity Burgers
+        rc = lib.lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 5,
+                           lmep.LMEP_F_PERSISTENT, ctypes.c_void_p(256), 1 << 30, None)
+        assert rc == lmep.LMEP_ERR_UNSUPPORTED, (over, lmep.lmep_last_error())
+    lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_PADE)
+    try:
+        rc = lib.lmep_step(_structs(), 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 5,
+                           lmep.LMEP_F_PERSISTENT, ctypes.c_void_p(256), 1 << 30, None)
+        assert rc == lmep.LMEP_ERR_UNSUPPORTED, lmep.lmep_last_error()
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_AUTO)
     opt = lmep.LMEP_OPT_STEPS_PER_LAUNCH
     assert lmep.lmep_get_option(opt) == 8
     for bad in (0, 3, 5, 16, -8):

@@ -167,9 +167,13 @@ def test_multistep_uneven_batch_and_graph():
         assert state_rel_err(got[k], oracle.run(p, u0, steps)) <= 1e-10, k
 
 
-def test_multistep_rejects_frozen_weights():
-    _print_case("multistep rejects frozen")
+def test_multistep_rejects_uncovered_frozen_weights():
+    """Frozen velocity runs several steps per launch only through the
+    finite-Taylor multi-step kernel (Dirichlet or periodic grids); a Neumann
+    instance is refused."""
+    _print_case("multistep rejects frozen neumann")
     p, u0 = workloads.burgers(N=512)
+    p = dict(p, bc="neumann")
     b = lmep.Batch([p], device=DEV)
     w = b.empty_weights()
     with pytest.raises(lmep.LmepError) as e:

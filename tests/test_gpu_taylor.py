@@ -206,3 +206,57 @@ def test_taylor_counts_nodes_without_squarings():
         _run([p], [u], 3, flags=lmep.LMEP_F_COUNT)
         prof = lmep.lmep_profile_last()
     assert prof["matrices"] == 3 * 1000
+
+
+def _set_kb(kb):
+    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
+
+
+# groups under 2^20 nodes stage half-size regions (n <= 9 at 8 steps per launch); the
+# 1.1M-node cases take the full ones
+MULTI_CASES = [(7, "dirichlet", 3000), (7, "periodic", 2000), (3, "dirichlet", 700), (9, "periodic", 513),
+               (15, "dirichlet", 1200), (5, "dirichlet", 5), (9, "periodic", 9), (11, "periodic", 300),
+               (7, "dirichlet", 1100001), (9, "periodic", 1100000)]
+
+
+@pytest.mark.parametrize("n,bc,N", MULTI_CASES)
+def test_taylor_multistep_equals_one_step(n, bc, N):
+    """LMEP_F_PERSISTENT for frozen velocity: 1, 2, 4 or 8 fused steps per
+    launch (11 steps, so the last launch is short) equal the one-step fused
+    kernel bit for bit, including instances smaller than the halo."""
+    _print_case("taylor multistep", n, bc, N)
+    p, u = _problem(N, n, bc, cfl=1.0, seed=200 + n)
+    want = _run([p], [u], 11)[0]
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    try:
+        for kb in (1, 2, 4, 8):
+            _set_kb(kb)
+            got = _run([p], [u], 11, flags=lmep.LMEP_F_PERSISTENT)[0]
+            assert np.array_equal(got, want), kb
+    finally:
+        _set_kb(saved)
+
+
+def test_taylor_multistep_batch_graph_and_oracle():
+    """Uneven frozen-velocity batch at 8 steps per launch: equals the one-step
+    path per instance, graph replay equals eager, and 20 steps match the
+    oracle to 1e-10; a high-Courant-number instance exercises shifted
+    expansions inside the staged region."""
+    _print_case("taylor multistep batch")
+    cases = [_problem(4000, 7, "dirichlet", seed=301), _problem(777, 9, "periodic", seed=302),
+             _problem(300, 7, "dirichlet", cfl=1.5, seed=303), _problem(2048, 7, "periodic", cfl=1.2, rough=True,
+                                                                       seed=304)]
+    probs = [c[0] for c in cases]
+    states = [c[1] for c in cases]
+    one = _run(probs, states, 20)
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    try:
+        _set_kb(8)
+        multi = _run(probs, states, 20, flags=lmep.LMEP_F_PERSISTENT)
+        graph = _run(probs, states, 20, flags=lmep.LMEP_F_PERSISTENT | lmep.LMEP_F_GRAPH)
+    finally:
+        _set_kb(saved)
+    for k, (p, u) in enumerate(zip(probs, states)):
+        assert np.array_equal(multi[k], one[k]), k
+        assert np.array_equal(graph[k], one[k]), k
+        assert _state_err(multi[k], oracle.run(p, u, 20)) <= 1e-10, k

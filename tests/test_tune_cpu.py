@@ -35,7 +35,12 @@ def test_candidates_follow_what_the_library_accepts():
     assert {_opts(x)[LMEP_OPT_FUSE_FROZEN] for x in c} == {0, 1}
     assert {_opts(x)[LMEP_OPT_EXP_METHOD] for x in c} == {LMEP_EXP_AUTO, LMEP_EXP_PADE}
     assert _opts(c[0])[LMEP_OPT_EXP_METHOD] == LMEP_EXP_AUTO  # the default comes first (reference result)
-    assert not any(x.flags & LMEP_F_PERSISTENT for x in c)
+    # frozen velocity several steps per launch: the finite-Taylor multi-step kernel only
+    pers = [x for x in c if x.flags & LMEP_F_PERSISTENT]
+    assert {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in pers} == {1, 2, 4, 8}
+    assert all(_opts(x)[LMEP_OPT_EXP_METHOD] == LMEP_EXP_AUTO for x in pers)
+    neumann = [dict(frozen[0], bc="neumann")]
+    assert not any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(neumann))
     stat = [workloads.kdv(N=4096)[0]]
     assert {_opts(x)[LMEP_OPT_EXP_METHOD] for x in tune.candidates(stat)} == {LMEP_EXP_AUTO}
     kbs = {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in tune.candidates(stat) if x.flags & LMEP_F_PERSISTENT}
