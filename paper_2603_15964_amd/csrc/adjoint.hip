@@ -168,18 +168,24 @@ __device__ __forceinline__ void solve_pair(Pair<M>& Q, Pair<M>& P, int lane) {
 
 // ------------------------------------------------------------- kernels ----
 // du/dx at every node from its own stencil (row r_j of D1).
+template <int NN>
 __global__ void adj_prep_kernel(const DevProb* __restrict__ probs, int nprob, const double* __restrict__ fd,
                                 const double* __restrict__ u_all, double* __restrict__ g_all) {
+    constexpr int R = (NN - 1) / 2;
     const int64_t tile = blockIdx.x;
     const DevProb& P = probs[find_instance(probs, nprob, tile)];
     const int64_t j = (tile - P.item_begin) * T + threadIdx.x;
     if (j >= P.N) return;
-    const int n = P.n;
     const double* u = u_all + P.state_off;
-    const int64_t o = window_offset(j, P.N, n, P.bc);
-    const int r = (int)(-o);
     double acc = 0.0;
-    for (int k = 0; k < n; ++k) acc += fd[fd_index(n, 0, r, k)] * u[map_index(j + o + k, P.N, P.bc)];
+    if (j >= R && j + R <= P.N - 1) {  // centred and inside the grid: no clamp, wrap or mirror
+#pragma unroll
+        for (int k = 0; k < NN; ++k) acc += fd[fd_index(NN, 0, R, k)] * u[j - R + k];
+    } else {
+        const int64_t o = window_offset(j, P.N, NN, P.bc);
+        const int r = (int)(-o);
+        for (int k = 0; k < NN; ++k) acc += fd[fd_index(NN, 0, r, k)] * u[map_index(j + o + k, P.N, P.bc)];
+    }
     g_all[P.state_off + j] = acc / P.h;
 }
 
@@ -331,38 +337,54 @@ __device__ __forceinline__ void for_each_stencil_containing(int64_t j, int64_t N
     }
 }
 
+// Nodes j whose gathers see only interior nodes: every node within n - 1 of
+// j has a centred window, none is a held Dirichlet end, no Neumann mirror or
+// periodic wrap is involved.  The stencils containing j are then those of
+// i = j + d, d = -(n-1)/2 .. (n-1)/2, at position k = (n-1)/2 - d -- the same
+// terms, in the same order (d ascending), that for_each_stencil_containing
+// visits, so the fast paths below agree with it bit for bit.
+__device__ __forceinline__ bool gather_interior(int64_t j, int64_t N, int n) {
+    return j >= 2 * (n - 1) && j <= N - 1 - 2 * (n - 1);
+}
+
 // ghat_m = sum_{i : m in S_i} lam_i W1_i[k] (-g)(u_m - u_i)
+template <int NN>
 __global__ void adj_ghat_kernel(const DevProb* __restrict__ probs, int nprob, const double* __restrict__ u_all,
                                 const double* __restrict__ lam_all, const double* __restrict__ ws, int ws_stride,
                                 double* __restrict__ ghat_all) {
+    constexpr int R = (NN - 1) / 2;
     const int64_t tile = blockIdx.x;
     const DevProb& P = probs[find_instance(probs, nprob, tile)];
     const int64_t m = (tile - P.item_begin) * T + threadIdx.x;
     if (m >= P.N) return;
-    const int n = P.n;
     const int64_t N = P.N;
     const double* u = u_all + P.state_off;
     const double* lam = lam_all + P.state_off;
     const double* wsb = ws + P.state_off * (int64_t)ws_stride;
     const double um = u[m], g = P.nl_coef;
     double acc = 0.0;
-    for_each_stencil_containing(m, N, n, P.bc, [&](int64_t i, int k) {
-        acc += lam[i] * wsb[(int64_t)(n + k) * N + i] * (-g) * (um - u[i]);
-    });
+    auto term = [&](int64_t i, int k) { acc += lam[i] * wsb[(int64_t)(NN + k) * N + i] * (-g) * (um - u[i]); };
+    if (gather_interior(m, N, NN)) {
+#pragma unroll
+        for (int d = -R; d <= R; ++d) term(m + d, R - d);
+    } else {
+        for_each_stencil_containing(m, N, NN, P.bc, term);
+    }
     ghat_all[P.state_off + m] = acc;
 }
 
 // lam_k at node j.
+template <int NN>
 __global__ void adj_lambda_kernel(const DevProb* __restrict__ probs, int nprob, const double* __restrict__ fd,
                                   const double* __restrict__ u_all, const double* __restrict__ lam_all,
                                   const double* __restrict__ ws, int ws_stride, const double* __restrict__ g_all,
                                   const double* __restrict__ ghat_all, const double* __restrict__ dparam,
                                   double* __restrict__ out_all) {
+    constexpr int n = NN, R = (NN - 1) / 2;
     const int64_t tile = blockIdx.x;
     const DevProb& P = probs[find_instance(probs, nprob, tile)];
     const int64_t j = (tile - P.item_begin) * T + threadIdx.x;
     if (j >= P.N) return;
-    const int n = P.n;
     const int64_t N = P.N;
     const int bc = P.bc;
     const double* u = u_all + P.state_off;
@@ -373,44 +395,60 @@ __global__ void adj_lambda_kernel(const DevProb* __restrict__ probs, int nprob, 
     const double gc = P.nl_coef;
     const bool etd = P.scheme == SCH_ETD1;
     const double uj = u[j];
+    const bool inner = gather_interior(j, N, n);
     // d N^(i)_j / d u_j (the same for every i): frozen Burgers -g g_j, Allen-Cahn g (1 - 3 u_j^2)
     double dNj = 0.0;
     if (etd && P.nonlin == NL_BURGERS) dNj = -gc * g[j];
     if (etd && P.nonlin == NL_AC) dNj = gc * (1.0 - 3.0 * uj * uj);
     double acc = 0.0;
-    for_each_stencil_containing(j, N, n, bc, [&](int64_t i, int k) {
+    auto term = [&](int64_t i, int k) {
         double w = wsb[(int64_t)k * N + i];
         if (etd) w += dNj * wsb[(int64_t)(n + k) * N + i];
         acc += lam[i] * w;
-    });
+    };
+    if (inner) {
+#pragma unroll
+        for (int d = -R; d <= R; ++d) term(j + d, R - d);
+    } else {
+        for_each_stencil_containing(j, N, n, bc, term);
+    }
     const bool fixed = (bc == BC_DIRICHLET) && (j == 0 || j == N - 1);
     if (P.nonlin == NL_BURGERS && !fixed) {
         // node j's own value: in N^(j) (+g (du/dx)_{j_k} through -g(u_{j_k} - u_j)) and in c_j = c + g u_j
-        const int64_t o = window_offset(j, N, n, bc);
         double s = 0.0;
-        for (int k = 0; k < n; ++k) s += wsb[(int64_t)(n + k) * N + j] * g[map_index(j + o + k, N, bc)];
+        if (inner) {
+#pragma unroll
+            for (int k = 0; k < n; ++k) s += wsb[(int64_t)(n + k) * N + j] * g[j - R + k];
+        } else {
+            const int64_t o = window_offset(j, N, n, bc);
+            for (int k = 0; k < n; ++k) s += wsb[(int64_t)(n + k) * N + j] * g[map_index(j + o + k, N, bc)];
+        }
         acc += lam[j] * gc * s + gc * dparam[3 * P.state_off + N + j];
     }
     if (P.nonlin == NL_BURGERS) {
         // through du/dx at the nodes m whose own stencil contains j: ghat_m D1[r_m][l] / h
         const double ih = 1.0 / P.h;
-        const int R = (n - 1) / 2;
-        int64_t ps[3];
-        int np = 0;
-        ps[np++] = j;
-        if (bc == BC_NEUMANN) {
-            if (j > 0 && j <= 2 * R) ps[np++] = -j;
-            if (j < N - 1 && j >= N - 1 - 2 * R) ps[np++] = 2 * (N - 1) - j;
-        }
-        for (int q = 0; q < np; ++q) {
-            for (int d = -(n - 1); d <= n - 1; ++d) {
-                int64_t m = ps[q] + d;
-                if (bc == BC_PERIODIC) m = map_index(m, N, bc);
-                else if (m < 0 || m > N - 1) continue;
-                const int64_t o = window_offset(m, N, n, bc);
-                const int64_t l = -d - o;
-                if (l < 0 || l >= n) continue;
-                acc += ghat[m] * fd[fd_index(n, 0, (int)(-o), (int)l)] * ih;
+        if (inner) {
+#pragma unroll
+            for (int d = -R; d <= R; ++d) acc += ghat[j + d] * fd[fd_index(n, 0, R, R - d)] * ih;
+        } else {
+            int64_t ps[3];
+            int np = 0;
+            ps[np++] = j;
+            if (bc == BC_NEUMANN) {
+                if (j > 0 && j <= 2 * R) ps[np++] = -j;
+                if (j < N - 1 && j >= N - 1 - 2 * R) ps[np++] = 2 * (N - 1) - j;
+            }
+            for (int q = 0; q < np; ++q) {
+                for (int d = -(n - 1); d <= n - 1; ++d) {
+                    int64_t m = ps[q] + d;
+                    if (bc == BC_PERIODIC) m = map_index(m, N, bc);
+                    else if (m < 0 || m > N - 1) continue;
+                    const int64_t o = window_offset(m, N, n, bc);
+                    const int64_t l = -d - o;
+                    if (l < 0 || l >= n) continue;
+                    acc += ghat[m] * fd[fd_index(n, 0, (int)(-o), (int)l)] * ih;
+                }
             }
         }
     }
@@ -475,6 +513,25 @@ hipError_t frechet_n(const AdjointLaunch& a, hipStream_t s) {
     return a.p == 0 ? frechet_np<NN, 0>(a, s) : frechet_np<NN, 1>(a, s);
 }
 
+template <int NN>
+hipError_t prep_n(const AdjointLaunch& a, hipStream_t s) {
+    hipLaunchKernelGGL((adj_prep_kernel<NN>), dim3((unsigned)a.tiles), dim3(T), 0, s, a.tile_probs, a.nprob, a.fd,
+                       a.u, a.g);
+    return hipGetLastError();
+}
+
+// The two gathers of the reverse step (ghat, then lambda_k), specialised on n.
+template <int NN>
+hipError_t gathers_n(const AdjointLaunch& a, hipStream_t s) {
+    hipLaunchKernelGGL((adj_ghat_kernel<NN>), dim3((unsigned)a.tiles), dim3(T), 0, s, a.tile_probs, a.nprob, a.u,
+                       a.lam, a.ws, a.ws_stride, a.ghat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((adj_lambda_kernel<NN>), dim3((unsigned)a.tiles), dim3(T), 0, s, a.tile_probs, a.nprob, a.fd,
+                       a.u, a.lam, a.ws, a.ws_stride, a.g, a.ghat, a.dparam, a.lam_out);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
@@ -482,9 +539,17 @@ hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
     const dim3 blk(T);
     if (a.tiles <= 0) return hipSuccess;
     // one group (same n and p) per call
-    hipLaunchKernelGGL(adj_prep_kernel, dim3((unsigned)a.tiles), blk, 0, s, a.tile_probs, a.nprob, a.fd, a.u,
-                       a.g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    switch (a.n) {
+        case 3: e = prep_n<3>(a, s); break;
+        case 5: e = prep_n<5>(a, s); break;
+        case 7: e = prep_n<7>(a, s); break;
+        case 9: e = prep_n<9>(a, s); break;
+        case 11: e = prep_n<11>(a, s); break;
+        case 13: e = prep_n<13>(a, s); break;
+        case 15: e = prep_n<15>(a, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
     if (a.frechet_begin && (e = hipEventRecord(a.frechet_begin, s)) != hipSuccess) return e;
     if (a.taylor) {
         e = launch_adj_taylor(a, s);
@@ -502,12 +567,17 @@ hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
     }
     if (e != hipSuccess) return e;
     if (a.frechet_end && (e = hipEventRecord(a.frechet_end, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(adj_ghat_kernel, dim3((unsigned)a.tiles), blk, 0, s, a.tile_probs, a.nprob, a.u, a.lam, a.ws,
-                       a.ws_stride, a.ghat);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(adj_lambda_kernel, dim3((unsigned)a.tiles), blk, 0, s, a.tile_probs, a.nprob, a.fd, a.u, a.lam,
-                       a.ws, a.ws_stride, a.g, a.ghat, a.dparam, a.lam_out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    switch (a.n) {
+        case 3: e = gathers_n<3>(a, s); break;
+        case 5: e = gathers_n<5>(a, s); break;
+        case 7: e = gathers_n<7>(a, s); break;
+        case 9: e = gathers_n<9>(a, s); break;
+        case 11: e = gathers_n<11>(a, s); break;
+        case 13: e = gathers_n<13>(a, s); break;
+        case 15: e = gathers_n<15>(a, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(adj_reduce_tiles, dim3((unsigned)a.tiles), blk, 0, s, a.tile_probs, a.nprob, a.dparam, a.part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(adj_reduce_instances, dim3((unsigned)a.nprob), blk, 0, s, a.tile_probs, a.nprob, a.part,
