@@ -85,8 +85,9 @@ enum { LMEP_NL_NONE = 0, LMEP_NL_BURGERS_FROZEN = 1, LMEP_NL_KDV = 2, LMEP_NL_AL
  * 13 / 15.
  * Frozen-velocity weights (rebuilt every step) are not balanced: ~1e-12 for
  * n = 7 across its band.  UPWIND is supported for LINEAR,
- * ETD1 and ETD2RK with the one-step kernels; ETDRK4, LMEP_F_PERSISTENT and
- * the reverse step return LMEP_ERR_UNSUPPORTED. */
+ * ETD1 and ETD2RK with the one-step kernels, and for BURGERS_FROZEN also
+ * under LMEP_F_PERSISTENT; ETDRK4, LMEP_F_PERSISTENT with stationary weights
+ * and the reverse step return LMEP_ERR_UNSUPPORTED. */
 enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
 
 /* lmep_step flags */
@@ -96,8 +97,11 @@ enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
                                   /* LMEP_OPT_STEPS_PER_LAUNCH), so                             */
                                   /* HBM is read and written once per launch instead of once    */
                                   /* per step; same result bit for bit as the one-step path.    */
-                                  /* Stationary weights only (LMEP_ERR_UNSUPPORTED if any       */
-                                  /* instance is BURGERS_FROZEN).  Non-uniform instances of at  */
+                                  /* Stationary weights: centred windows.  BURGERS_FROZEN:      */
+                                  /* the fused finite-Taylor build and step (react = 0,         */
+                                  /* LMEP_EXP_AUTO) on Dirichlet or periodic grids, centred or  */
+                                  /* upwind windows; other frozen-velocity instances are        */
+                                  /* LMEP_ERR_UNSUPPORTED.  Non-uniform instances of at         */
                                   /* most 512 nodes are held whole by one block each (weights   */
                                   /* in registers) for all n_steps (launches of up to 65536     */
                                   /* steps); larger ones are LMEP_ERR_UNSUPPORTED.              */

@@ -232,14 +232,15 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
     }
 }
 
-// Several frozen-velocity steps per launch (LMEP_F_PERSISTENT; centred
-// windows on Dirichlet or periodic grids).  A block stages reg <=
+// Several frozen-velocity steps per launch (LMEP_F_PERSISTENT; centred or
+// one-sided windows on Dirichlet or periodic grids).  A block stages reg <=
 // kTaylorRegion consecutive positions of its instance in LDS, advances them
 // ksteps <= kb steps there and writes the middle reg - 2 kb (n - 1) of them.
 // Each step spoils n - 1 positions at each open end of the valid range (a
 // node's window reaches (n-1)/2 positions and the frozen-velocity derivative
-// at a window position another (n-1)/2); at a Dirichlet end inside the region
-// the windows are clamped and nothing is spoilt.  Every node is formed by the
+// at a window position another (n-1)/2), 2 (n - 1) with one-sided windows; at
+// a Dirichlet end inside the region the windows are clamped and nothing is
+// spoilt.  Every node is formed by the
 // same expressions in the same order as in the one-step kernel (derivative
 // from the position's own window, weights of the node, stencil sum), so the
 // two paths agree bit for bit.
@@ -259,7 +260,9 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
     const DevProb& P = probs[find_instance(probs, nprob, tile)];
     const int64_t N = P.N;
-    const int halo = kb * H;
+    const bool upw = P.window == WIN_UPWIND;
+    const int rw = upw ? H : R;       // reach of a window and of a derivative's window
+    const int halo = kb * taylor_stepk_reach(NN, upw);
     const int tw = REG - 2 * halo;  // nodes written per block
     const int bc = P.bc;
     const bool dir = bc == BC_DIRICHLET;
@@ -290,15 +293,20 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
     int lo = g_lo, hi = g_hi;  // slots whose current u is valid
     for (int st = 0; st < ksteps; ++st) {
         const bool lend = dir && v0 + lo == 0, rend = dir && v0 + hi == N;  // grid ends: nothing spoilt
-        const int nlo = lend ? lo : lo + H, nhi = rend ? hi : hi - H;      // slots updated this step
-        const int dlo = lend ? lo : lo + R, dhi = rend ? hi : hi - R;      // slots whose derivative they read
+        const int nlo = lend ? lo : lo + 2 * rw, nhi = rend ? hi : hi - 2 * rw;  // slots updated this step
+        const int dlo = lend ? lo : lo + rw, dhi = rend ? hi : hi - rw;          // slots whose derivative they read
         for (int t = dlo + tid; t < dhi; t += kTaylorTile) {
             const int64_t j = map_index(v0 + t, N, bc);
-            const int oj = (int)window_offset(j, N, NN, bc);
-            const int rj = -oj;
+            const int oj = (int)window_offset(j, N, NN, bc, P.window, P.c + g * lds[cu + t]);
             double dv = 0.0;
+            if (oj == -R) {  // centred: a compile-time row, loaded once outside the step loop
 #pragma unroll
-            for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, rj, l)] * ih) * lds[cu + t + oj + l];
+                for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, R, l)] * ih) * lds[cu + t - R + l];
+            } else {
+                const int rj = -oj;
+#pragma unroll
+                for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, rj, l)] * ih) * lds[cu + t + oj + l];
+            }
             lds[cd + t] = dv;
         }
         __syncthreads();
@@ -310,7 +318,7 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
             const int64_t i = map_index(v0 + te, N, bc);
             const double ui = lds[cu + te];
             const double ceff = P.c + g * ui;
-            const int o = (int)window_offset(i, N, NN, bc);
+            const int o = (int)window_offset(i, N, NN, bc, P.window, ceff);
             const int r = -o;
             const double a = -ceff * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
             const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
@@ -365,7 +373,7 @@ hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb
                                unsigned long long* stats, hipStream_t stream) {
     if (tiles <= 0) return hipSuccess;
     if (tiles > 0x7fffffff || kb < 1 || kb > 8 || ksteps < 1 || ksteps > kb || reg < kTaylorTile ||
-        reg > kTaylorRegion || reg % kTaylorTile != 0 || taylor_stepk_tile(n, kb, reg) < 1)
+        reg > kTaylorRegion || reg % kTaylorTile != 0 || taylor_stepk_tile(n, kb, reg, false) < 1)
         return hipErrorInvalidValue;
 #define LMEP_TSK_CASE(NN)                                                                                         \
     case NN:                                                                                                      \

@@ -275,8 +275,12 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             // half-size regions for groups of under 2^20 nodes, whose blocks would
             // otherwise not reach every CU, unless the halo would eat most of it
             int64_t nodes = 0;
-            for (const Part& part : kv.second) nodes += prob[part.k].N;
-            g.reg = (nodes < kSmallGroupNodes && taylor_stepk_tile(g.n, frozen_kb, kTaylorRegion / 2) >= 128)
+            bool upwind = false;
+            for (const Part& part : kv.second) {
+                nodes += prob[part.k].N;
+                upwind |= prob[part.k].window == LMEP_WIN_UPWIND;
+            }
+            g.reg = (nodes < kSmallGroupNodes && taylor_stepk_tile(g.n, frozen_kb, kTaylorRegion / 2, upwind) >= 128)
                         ? kTaylorRegion / 2
                         : kTaylorRegion;
         }
@@ -288,7 +292,9 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             d.harvest = part.harvest;
             if (part.harvest == HARVEST_RK4_HALF) d.dt = 0.5 * prob[part.k].dt;
             d.item_begin = items;
-            const int64_t tt = frozen_kb > 0 ? taylor_stepk_tile(g.n, frozen_kb, g.reg) : kTaylorTile;
+            const int64_t tt = frozen_kb > 0 ? taylor_stepk_tile(g.n, frozen_kb, g.reg,
+                                                                 prob[part.k].window == LMEP_WIN_UPWIND)
+                                             : kTaylorTile;
             items += g.taylor ? (prob[part.k].N + tt - 1) / tt
                               : (pernode(prob[part.k]) ? prob[part.k].N : prob[part.k].n);
             tab.push_back(d);
@@ -557,8 +563,9 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
             if (frozen(prob[k]) && (!taylor(prob[k]) || prob[k].bc == LMEP_BC_NEUMANN))
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with BURGERS_FROZEN (instance %d) needs the "
                             "finite-Taylor build (react = 0, LMEP_EXP_AUTO) on a Dirichlet or periodic grid", k);
-            if (prob[k].window != LMEP_WIN_CENTRED)
-                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT needs centred windows (instance %d)", k);
+            if (prob[k].window != LMEP_WIN_CENTRED && !frozen(prob[k]))
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with stationary weights needs centred windows "
+                            "(instance %d)", k);
             if (nonuniform(prob[k]) && prob[k].N > kResidentMaxN)
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT on a non-uniform grid needs N <= %d "
                             "(instance %d)", kResidentMaxN, k);

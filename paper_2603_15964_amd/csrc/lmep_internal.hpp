@@ -83,13 +83,20 @@ constexpr int kTaylorTile = 256;
 hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd,
                                const double* taylor, const double* d_u, double* d_w, unsigned long long* stats,
                                hipStream_t stream, double* d_u_out = nullptr);
-// The same fused step, ksteps <= kb steps per launch (centred windows,
-// Dirichlet or periodic): a block stages `reg` positions (kTaylorRegion, or
-// half of it for groups too small to fill the GPU otherwise) and writes
-// taylor_stepk_tile(n, kb, reg) nodes; items = tiles of that size per instance.
+// The same fused step, ksteps <= kb steps per launch (Dirichlet or periodic):
+// a block stages `reg` positions (kTaylorRegion, or half of it for groups too
+// small to fill the GPU otherwise) and writes taylor_stepk_tile(n, kb, reg,
+// upwind) nodes; items = tiles of that size per instance.  A step spoils
+// n - 1 positions at an open end with centred windows and 2 (n - 1) with
+// one-sided ones (the window and the derivative at its positions each reach
+// that far to one side).
 constexpr int kTaylorRegion = 512;
-__host__ __device__ constexpr int taylor_stepk_tile(int n, int kb, int reg) { return reg - 2 * kb * (n - 1); }
-static_assert(taylor_stepk_tile(15, 8, kTaylorRegion) >= 256, "halo too wide for the staged region");
+__host__ __device__ constexpr int taylor_stepk_reach(int n, bool upwind) { return upwind ? 2 * (n - 1) : n - 1; }
+__host__ __device__ constexpr int taylor_stepk_tile(int n, int kb, int reg, bool upwind) {
+    return reg - 2 * kb * taylor_stepk_reach(n, upwind);
+}
+static_assert(taylor_stepk_tile(15, 8, kTaylorRegion, false) >= 256, "halo too wide for the staged region");
+static_assert(taylor_stepk_tile(15, 8, kTaylorRegion, true) >= 32, "halo too wide for the staged region");
 hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb* d_probs, int nprob, int64_t tiles,
                                const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
                                unsigned long long* stats, hipStream_t stream);

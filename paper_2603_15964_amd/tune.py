@@ -85,13 +85,12 @@ def signature(problems) -> str:
 def candidates(problems):
     """Every configuration the library accepts for this batch."""
     frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
-    # several steps per launch: centred windows; non-uniform instances held whole by a
-    # block; frozen velocity through the finite-Taylor multi-step kernel (no reaction
-    # term, Dirichlet or periodic)
-    persistent_ok = all(p.get("window", "centred") == "centred" for p in problems) and \
-        all(p.get("x") is None or int(p["N"]) <= 512 for p in problems) and \
-        all(p.get("nonlin") != "burgers_frozen" or (p["bc"] != "neumann" and p.get("react", 0.0) == 0.0)
-            for p in problems)
+    # several steps per launch: stationary weights on centred windows (non-uniform
+    # instances held whole by a block); frozen velocity through the finite-Taylor
+    # multi-step kernel (no reaction term, Dirichlet or periodic, either window)
+    persistent_ok = all(p.get("x") is None or int(p["N"]) <= 512 for p in problems) and \
+        all((p["bc"] != "neumann" and p.get("react", 0.0) == 0.0) if p.get("nonlin") == "burgers_frozen"
+            else p.get("window", "centred") == "centred" for p in problems)
     nonuniform = any(p.get("x") is not None for p in problems)
     tiles = (0, 256, 1024) + ((64,) if nonuniform else ())
     out = []

@@ -260,3 +260,44 @@ def test_taylor_multistep_batch_graph_and_oracle():
         assert np.array_equal(multi[k], one[k]), k
         assert np.array_equal(graph[k], one[k]), k
         assert _state_err(multi[k], oracle.run(p, u, 20)) <= 1e-10, k
+
+
+# frozen upwind stencils are stable only for small n (n = 9 blows up on these fields)
+UPWIND_MULTI = [(5, "periodic", 2000, 1.5), (7, "dirichlet", 3000, 1.5), (5, "periodic", 700, 2.0),
+                (3, "dirichlet", 700, 1.0), (7, "periodic", 1100000, 1.5)]
+
+
+@pytest.mark.parametrize("n,bc,N,cfl", UPWIND_MULTI)
+def test_taylor_multistep_upwind_equals_one_step(n, bc, N, cfl):
+    """One-sided windows under LMEP_F_PERSISTENT (halo 2 (n - 1) per step):
+    1, 2, 4 and 8 steps per launch equal the one-step fused kernel bit for
+    bit over 11 steps."""
+    _print_case("taylor multistep upwind", n, bc, N, cfl)
+    p, u = _problem(N, n, bc, "upwind", cfl=cfl, seed=400 + n)
+    want = _run([p], [u], 11)[0]
+    assert np.all(np.isfinite(want))
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    try:
+        for kb in (1, 2, 4, 8):
+            _set_kb(kb)
+            got = _run([p], [u], 11, flags=lmep.LMEP_F_PERSISTENT)[0]
+            assert np.array_equal(got, want), kb
+    finally:
+        _set_kb(saved)
+
+
+def test_taylor_multistep_upwind_workload_and_oracle():
+    """The upwind Burgers workload (N = 65536, n = 7, CFL 3.5) at 8 steps per
+    launch: equal to the one-step path, and 5 steps match the oracle."""
+    _print_case("taylor multistep upwind workload")
+    p, u = workloads.burgers_upwind()
+    one = _run([p], [u], 16)[0]
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    try:
+        _set_kb(8)
+        multi = _run([p], [u], 16, flags=lmep.LMEP_F_PERSISTENT)[0]
+        five = _run([p], [u], 5, flags=lmep.LMEP_F_PERSISTENT)[0]
+    finally:
+        _set_kb(saved)
+    assert np.array_equal(multi, one)
+    assert _state_err(five, oracle.run(p, u, 5)) <= 1e-10

@@ -45,8 +45,10 @@ def test_candidates_follow_what_the_library_accepts():
     assert {_opts(x)[LMEP_OPT_EXP_METHOD] for x in tune.candidates(stat)} == {LMEP_EXP_AUTO}
     kbs = {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in tune.candidates(stat) if x.flags & LMEP_F_PERSISTENT}
     assert kbs == {1, 2, 4, 8}
-    upwind = [workloads.burgers_upwind(N=1000)[0]]
-    assert not any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(upwind))
+    upwind = [workloads.burgers_upwind(N=1000)[0]]  # frozen velocity: the multi-step Taylor kernel takes it
+    assert any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(upwind))
+    ac_upwind = [dict(workloads.allen_cahn_batch(count=1)[0][0], window="upwind")]
+    assert not any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(ac_upwind))
     cheb = [workloads.allen_cahn_chebyshev()[0]]
     cc = tune.candidates(cheb)
     assert sum(1 for x in cc if x.flags & LMEP_F_PERSISTENT) == 1
