@@ -231,6 +231,15 @@ def adj_taylor_flops(n: int, p: int) -> float:
     return float(rec + sums + con + der + nval + out)
 
 
+def adj_fused_flops(n: int, p: int) -> float:
+    """Algorithmic flops per node of the fused reverse-step kernel: the
+    per-node part (adj_taylor_flops) and the two gathers over the n stencils
+    containing the node -- ghat (5 per term) and lambda (4 per term, the own
+    window's n multiply-adds, and 3 per ghat term) -- halo recomputation not
+    counted."""
+    return adj_taylor_flops(n, p) + (5 + 4 + 2 + 3) * n
+
+
 def adjoint_roofline(problems, states, reps: int = 5):
     """Roofline of the per-node kernel of the reverse step (finite Taylor
     series, or the Frechet derivative by the block-triangular Pade exponential
@@ -264,8 +273,9 @@ def adjoint_roofline(problems, states, reps: int = 5):
     taylor = (lmep.lmep_get_option(lmep.LMEP_OPT_EXP_METHOD) == lmep.LMEP_EXP_AUTO and
               all(p.get("react", 0.0) == 0.0 for p in problems))
     if taylor:
-        flops = batch.state_size * adj_taylor_flops(p0["n"], m - p0["n"]) * reps
-        kname = f"adj_taylor_kernel<{p0['n']},{m - p0['n']}>"
+        # the whole reverse step of a tile in one kernel (per-node part and gathers)
+        flops = batch.state_size * adj_fused_flops(p0["n"], m - p0["n"]) * reps
+        kname = f"adj_fused_kernel<{p0['n']},{m - p0['n']}>"
         mean_s = 0.0
     else:
         flops = batch.state_size * pair_pade_flops(m, mean_s) * reps

@@ -22,8 +22,9 @@
 // Kernels (all deterministic, no atomics):
 //   adj_prep     du/dx at every node from its own stencil (frozen velocity)
 //   adj_frechet  per node: W0, W1 of E_i and the three contractions of F_i
-//                (or adj_taylor_kernel, the same from the finite Taylor series,
-//                adjoint_taylor.hip)
+//                (instances without a reaction term take adj_fused_kernel of
+//                adjoint_taylor.hip instead: the same from the finite Taylor
+//                series, with the gathers below, in one kernel per tile)
 //   adj_ghat     ghat_m = sum_i lam_i W1_i[k] (-g)(u_m - u_i) over stencils S_i
 //                containing m (adjoint of du/dx at m)
 //   adj_lambda   lam_k by the transposed banded apply (gather over the
@@ -337,16 +338,6 @@ __device__ __forceinline__ void for_each_stencil_containing(int64_t j, int64_t N
     }
 }
 
-// Nodes j whose gathers see only interior nodes: every node within n - 1 of
-// j has a centred window, none is a held Dirichlet end, no Neumann mirror or
-// periodic wrap is involved.  The stencils containing j are then those of
-// i = j + d, d = -(n-1)/2 .. (n-1)/2, at position k = (n-1)/2 - d -- the same
-// terms, in the same order (d ascending), that for_each_stencil_containing
-// visits, so the fast paths below agree with it bit for bit.
-__device__ __forceinline__ bool gather_interior(int64_t j, int64_t N, int n) {
-    return j >= 2 * (n - 1) && j <= N - 1 - 2 * (n - 1);
-}
-
 // ghat_m = sum_{i : m in S_i} lam_i W1_i[k] (-g)(u_m - u_i)
 template <int NN>
 __global__ void adj_ghat_kernel(const DevProb* __restrict__ probs, int nprob, const double* __restrict__ u_all,
@@ -475,14 +466,16 @@ __global__ void adj_reduce_tiles(const DevProb* __restrict__ probs, int nprob, c
 }
 
 // Stage 2: one block per instance sums its tiles in order and adds to grad.
+// tile_nodes: nodes per tile of the kernel that wrote part[] (item_begin = the
+// instance's first tile).
 __global__ void adj_reduce_instances(const DevProb* __restrict__ probs, int nprob, const double* __restrict__ part,
-                                     double* __restrict__ grad) {
+                                     int tile_nodes, double* __restrict__ grad) {
     __shared__ double sh[3][T];
     const int p = blockIdx.x;
     if (p >= nprob) return;
     const DevProb& P = probs[p];
     const int64_t t0 = P.item_begin;
-    const int64_t nt = (P.N + T - 1) / T;
+    const int64_t nt = (P.N + tile_nodes - 1) / tile_nodes;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t t = threadIdx.x; t < nt; t += T)
         for (int c = 0; c < 3; ++c) acc[c] += part[3 * (t0 + t) + c];
@@ -550,10 +543,17 @@ hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
+    if (a.fused_probs) {
+        // one kernel for the per-node part, both gathers and the tile sums
+        if (a.frechet_begin && (e = hipEventRecord(a.frechet_begin, s)) != hipSuccess) return e;
+        if ((e = launch_adj_fused(a, s)) != hipSuccess) return e;
+        if (a.frechet_end && (e = hipEventRecord(a.frechet_end, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(adj_reduce_instances, dim3((unsigned)a.nprob), blk, 0, s, a.fused_probs, a.nprob, a.part,
+                           adj_fused_tile(a.n), a.grad);
+        return hipGetLastError();
+    }
     if (a.frechet_begin && (e = hipEventRecord(a.frechet_begin, s)) != hipSuccess) return e;
-    if (a.taylor) {
-        e = launch_adj_taylor(a, s);
-    } else {
+    {
         switch (a.n) {
             case 3: e = frechet_n<3>(a, s); break;
             case 5: e = frechet_n<5>(a, s); break;
@@ -580,7 +580,7 @@ hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t s) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(adj_reduce_tiles, dim3((unsigned)a.tiles), blk, 0, s, a.tile_probs, a.nprob, a.dparam, a.part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(adj_reduce_instances, dim3((unsigned)a.nprob), blk, 0, s, a.tile_probs, a.nprob, a.part,
+    hipLaunchKernelGGL(adj_reduce_instances, dim3((unsigned)a.nprob), blk, 0, s, a.tile_probs, a.nprob, a.part, T,
                        a.grad);
     return hipGetLastError();
 }

@@ -1,8 +1,9 @@
-// Reverse step, per-node part, by the finite Taylor series (step a10 for
-// instances without a reaction term on uniform grids): the weights W0, W1 of
-// each node and the derivatives of lam_i u+_i with respect to nu, c and delta
-// through those weights -- what adj_frechet_kernel reads off the
-// block-triangular Pade exponential, here in O(n^2) per node.
+// Reverse step by the finite Taylor series (step a10 for instances without a
+// reaction term on uniform grids).  Per node: the weights W0, W1 and the
+// derivatives of lam_i u+_i with respect to nu, c and delta through those
+// weights -- what adj_frechet_kernel reads off the block-triangular Pade
+// exponential, here in O(n^2) per node -- and, in the same kernel, the
+// gathers of the reverse step over a tile.
 //
 // As in the forward finite-Taylor build, with q(x) = a x + b x^2 + e x^3
 // (a = -c dt/h, b = nu dt/h^2, e = -delta dt/h^3) and the moments
@@ -21,9 +22,8 @@
 //     d(lam_i u+_i)/da = lam_i sum_k k (M_{k-1}(1) tau_k + dt I_1(k-1) nu_k)
 // with tau_k = T_k[r'] . U and nu_k = T_k[r'] . V, and the chain rule gives
 // nu, c and delta.  The derivative in c also serves c_i = c + g u_i of the
-// frozen velocity.  Blocks cover 256-node tiles of one instance (the tile
-// table of the reverse step), so a node's result does not depend on how the
-// instances are batched.
+// frozen velocity.  Blocks cover tiles of one instance, so a node's result
+// does not depend on how the instances are batched.
 #include "lmep_device.hpp"
 
 namespace lmep {
@@ -118,99 +118,277 @@ __device__ __forceinline__ void adj_taylor_node(double a, double b, double e, do
     }
 }
 
+// Stencils S_i that contain position j, as in the reverse step's gathers, but
+// with periodic candidates left unwrapped: calls f(x, k) with x the node's
+// index (its unwrapped position on a periodic grid) and k its stencil
+// position, in the same order as the one-kernel-per-gather path.
+template <class F>
+__device__ __forceinline__ void stencils_containing(int64_t j, int64_t N, int n, int bc, F&& f) {
+    const int R = (n - 1) / 2;
+    int64_t ps[3];
+    int np = 0;
+    ps[np++] = j;
+    if (bc == BC_NEUMANN) {
+        if (j > 0 && j <= 2 * R) ps[np++] = -j;
+        if (j < N - 1 && j >= N - 1 - 2 * R) ps[np++] = 2 * (N - 1) - j;
+    }
+    for (int q = 0; q < np; ++q) {
+        const int64_t p = ps[q];
+        for (int d = -(n - 1); d <= n - 1; ++d) {
+            const int64_t x = p + d;
+            int64_t i = x;
+            if (bc == BC_PERIODIC) {
+                i = map_index(x, N, bc);
+            } else if (i < 0 || i > N - 1) {
+                continue;
+            }
+            if (bc == BC_DIRICHLET && (i == 0 || i == N - 1)) continue;
+            const int64_t o = window_offset(i, N, n, bc);
+            const int64_t k = -d - o;
+            if (k < 0 || k >= n) continue;
+            f(bc == BC_PERIODIC ? x : i, (int)k);
+        }
+    }
+}
+
+// The whole reverse step of a tile of T - 4 (n - 1) nodes in one block:
+//   1. stage u, du/dx and lambda over the block's 256 weight positions (the
+//      tile and 2 (n - 1) on each side) plus the windows' reach;
+//   2. each thread forms the weights and parameter terms of one position
+//      (adj_taylor_node) into LDS -- positions next to the tile are
+//      recomputed by the neighbouring blocks instead of being exchanged;
+//   3. ghat at the positions within n - 1 of the tile (gather over LDS);
+//   4. lambda_k of the tile's nodes (gather over LDS), written to HBM;
+//   5. the tile's parameter terms summed in a fixed order into part[].
+// The per-node weights never reach HBM.  Each term is formed and summed in
+// the same order as in the three-kernel path, so lambda_k agrees with it bit
+// for bit (the parameter sums are split into tiles differently).
 template <int NN, int PP>
-__global__ __launch_bounds__(T) void adj_taylor_kernel(const DevProb* __restrict__ probs, int nprob,
-                                                       const double* __restrict__ taylor,
-                                                       const double* __restrict__ u_all,
-                                                       const double* __restrict__ lam_all,
-                                                       const double* __restrict__ g_all, double* __restrict__ ws,
-                                                       int ws_stride, double* __restrict__ dparam) {
+__global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict__ probs, int nprob,
+                                                      const double* __restrict__ fd,
+                                                      const double* __restrict__ taylor,
+                                                      const double* __restrict__ u_all,
+                                                      const double* __restrict__ lam_all,
+                                                      const double* __restrict__ g_all,
+                                                      double* __restrict__ lam_out_all, double* __restrict__ part) {
+    constexpr int R = (NN - 1) / 2;
+    constexpr int H = NN - 1;   // reach of a window
+    constexpr int HW = 2 * H;   // weight positions on each side of the tile
+    constexpr int TO = T - 2 * HW;  // nodes of the tile
+    constexpr int SU = T + 2 * H;   // staged u and du/dx positions
+    __shared__ double su[SU], sg[SU], sl[T], sgh[T], sdc[T], sW[2 * NN * T];
+    __shared__ double red[3][T];
+
     const int64_t tile = blockIdx.x;
     const DevProb& P = probs[find_instance(probs, nprob, tile)];
     const int64_t N = P.N;
-    const int64_t node = (tile - P.item_begin) * T + threadIdx.x;
-    // lane 0 holds the wavefront's first node: past the end, so is every lane
-    if (__builtin_amdgcn_readfirstlane(node < N ? 1 : 0) == 0) return;
-    const bool active = node < N;
-    const int64_t i = active ? node : N - 1;  // idle lanes repeat the last node; their results are dropped
+    const int64_t t0 = (tile - P.item_begin) * TO;  // first node of the tile
+    const int64_t base = t0 - HW;                    // position of weight slot 0
     const int bc = P.bc;
+    const bool dir = bc == BC_DIRICHLET, per = bc == BC_PERIODIC;
     const double* __restrict__ u = u_all + P.state_off;
-    const bool fixed = (bc == BC_DIRICHLET) && (i == 0 || i == N - 1);
-    const double lam = fixed ? 0.0 : lam_all[P.state_off + i];
-    const int64_t o = window_offset(i, N, NN, bc);
-    const int r = (int)(-o);
+    const double* __restrict__ gg = g_all + P.state_off;
     const double dt = P.dt, g = P.nl_coef, ih = 1.0 / P.h;
-    const double ui = u[i];
-    const double ceff = P.c + (P.nonlin == NL_BURGERS ? g * ui : 0.0);
-    const double a = -ceff * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
+    const bool burgers = P.nonlin == NL_BURGERS;
+    const int tid = threadIdx.x;
+    // a position holds a node: inside the grid, or anywhere on a periodic grid
+    auto holds = [&](int64_t x) { return per || (x >= 0 && x < N); };
 
-    double U[NN], V[NN];
+    // 1. staging.  Positions outside a Dirichlet grid, or more than one
+    // reflection away from a Neumann grid, are never read (a node's window
+    // reaches at most (n-1)/2 beyond an end).
+    for (int q = tid; q < SU; q += T) {
+        const int64_t x = base - H + q;
+        const bool ok = per || (dir ? (x >= 0 && x < N) : (x >= -(N - 1) && x <= 2 * (N - 1)));
+        const int64_t xi = ok ? map_index(x, N, bc) : 0;
+        su[q] = ok ? u[xi] : 0.0;
+        sg[q] = ok ? gg[xi] : 0.0;
+    }
+    {
+        const int64_t x = base + tid;
+        sl[tid] = holds(x) ? lam_all[P.state_off + map_index(x, N, bc)] : 0.0;
+    }
+    __syncthreads();
+
+    // 2. weights and parameter terms of weight slot tid
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    {
+        const int64_t x = base + tid;
+        const bool active = holds(x);
+        // idle lanes take a node of the tile (results dropped)
+        const int64_t i = active ? map_index(x, N, bc) : (t0 < N ? t0 : N - 1);
+        const int64_t xs = active ? x : i;  // position whose staged window is read
+        const int us0 = (int)(xs - (base - H));
+        const double ui = su[us0];
+        const double ceff = P.c + (burgers ? g * ui : 0.0);
+        const int o = (int)window_offset(i, N, NN, bc);
+        const int r = -o;
+        const double a = -ceff * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
+        double U[NN], V[NN];
 #pragma unroll
-    for (int j = 0; j < NN; ++j) {
-        const int64_t jj = map_index(i + o + j, N, bc);
-        U[j] = u[jj];
-        double v = 0.0;
-        if constexpr (PP >= 1) {
-            if (P.nonlin == NL_BURGERS) v = -g * (U[j] - ui) * g_all[P.state_off + jj];
-            else if (P.nonlin == NL_AC) v = g * (U[j] - U[j] * U[j] * U[j]);
+        for (int j = 0; j < NN; ++j) {
+            U[j] = su[us0 + o + j];
+            double v = 0.0;
+            if constexpr (PP >= 1) {
+                if (burgers) v = -g * (U[j] - ui) * sg[us0 + o + j];
+                else if (P.nonlin == NL_AC) v = g * (U[j] - U[j] * U[j] * U[j]);
+            }
+            V[j] = v;
         }
-        V[j] = v;
+        const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
+        const int sh = (int)rint(half);
+        const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
+        double W0[NN], W1[NN], Ga, Gb, Ge;
+        int rp = r + sh;
+        rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
+        const int r0 = __builtin_amdgcn_readfirstlane(r), rp0 = __builtin_amdgcn_readfirstlane(rp);
+        if (__ballot(active && (r != r0 || rp != rp0)) == 0) {
+            const double* __restrict__ Tr = tb + rp0 * (kMaxN * kMaxN);
+            if (rp0 == r0)
+                adj_taylor_node<NN, PP, false>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
+            else
+                adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp0 - r0), dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
+        } else {
+            adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp - r), dt, tb + rp * (kMaxN * kMaxN), U, V, W0, W1,
+                                          Ga, Gb, Ge);
+        }
+#pragma unroll
+        for (int j = 0; j < NN; ++j) {
+            sW[j * T + tid] = W0[j];
+            if constexpr (PP >= 1) sW[(NN + j) * T + tid] = dt * W1[j];
+        }
+        const bool fixed = dir && (i == 0 || i == N - 1);
+        const double lam = (active && !fixed) ? sl[tid] : 0.0;
+        const bool mine = active && tid >= HW && tid < HW + TO && x < N;  // a node of the tile
+        if (mine) {
+            d0 = lam * (dt * ih * ih) * Gb;
+            d1 = lam * (-dt * ih) * Ga;
+            d2 = lam * (-dt * ih * ih * ih) * Ge;
+        }
+        sdc[tid] = d1;
+    }
+    __syncthreads();
+
+    // 3. ghat at the weight slots within n - 1 of the tile
+    if (burgers && tid >= H && tid < T - H) {
+        const int64_t m = base + tid;
+        double acc = 0.0;
+        if (holds(m)) {
+            const int64_t mi = map_index(m, N, bc);
+            const double um = su[tid + H];
+            auto term = [&](int64_t x, int k) {
+                const int q = (int)(x - base);
+                acc += sl[q] * sW[(NN + k) * T + q] * (-g) * (um - su[q + H]);
+            };
+            if (gather_interior(mi, N, NN)) {
+#pragma unroll
+                for (int d = -R; d <= R; ++d) term(m + d, R - d);
+            } else {
+                stencils_containing(per ? m : mi, N, NN, bc, term);
+            }
+        }
+        sgh[tid] = acc;
+    }
+    __syncthreads();
+
+    // 4. lambda_k of the tile's nodes
+    const int64_t j = t0 + tid;
+    if (tid < TO && j < N) {
+        const int qj = HW + tid;  // weight slot of node j
+        const double uj = su[qj + H];
+        const bool etd = P.scheme == SCH_ETD1;
+        double dNj = 0.0;
+        if (etd && burgers) dNj = -g * sg[qj + H];
+        if (etd && P.nonlin == NL_AC) dNj = g * (1.0 - 3.0 * uj * uj);
+        double acc = 0.0;
+        auto term = [&](int64_t x, int k) {
+            const int q = (int)(x - base);
+            double w = sW[k * T + q];
+            if (etd) w += dNj * sW[(NN + k) * T + q];
+            acc += sl[q] * w;
+        };
+        const bool inner = gather_interior(j, N, NN);
+        if (inner) {
+#pragma unroll
+            for (int d = -R; d <= R; ++d) term(j + d, R - d);
+        } else {
+            stencils_containing(j, N, NN, bc, term);
+        }
+        const bool fixed = dir && (j == 0 || j == N - 1);
+        if (burgers && !fixed) {
+            const int o = (int)window_offset(j, N, NN, bc);
+            double sacc = 0.0;
+#pragma unroll
+            for (int k = 0; k < NN; ++k) sacc += sW[(NN + k) * T + qj] * sg[qj + H + o + k];
+            acc += sl[qj] * g * sacc + g * sdc[qj];
+        }
+        if (burgers) {
+            if (inner) {
+#pragma unroll
+                for (int d = -R; d <= R; ++d) acc += sgh[qj + d] * fd[fd_index(NN, 0, R, R - d)] * ih;
+            } else {
+                int64_t ps[3];
+                int np = 0;
+                ps[np++] = j;
+                if (bc == BC_NEUMANN) {
+                    if (j > 0 && j <= 2 * R) ps[np++] = -j;
+                    if (j < N - 1 && j >= N - 1 - 2 * R) ps[np++] = 2 * (N - 1) - j;
+                }
+                for (int q = 0; q < np; ++q) {
+                    for (int d = -(NN - 1); d <= NN - 1; ++d) {
+                        const int64_t x = ps[q] + d;
+                        int64_t m = x;
+                        if (bc == BC_PERIODIC) m = map_index(x, N, bc);
+                        else if (m < 0 || m > N - 1) continue;
+                        const int64_t o = window_offset(m, N, NN, bc);
+                        const int64_t l = -d - o;
+                        if (l < 0 || l >= NN) continue;
+                        acc += sgh[(int)((per ? x : m) - base)] * fd[fd_index(NN, 0, (int)(-o), (int)l)] * ih;
+                    }
+                }
+            }
+        }
+        lam_out_all[P.state_off + j] = acc;
     }
 
-    const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
-    const int sh = (int)rint(half);
-    const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
-    double W0[NN], W1[NN], Ga, Gb, Ge;
-    int rp = r + sh;
-    rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
-    const int r0 = __builtin_amdgcn_readfirstlane(r), rp0 = __builtin_amdgcn_readfirstlane(rp);
-    if (__ballot(active && (r != r0 || rp != rp0)) == 0) {  // one expansion row for the wavefront
-        const double* __restrict__ Tr = tb + rp0 * (kMaxN * kMaxN);
-        if (rp0 == r0)
-            adj_taylor_node<NN, PP, false>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
-        else
-            adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp0 - r0), dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
-    } else {
-        adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp - r), dt, tb + rp * (kMaxN * kMaxN), U, V, W0, W1, Ga,
-                                      Gb, Ge);
+    // 5. the tile's parameter terms, fixed-order tree sum
+    red[0][tid] = d0;
+    red[1][tid] = d1 * (tid >= HW && tid < HW + TO ? 1.0 : 0.0);
+    red[2][tid] = d2;
+    __syncthreads();
+    for (int w = T / 2; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + w];
+        __syncthreads();
     }
-    if (!active) return;
-    double* __restrict__ wsb = ws + P.state_off * (int64_t)ws_stride;  // [kind][k][N]
-    double* __restrict__ dp = dparam + 3 * P.state_off;
-#pragma unroll
-    for (int j = 0; j < NN; ++j) {
-        wsb[(int64_t)j * N + i] = W0[j];
-        if constexpr (PP >= 1) wsb[(int64_t)(NN + j) * N + i] = dt * W1[j];
-    }
-    dp[i] = fixed ? 0.0 : lam * (dt * ih * ih) * Gb;                // d/dnu
-    dp[N + i] = fixed ? 0.0 : lam * (-dt * ih) * Ga;                // d/dc (also d/dc_i)
-    dp[2 * N + i] = fixed ? 0.0 : lam * (-dt * ih * ih * ih) * Ge;  // d/ddelta
+    if (tid == 0)
+        for (int c = 0; c < 3; ++c) part[3 * tile + c] = red[c][0];
 }
 
 template <int NN>
-hipError_t go_adj_taylor(const AdjointLaunch& a, hipStream_t s) {
+hipError_t go_adj_fused(const AdjointLaunch& a, hipStream_t s) {
     if (a.p == 0)
-        hipLaunchKernelGGL((adj_taylor_kernel<NN, 0>), dim3((unsigned)a.tiles), dim3(T), 0, s, a.tile_probs, a.nprob,
-                           a.taylor, a.u, a.lam, a.g, a.ws, a.ws_stride, a.dparam);
+        hipLaunchKernelGGL((adj_fused_kernel<NN, 0>), dim3((unsigned)a.fused_tiles), dim3(T), 0, s, a.fused_probs,
+                           a.nprob, a.fd, a.taylor, a.u, a.lam, a.g, a.lam_out, a.part);
     else
-        hipLaunchKernelGGL((adj_taylor_kernel<NN, 1>), dim3((unsigned)a.tiles), dim3(T), 0, s, a.tile_probs, a.nprob,
-                           a.taylor, a.u, a.lam, a.g, a.ws, a.ws_stride, a.dparam);
+        hipLaunchKernelGGL((adj_fused_kernel<NN, 1>), dim3((unsigned)a.fused_tiles), dim3(T), 0, s, a.fused_probs,
+                           a.nprob, a.fd, a.taylor, a.u, a.lam, a.g, a.lam_out, a.part);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_adj_taylor(const AdjointLaunch& a, hipStream_t s) {
-    if (a.tiles <= 0) return hipSuccess;
-    if (a.p < 0 || a.p > 1 || !a.taylor) return hipErrorInvalidValue;
+hipError_t launch_adj_fused(const AdjointLaunch& a, hipStream_t s) {
+    if (a.fused_tiles <= 0) return hipSuccess;
+    if (a.p < 0 || a.p > 1 || !a.taylor || !a.fused_probs) return hipErrorInvalidValue;
     switch (a.n) {
-        case 3: return go_adj_taylor<3>(a, s);
-        case 5: return go_adj_taylor<5>(a, s);
-        case 7: return go_adj_taylor<7>(a, s);
-        case 9: return go_adj_taylor<9>(a, s);
-        case 11: return go_adj_taylor<11>(a, s);
-        case 13: return go_adj_taylor<13>(a, s);
-        case 15: return go_adj_taylor<15>(a, s);
+        case 3: return go_adj_fused<3>(a, s);
+        case 5: return go_adj_fused<5>(a, s);
+        case 7: return go_adj_fused<7>(a, s);
+        case 9: return go_adj_fused<9>(a, s);
+        case 11: return go_adj_fused<11>(a, s);
+        case 13: return go_adj_fused<13>(a, s);
+        case 15: return go_adj_fused<15>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -190,8 +190,8 @@ Layout layout(const lmep_problem* prob, int32_t count, int op) {
         off += align256(sizeof(double) * ext * (size_t)L.ws_stride);
         L.dparam = off;
         off += align256(sizeof(double) * 3 * ext);
-        L.part = off;
-        off += align256(sizeof(double) * 3 * (size_t)total_tiles(prob, count, kAdjTile));
+        L.part = off;  // per tile partial sums: 256-node tiles, or the fused kernel's (>= 128 nodes)
+        off += align256(sizeof(double) * 3 * (size_t)total_tiles(prob, count, 128));
     }
     L.flag = off;
     off += 256;
@@ -766,11 +766,13 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
     std::map<std::tuple<int, int, int>, std::vector<int>> by;
     for (int k = 0; k < count; ++k)
         by[{prob[k].n, scheme_p(prob[k].scheme), (auto_method && prob[k].react == 0.0) ? 1 : 0}].push_back(k);
-    std::vector<DevProb> ntab, ttab;
+    std::vector<DevProb> ntab, ttab, ftab;
     struct G {
         int n, p, first, cnt;
         int64_t nodes, tiles;
         bool taylor;
+        bool fused = false;  // whole step in one kernel (finite Taylor, tiles of adj_fused_tile(n) nodes)
+        int64_t ftiles = 0;
     };
     std::vector<G> groups;
     const double* tay = nullptr;
@@ -779,14 +781,18 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
         G g{std::get<0>(kv.first), std::get<1>(kv.first), (int)ntab.size(), (int)kv.second.size(), 0, 0,
             std::get<2>(kv.first) == 1};
         if (g.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
+        g.fused = g.taylor;
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
             d.item_begin = g.nodes;
             ntab.push_back(d);
             d.item_begin = tile_base + g.tiles;  // global tile index: rows of the partial-sum array
             ttab.push_back(d);
+            d.item_begin = g.ftiles;
+            ftab.push_back(d);
             g.nodes += prob[k].N;
             g.tiles += (prob[k].N + kAdjTile - 1) / kAdjTile;
+            g.ftiles += (prob[k].N + adj_fused_tile(g.n) - 1) / adj_fused_tile(g.n);
         }
         // tile tables are searched from the group's first tile
         for (int q = g.first; q < g.first + g.cnt; ++q) ttab[q].item_begin -= tile_base;
@@ -794,8 +800,12 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
         tile_base += g.tiles;
     }
     char* base = (char*)d_scratch;
-    if ((rc = upload(ntab, ttab, base + L.build_tab, base + L.apply_tab, s))) return rc;
+    // the build-table region holds two tables per instance: node table, then fused-tile table
+    std::vector<DevProb> nftab(ntab);
+    nftab.insert(nftab.end(), ftab.begin(), ftab.end());
+    if ((rc = upload(nftab, ttab, base + L.build_tab, base + L.apply_tab, s))) return rc;
     const DevProb* dn = (const DevProb*)(base + L.build_tab);
+    const DevProb* df = dn + ntab.size();
     const DevProb* dtt = (const DevProb*)(base + L.apply_tab);
     // optional profiling: events around each group's Frechet kernel and around the whole step
     Timer timer;
@@ -824,13 +834,17 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
         a.dparam = (double*)(base + L.dparam);
         a.part = (double*)(base + L.part) + 3 * part_base;
         a.taylor = g.taylor ? tay : nullptr;
+        if (g.fused) {
+            a.fused_probs = df + g.first;
+            a.fused_tiles = g.ftiles;
+        }
         if (timer.on) {
             a.frechet_begin = timer.build[timer.nb].first;
             a.frechet_end = timer.build[timer.nb].second;
             ++timer.nb;
         }
         HIP_TRY(launch_adjoint(a, s));
-        part_base += g.tiles;
+        part_base += g.fused ? g.ftiles : g.tiles;
     }
     HIP_TRY(timer.mark(false, s, false));
     if (timer.on) {

@@ -54,6 +54,16 @@ __device__ __forceinline__ int64_t map_index(int64_t j, int64_t N, int bc) {
     return j;
 }
 
+// Reverse-step gathers: nodes j whose gathers see only interior nodes (every
+// node within n - 1 of j has a centred window, none is a held Dirichlet end,
+// no Neumann mirror or periodic wrap is involved).  The stencils containing j
+// are then those of i = j + d, d = -(n-1)/2 .. (n-1)/2, at position
+// k = (n-1)/2 - d -- the same terms, in the same order (d ascending), as the
+// general loop over candidates, so the fast paths agree with it bit for bit.
+__device__ __forceinline__ bool gather_interior(int64_t j, int64_t N, int n) {
+    return j >= 2 * (n - 1) && j <= N - 1 - 2 * (n - 1);
+}
+
 // Instance owning work item `item` (binary search over item_begin).
 __device__ __forceinline__ int find_instance(const DevProb* __restrict__ probs, int nprob, int64_t item) {
     int lo = 0, hi = nprob - 1;

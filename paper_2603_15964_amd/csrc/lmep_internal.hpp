@@ -182,11 +182,19 @@ struct AdjointLaunch {
     int ws_stride = 0;
     double* dparam = nullptr;
     double* part = nullptr;
-    const double* taylor = nullptr;  // set: per-node part by the finite Taylor series (adjoint_taylor.hip)
+    // set: the whole step by the finite Taylor series (table `taylor`) in one
+    // kernel per tile of adj_fused_tile(n) nodes; item_begin = prefix of those tiles
+    const double* taylor = nullptr;
+    const DevProb* fused_probs = nullptr;
+    int64_t fused_tiles = 0;
     hipEvent_t frechet_begin = nullptr, frechet_end = nullptr;  // recorded around the Frechet kernel if set
 };
 hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t stream);
-hipError_t launch_adj_taylor(const AdjointLaunch& a, hipStream_t stream);
+hipError_t launch_adj_fused(const AdjointLaunch& a, hipStream_t stream);
+// Nodes per tile of the fused reverse step: a block forms the weights of
+// kAdjTile positions, the tile and 2 (n - 1) on each side.
+__host__ __device__ constexpr int adj_fused_tile(int n) { return kAdjTile - 4 * (n - 1); }
+static_assert(adj_fused_tile(15) >= 128, "fused reverse-step tile");
 
 // Finite check: writes 1 into *d_flag if any of the count doubles is not finite.
 hipError_t launch_check_finite(const double* d_x, int64_t count, int* d_flag, hipStream_t stream);
