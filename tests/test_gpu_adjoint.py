@@ -215,3 +215,37 @@ def test_reaction_term_reverse_step_takes_pade():
         lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, saved)
     assert np.array_equal(got[1], lp[0])
     assert np.array_equal(gr[1], gp[0])
+
+
+FUSED_CASES = [
+    ("burgers dirichlet n3 multi-tile", make_problem(N=700, n=3, bc="dirichlet", h=0.02, dt=0.005, nu=5e-3,
+                                                     scheme="etd1", nonlin="burgers_frozen", nl_coef=1.0)),
+    ("burgers neumann n13 tiny", make_problem(N=13, n=13, bc="neumann", h=0.05, dt=0.004, nu=2e-2, scheme="etd1",
+                                              nonlin="burgers_frozen", nl_coef=1.0)),
+    ("burgers neumann n9 short", make_problem(N=30, n=9, bc="neumann", h=0.05, dt=0.005, nu=2e-2, scheme="etd1",
+                                              nonlin="burgers_frozen", nl_coef=1.0)),
+    ("burgers periodic n15 multi-tile", make_problem(N=611, n=15, bc="periodic", h=0.05, dt=0.004, nu=2e-2,
+                                                     scheme="etd1", nonlin="burgers_frozen", nl_coef=1.0)),
+    ("burgers periodic n7 tiny", make_problem(N=8, n=7, bc="periodic", h=0.05, dt=0.005, nu=2e-2, scheme="etd1",
+                                              nonlin="burgers_frozen", nl_coef=1.0)),
+    ("allen-cahn dirichlet n15 multi-tile", make_problem(N=450, n=15, bc="dirichlet", h=0.02, dt=0.05, nu=1e-4,
+                                                         scheme="etd1", nonlin="allen_cahn", nl_coef=1.0)),
+    ("linear neumann n11 multi-tile", make_problem(N=520, n=11, bc="neumann", h=0.1, dt=0.05, c=0.7, nu=0.01,
+                                                   delta=2e-4, scheme="linear")),
+]
+
+
+@pytest.mark.parametrize("name,p", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_fused_reverse_step_edges_match_oracle(name, p):
+    """The one-kernel reverse step on what its tiling makes special: several
+    tiles with a ragged last one, grids shorter than a stencil's reach on
+    Neumann and periodic ends, the largest and smallest stencils."""
+    _case("fused reverse step", name)
+    u = _state(p, 5)
+    lam = np.random.default_rng(6).normal(size=p["N"])
+    got, gr = _reverse([p], [u], [lam])
+    want, wgrad = oracle.adjoint_step(p, u, lam)
+    assert _rel(got[0], want) <= 1e-10, _rel(got[0], want)
+    for k in range(3):
+        scale = max(abs(wgrad[k]), 1e-12 * np.max(np.abs(wgrad)), 1e-300)
+        assert abs(gr[0][k] - wgrad[k]) <= 1e-10 * scale, (k, gr[0][k], wgrad[k])
