@@ -231,14 +231,23 @@ def test_check_finite_flag():
 
 # ---------------------------------------------------------- full size ----
 def test_full_size_burgers_65536():
-    """The Burgers workload at its full size, in the launch configuration the
-    benchmark times (one instance, weights rebuilt every step), for 20 steps."""
+    """The Burgers workload at its full size (one instance, weights rebuilt
+    every step): 20 graph-replayed one-step launches, and 200 steps in the
+    launch configuration the benchmark times (8 fused steps per launch),
+    against the oracle."""
     _print_case("full size burgers N=65536 n=7")
     p, u0 = workloads.burgers()
     steps = 20
     got = gpu_run([p], [u0], steps, flags=lmep.LMEP_F_GRAPH)[0]
     want = oracle.run(p, u0, steps)
     assert state_rel_err(got, want) <= 1e-10
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, 8)
+    try:
+        got = gpu_run([p], [u0], 200, flags=lmep.LMEP_F_PERSISTENT)[0]
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, saved)
+    assert state_rel_err(got, oracle.run(p, u0, 200)) <= 1e-10
 
 
 def test_full_size_kdv_conservation_and_sample():

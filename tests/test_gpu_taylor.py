@@ -301,3 +301,26 @@ def test_taylor_multistep_upwind_workload_and_oracle():
         _set_kb(saved)
     assert np.array_equal(multi, one)
     assert _state_err(five, oracle.run(p, u, 5)) <= 1e-10
+
+
+def test_taylor_multistep_mixed_windows_speed_and_dispersion():
+    """One frozen-velocity group at 4 steps per launch holding centred and
+    one-sided instances (per-instance tiles), a background speed c and a
+    dispersive term: equal to the one-step path instance by instance."""
+    _print_case("taylor multistep mixed")
+    a, ua = _problem(1500, 5, "periodic", "centred", cfl=1.0, tau=0.02, seed=501)
+    b, ub = _problem(900, 5, "dirichlet", "upwind", cfl=1.2, seed=502)
+    c, uc = _problem(2000, 5, "periodic", "upwind", cfl=1.0, seed=503)
+    a = dict(a, c=0.4)
+    probs, states = [a, b, c], [ua, ub, uc]
+    one = _run(probs, states, 9)
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    try:
+        _set_kb(4)
+        multi = _run(probs, states, 9, flags=lmep.LMEP_F_PERSISTENT)
+    finally:
+        _set_kb(saved)
+    for k in range(3):
+        assert np.all(np.isfinite(one[k])), k
+        assert np.array_equal(multi[k], one[k]), k
+    assert _state_err(one[0], oracle.run(a, ua, 9)) <= 1e-10
