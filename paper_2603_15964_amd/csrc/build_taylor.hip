@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
 // from the position's own window, weights of the node, stencil sum), so the
 // two paths agree bit for bit.
 template <int NN>
-__global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb* __restrict__ probs, int nprob,
+__global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevProb* __restrict__ probs, int nprob,
                                                                    int kb, int ksteps, int reg,
                                                                    const double* __restrict__ fd,
                                                                    const double* __restrict__ taylor,
@@ -257,6 +257,7 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
     constexpr int MAXR = kTaylorRegion;
     __shared__ double lds[3 * MAXR];  // current u, next u, derivative: addressed by offsets
     const int REG = reg;
+    const int nt = blockDim.x;  // threads: one staged position each per pass (normally nt = reg)
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
     const DevProb& P = probs[find_instance(probs, nprob, tile)];
     const int64_t N = P.N;
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
     const int g_hi = dir ? (int)(N - v0 < REG ? N - v0 : REG) : REG;
     int cu = 0, cn = MAXR;
     const int cd = 2 * MAXR;
-    for (int t = tid; t < REG; t += kTaylorTile)
+    for (int t = tid; t < REG; t += nt)
         lds[cu + t] = (t >= g_lo && t < g_hi) ? us[map_index(v0 + t, N, bc)] : 0.0;
     __syncthreads();
     int lo = g_lo, hi = g_hi;  // slots whose current u is valid
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
         const bool lend = dir && v0 + lo == 0, rend = dir && v0 + hi == N;  // grid ends: nothing spoilt
         const int nlo = lend ? lo : lo + 2 * rw, nhi = rend ? hi : hi - 2 * rw;  // slots updated this step
         const int dlo = lend ? lo : lo + rw, dhi = rend ? hi : hi - rw;          // slots whose derivative they read
-        for (int t = dlo + tid; t < dhi; t += kTaylorTile) {
+        for (int t = dlo + tid; t < dhi; t += nt) {
             const int64_t j = map_index(v0 + t, N, bc);
             const int oj = (int)window_offset(j, N, NN, bc, P.window, P.c + g * lds[cu + t]);
             double dv = 0.0;
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
             lds[cd + t] = dv;
         }
         __syncthreads();
-        for (int base = 0; base < REG; base += kTaylorTile) {
+        for (int base = 0; base < REG; base += nt) {
             const int t = base + tid;
             const bool active = t >= nlo && t < nhi;
             if (__ballot(active) == 0) continue;  // the whole wavefront idles (uniform)
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(kTaylorTile) void taylor_stepk_kernel(const DevProb
         hi = nhi;
     }
     double* __restrict__ uo = u_out + P.state_off;
-    for (int t = halo + tid; t < halo + tw; t += kTaylorTile) {
+    for (int t = halo + tid; t < halo + tw; t += nt) {
         const int64_t node = v0 + t;
         if (node < N) uo[node] = lds[cu + t];
     }
@@ -372,12 +373,12 @@ hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb
                                const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
                                unsigned long long* stats, hipStream_t stream) {
     if (tiles <= 0) return hipSuccess;
-    if (tiles > 0x7fffffff || kb < 1 || kb > 8 || ksteps < 1 || ksteps > kb || reg < kTaylorTile ||
-        reg > kTaylorRegion || reg % kTaylorTile != 0 || taylor_stepk_tile(n, kb, reg, false) < 1)
+    if (tiles > 0x7fffffff || kb < 1 || kb > 8 || ksteps < 1 || ksteps > kb || reg < 64 || reg > kTaylorRegion ||
+        reg % 64 != 0 || taylor_stepk_tile(n, kb, reg, false) < 1)
         return hipErrorInvalidValue;
 #define LMEP_TSK_CASE(NN)                                                                                         \
     case NN:                                                                                                      \
-        hipLaunchKernelGGL((taylor_stepk_kernel<NN>), dim3((unsigned)tiles), dim3(kTaylorTile), 0, stream, d_probs, \
+        hipLaunchKernelGGL((taylor_stepk_kernel<NN>), dim3((unsigned)tiles), dim3(reg), 0, stream, d_probs,         \
                            nprob, kb, ksteps, reg, fd, taylor, d_u_in, d_u_out, stats);                           \
         return hipGetLastError();
     switch (n) {

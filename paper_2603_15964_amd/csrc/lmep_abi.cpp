@@ -242,6 +242,19 @@ struct Group {
     int64_t items = 0;         // matrices (build) or tiles (apply)
 };
 
+// Compute units of the current device (cached per device; 256 on MI355X).
+int cu_count() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cache[dev].load();
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+        cache[dev].store(c);
+    }
+    return c;
+}
+
 // Build groups: keyed by (n, p).  Instances selected by `want`.  frozen_kb > 0:
 // finite-Taylor groups advance frozen_kb steps per launch (tiles of
 // taylor_stepk_tile(n, frozen_kb) nodes instead of kTaylorTile).
@@ -272,17 +285,19 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         g.nonuniform = std::get<2>(kv.first) == 1;
         g.taylor = std::get<2>(kv.first) == 2;
         if (g.taylor && frozen_kb > 0) {
-            // half-size regions for groups of under 2^20 nodes, whose blocks would
-            // otherwise not reach every CU, unless the halo would eat most of it
+            // staged positions per block (= threads): about one block per CU for
+            // groups too small to fill the GPU -- a step then costs the latency of
+            // one block, not of the two or three an uneven spread puts on some
+            // CUs -- and the full region for larger ones
             int64_t nodes = 0;
             bool upwind = false;
             for (const Part& part : kv.second) {
                 nodes += prob[part.k].N;
                 upwind |= prob[part.k].window == LMEP_WIN_UPWIND;
             }
-            g.reg = (nodes < kSmallGroupNodes && taylor_stepk_tile(g.n, frozen_kb, kTaylorRegion / 2, upwind) >= 128)
-                        ? kTaylorRegion / 2
-                        : kTaylorRegion;
+            const int64_t halo = (int64_t)frozen_kb * taylor_stepk_reach(g.n, upwind);
+            const int64_t want_tile = std::max<int64_t>((nodes + cu_count() - 1) / cu_count(), 64);
+            g.reg = (int)std::min<int64_t>((want_tile + 2 * halo + 63) / 64 * 64, kTaylorRegion);
         }
         g.first = (int)tab.size();
         int64_t items = 0;
