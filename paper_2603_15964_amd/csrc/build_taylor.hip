@@ -46,9 +46,9 @@
 namespace lmep {
 namespace {
 
-// Weights of one node from table row T (T[k * kMaxN + j] = T_k[r'][j]).
+// Weights of one node from table row T (T[k * TS + j] = T_k[r'][j]).
 // SHIFT: s != 0; DISP: e != 0.
-template <int NN, bool SHIFT, bool DISP>
+template <int NN, bool SHIFT, bool DISP, int TS>
 __device__ __forceinline__ void taylor_weights(double a, double b, double e, double s,
                                                const double* __restrict__ T, double (&W0)[NN], double (&W1)[NN]) {
     double m2[NN], m1[NN], m0[NN];  // mu[k-2][.], mu[k-1][.], mu[k][.]
@@ -94,7 +94,7 @@ __device__ __forceinline__ void taylor_weights(double a, double b, double e, dou
                 F = fma(nx[m], 1.0 / (double)(m + 1), F);
             }
         }
-        const double* __restrict__ Tk = T + (k + 1) * kMaxN;
+        const double* __restrict__ Tk = T + (k + 1) * TS;
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
             const double t = Tk[j];
@@ -104,21 +104,34 @@ __device__ __forceinline__ void taylor_weights(double a, double b, double e, dou
     }
 }
 
-template <int NN, bool SHIFT>
+template <int NN, bool SHIFT, int TS = kMaxN>
 __device__ __forceinline__ void taylor_weights_d(bool disp, double a, double b, double e, double s,
                                                  const double* __restrict__ T, double (&W0)[NN], double (&W1)[NN]) {
     if (disp)
-        taylor_weights<NN, SHIFT, true>(a, b, e, s, T, W0, W1);
+        taylor_weights<NN, SHIFT, true, TS>(a, b, e, s, T, W0, W1);
     else
-        taylor_weights<NN, SHIFT, false>(a, b, e, s, T, W0, W1);
+        taylor_weights<NN, SHIFT, false, TS>(a, b, e, s, T, W0, W1);
+}
+
+// The n x n x n block of the table for this stencil size, copied to LDS as
+// lt[(r' * NN + k) * NN + j]: mixed wavefronts read their rows from there.
+template <int NN>
+__device__ __forceinline__ void stage_taylor_block(const double* __restrict__ taylor, double* lt, int tid, int nt) {
+    for (int i = tid; i < NN * NN * NN; i += nt) {
+        const int rp = i / (NN * NN), k = (i / NN) % NN, j = i % NN;
+        lt[i] = taylor[taylor_index(NN, rp, k, j)];
+    }
 }
 
 // Weights of this lane's node (harvest row r, shift sh) with the expansion
 // row r + sh read through the scalar unit when the wavefront's active lanes
-// share it.  Lanes with the same (r, sh) get the same values either way.
+// share it; otherwise each lane reads its own row, from the LDS copy of the
+// table block when the kernel holds one (lt != nullptr), else from the table
+// in global memory.  Lanes with the same (r, sh) get the same values either
+// way.
 template <int NN>
 __device__ __forceinline__ void node_weights(bool active, int r, int sh, bool disp, double a, double b, double e,
-                                             const double* __restrict__ taylor, double (&W0)[NN],
+                                             const double* __restrict__ taylor, const double* lt, double (&W0)[NN],
                                              double (&W1)[NN]) {
     const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
     int rp = r + sh;
@@ -130,6 +143,18 @@ __device__ __forceinline__ void node_weights(bool active, int r, int sh, bool di
             taylor_weights_d<NN, false>(disp, a, b, e, 0.0, T, W0, W1);
         else
             taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp0 - r0), T, W0, W1);
+    } else if (lt) {
+        const double* lr = lt + rp * (NN * NN);
+        if constexpr (NN <= 7) {
+            // the whole row in registers first: one round of LDS reads instead
+            // of one per order (larger rows would spill)
+            double Tl[NN * NN];
+#pragma unroll
+            for (int i = 0; i < NN * NN; ++i) Tl[i] = lr[i];
+            taylor_weights_d<NN, true, NN>(disp, a, b, e, (double)(rp - r), Tl, W0, W1);
+        } else {
+            taylor_weights_d<NN, true, NN>(disp, a, b, e, (double)(rp - r), lr, W0, W1);
+        }
     } else {
         taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp - r), tb + rp * (kMaxN * kMaxN), W0, W1);
     }
@@ -204,7 +229,7 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
     const int sh = (int)rint(half);
 
     double W0[NN], W1[NN];
-    node_weights<NN>(active, r, sh, disp, a, b, e, taylor, W0, W1);
+    node_weights<NN>(active, r, sh, disp, a, b, e, taylor, nullptr, W0, W1);
 #pragma unroll
     for (int j = 0; j < NN; ++j) W1[j] *= dt;
 
@@ -243,7 +268,10 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
 // spoilt.  Every node is formed by the
 // same expressions in the same order as in the one-step kernel (derivative
 // from the position's own window, weights of the node, stencil sum), so the
-// two paths agree bit for bit.
+// two paths agree bit for bit.  The block also copies the table block of its
+// stencil size to LDS: a wavefront whose lanes expand about different rows
+// (next to a Dirichlet end, or where the shift changes) reads its rows from
+// there instead of gathering them from global memory at every step.
 template <int NN>
 __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevProb* __restrict__ probs, int nprob,
                                                                    int kb, int ksteps, int reg,
@@ -256,6 +284,8 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
     constexpr int H = NN - 1;
     constexpr int MAXR = kTaylorRegion;
     __shared__ double lds[3 * MAXR];  // current u, next u, derivative: addressed by offsets
+    __shared__ double lt[NN * NN * NN];  // this stencil size's table block
+    __shared__ double lfd[NN * NN];      // first-derivative rows of the clamped and one-sided windows
     const int REG = reg;
     const int nt = blockDim.x;  // threads: one staged position each per pass (normally nt = reg)
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
@@ -290,6 +320,8 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
     const int cd = 2 * MAXR;
     for (int t = tid; t < REG; t += nt)
         lds[cu + t] = (t >= g_lo && t < g_hi) ? us[map_index(v0 + t, N, bc)] : 0.0;
+    stage_taylor_block<NN>(taylor, lt, tid, nt);
+    for (int i = tid; i < NN * NN; i += nt) lfd[i] = fd[fd_index(NN, 0, i / NN, i % NN)] * ih;
     __syncthreads();
     int lo = g_lo, hi = g_hi;  // slots whose current u is valid
     for (int st = 0; st < ksteps; ++st) {
@@ -304,9 +336,9 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
 #pragma unroll
                 for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, R, l)] * ih) * lds[cu + t - R + l];
             } else {
-                const int rj = -oj;
+                const double* fr = lfd + (-oj) * NN;
 #pragma unroll
-                for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, rj, l)] * ih) * lds[cu + t + oj + l];
+                for (int l = 0; l < NN; ++l) dv += fr[l] * lds[cu + t + oj + l];
             }
             lds[cd + t] = dv;
         }
@@ -325,7 +357,7 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
             const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
             const int sh = (int)rint(half);
             double W0[NN], W1[NN];
-            node_weights<NN>(active, r, sh, disp, a, b, e, taylor, W0, W1);
+            node_weights<NN>(active, r, sh, disp, a, b, e, taylor, lt, W0, W1);
 #pragma unroll
             for (int j = 0; j < NN; ++j) W1[j] *= dt;
             double acc = 0.0;
