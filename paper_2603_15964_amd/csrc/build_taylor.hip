@@ -268,10 +268,12 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
 // spoilt.  Every node is formed by the
 // same expressions in the same order as in the one-step kernel (derivative
 // from the position's own window, weights of the node, stencil sum), so the
-// two paths agree bit for bit.  The block also copies the table block of its
-// stencil size to LDS: a wavefront whose lanes expand about different rows
-// (next to a Dirichlet end, or where the shift changes) reads its rows from
-// there instead of gathering them from global memory at every step.
+// two paths agree bit for bit.  The block copies the first-derivative rows of
+// its stencil size to LDS, and on a Dirichlet grid the table block as well:
+// the wavefronts next to an end, whose lanes harvest different window rows,
+// read their rows from there at every step instead of from global memory.
+// Elsewhere a wavefront's lanes part only where the shift or the window side
+// changes; those few read the table in global memory, which measured faster.
 template <int NN>
 __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevProb* __restrict__ probs, int nprob,
                                                                    int kb, int ksteps, int reg,
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
     const int cd = 2 * MAXR;
     for (int t = tid; t < REG; t += nt)
         lds[cu + t] = (t >= g_lo && t < g_hi) ? us[map_index(v0 + t, N, bc)] : 0.0;
-    stage_taylor_block<NN>(taylor, lt, tid, nt);
+    if (dir) stage_taylor_block<NN>(taylor, lt, tid, nt);
     for (int i = tid; i < NN * NN; i += nt) lfd[i] = fd[fd_index(NN, 0, i / NN, i % NN)] * ih;
     __syncthreads();
     int lo = g_lo, hi = g_hi;  // slots whose current u is valid
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
             const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
             const int sh = (int)rint(half);
             double W0[NN], W1[NN];
-            node_weights<NN>(active, r, sh, disp, a, b, e, taylor, lt, W0, W1);
+            node_weights<NN>(active, r, sh, disp, a, b, e, taylor, dir ? lt : nullptr, W0, W1);
 #pragma unroll
             for (int j = 0; j < NN; ++j) W1[j] *= dt;
             double acc = 0.0;
