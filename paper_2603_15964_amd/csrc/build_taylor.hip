@@ -65,6 +65,11 @@ __device__ __forceinline__ void taylor_weights(double a, double b, double e, dou
         W0[j] = t;
         W1[j] = t;
     }
+    // Without a shift mu[k][m] can be non-zero only for lo(k) <= m <= k: the
+    // coefficient of x^k in (theta q(x))^m / m! needs m <= k <= 2m (3m with
+    // the cubic term).  Terms whose moment lies outside that range are exact
+    // zeros and are skipped (multiplying by a zero is not folded away for us).
+    constexpr auto lo = [](int k) constexpr { return SHIFT ? 0 : (DISP ? (k + 2) / 3 : (k + 1) / 2); };
 #pragma unroll
     for (int k = 0; k + 1 < NN; ++k) {
         const double bk = (double)(2 * k) * b;
@@ -72,14 +77,14 @@ __device__ __forceinline__ void taylor_weights(double a, double b, double e, dou
         double nx[NN];
 #pragma unroll
         for (int m = 0; m < NN; ++m) {
+            // every term an explicit fma (a plain first product could be
+            // contracted into the sums below differently in different kernels)
             double v = 0.0;
-            if (m <= k + 1) {
+            if (m <= k + 1 && m >= lo(k + 1)) {
                 if (SHIFT && m <= k) v = -s * m0[m];
-                if (m >= 1) {
-                    v = fma(a, m0[m - 1], v);
-                    if (k >= 1) v = fma(bk, m1[m - 1], v);
-                    if (DISP && k >= 2) v = fma(ek, m2[m - 1], v);
-                }
+                if (m >= 1 && m - 1 >= lo(k)) v = fma(a, m0[m - 1], v);
+                if (k >= 1 && m >= 1 && m - 1 >= lo(k - 1) && m <= k) v = fma(bk, m1[m - 1], v);
+                if (DISP && k >= 2 && m >= 1 && m - 1 >= lo(k - 2) && m <= k - 1) v = fma(ek, m2[m - 1], v);
             }
             nx[m] = v;
         }
@@ -89,7 +94,7 @@ __device__ __forceinline__ void taylor_weights(double a, double b, double e, dou
             m2[m] = m1[m];
             m1[m] = m0[m];
             m0[m] = nx[m];
-            if (m <= k + 1 && (SHIFT || m >= 1)) {
+            if (m <= k + 1 && m >= lo(k + 1) && (SHIFT || m >= 1)) {
                 E += nx[m];
                 F = fma(nx[m], 1.0 / (double)(m + 1), F);
             }
