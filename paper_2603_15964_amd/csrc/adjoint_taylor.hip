@@ -31,7 +31,7 @@ namespace {
 
 constexpr int T = kAdjTile;
 
-template <int NN, int PP, bool SHIFT>
+template <int NN, int PP, bool SHIFT, bool DISP = true>
 __device__ __forceinline__ void adj_taylor_node(double a, double b, double e, double s, double dt,
                                                 const double* __restrict__ Tr, const double (&U)[NN],
                                                 const double (&V)[NN], double (&W0)[NN], double (&W1)[NN],
@@ -56,6 +56,11 @@ __device__ __forceinline__ void adj_taylor_node(double a, double b, double e, do
         W0[j] = t;
         W1[j] = t;
     }
+    // Without a shift mu[k][m] can be non-zero only for lo(k) <= m <= k (the
+    // forward series states why); terms on the exact zeros outside that range,
+    // and the cubic term when e = 0 (DISP false), are skipped: each remaining
+    // term is the same fma as before, so the values do not change.
+    constexpr auto lo = [](int k) constexpr { return SHIFT ? 0 : (DISP ? (k + 2) / 3 : (k + 1) / 2); };
 #pragma unroll
     for (int k = 0; k + 1 < NN; ++k) {
         const int K = k + 1;  // order formed in this pass
@@ -65,13 +70,11 @@ __device__ __forceinline__ void adj_taylor_node(double a, double b, double e, do
 #pragma unroll
         for (int m = 0; m < NN; ++m) {
             double v = 0.0;
-            if (m <= K) {
+            if (m <= K && m >= lo(K)) {
                 if (SHIFT && m <= k) v = -s * m0[m];
-                if (m >= 1) {
-                    v = fma(a, m0[m - 1], v);
-                    if (k >= 1) v = fma(bk, m1[m - 1], v);
-                    if (k >= 2) v = fma(ek, m2[m - 1], v);
-                }
+                if (m >= 1 && m - 1 >= lo(k)) v = fma(a, m0[m - 1], v);
+                if (k >= 1 && m >= 1 && m - 1 >= lo(k - 1) && m <= k) v = fma(bk, m1[m - 1], v);
+                if (DISP && k >= 2 && m >= 1 && m - 1 >= lo(k - 2) && m <= k - 1) v = fma(ek, m2[m - 1], v);
             }
             nx[m] = v;
         }
@@ -81,7 +84,7 @@ __device__ __forceinline__ void adj_taylor_node(double a, double b, double e, do
             m2[m] = m1[m];
             m1[m] = m0[m];
             m0[m] = nx[m];
-            if (m <= K && (SHIFT || m >= 1)) {
+            if (m <= K && m >= lo(K) && (SHIFT || m >= 1)) {
                 E += nx[m];
                 F = fma(nx[m], 1.0 / (double)(m + 1), F);
                 I1 = fma(nx[m], 1.0 / (double)(m + 2), I1);
@@ -244,9 +247,12 @@ __global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict_
         const int r0 = __builtin_amdgcn_readfirstlane(r), rp0 = __builtin_amdgcn_readfirstlane(rp);
         if (__ballot(active && (r != r0 || rp != rp0)) == 0) {
             const double* __restrict__ Tr = tb + rp0 * (kMaxN * kMaxN);
-            if (rp0 == r0)
-                adj_taylor_node<NN, PP, false>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
-            else
+            if (rp0 == r0) {
+                if (P.delta != 0.0)
+                    adj_taylor_node<NN, PP, false, true>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
+                else
+                    adj_taylor_node<NN, PP, false, false>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
+            } else
                 adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp0 - r0), dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
         } else {
             adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp - r), dt, tb + rp * (kMaxN * kMaxN), U, V, W0, W1,
