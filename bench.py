@@ -34,19 +34,40 @@ def pade_flops(m: int, matrices: int, squarings: int) -> float:
     return matrices * (2.0 * 6 * m ** 3 + 8.0 * m ** 3 / 3.0) + squarings * 2.0 * m ** 3
 
 
+def _moment_terms(n: int):
+    """Per order K = 1..n-1 of the unshifted, dispersion-free moment recursion:
+    (entries, terms) -- the theta-degrees m that can be non-zero
+    (ceil(K/2) <= m <= K) and the recursion terms that feed them (a mu[K-1][m-1]
+    and 2 b (K-1) mu[K-2][m-1], each only where that moment can be non-zero)."""
+    lo = lambda k: (k + 1) // 2
+    out = []
+    for K in range(1, n):
+        k = K - 1
+        ms = range(lo(K), K + 1)
+        terms = 0
+        for m in ms:
+            terms += (m >= 1 and m - 1 >= lo(k))
+            terms += (k >= 1 and m >= 1 and m - 1 >= lo(k - 1) and m <= k)
+        out.append((len(ms), terms))
+    return out
+
+
 def taylor_flops(n: int, fused: bool) -> float:
     """Algorithmic flops of one node of the finite-Taylor build (multiply-add =
-    2), in the unshifted, dispersion-free case: the moment recursion (orders
-    1..n-1, order k+1 having k+1 entries, one multiply and, from order 2 on, one
-    multiply-add each, plus the scaled diffusion coefficient per order), the
-    two moment sums per order (exponential and phi1), the contraction with the
-    table rows (2 n multiply-adds per order), the dt scaling of W1, and with
-    fusion the derivative at the node (n multiplies + n multiply-adds) and the
-    stencil sum W0.u + W1.N with N_j = -g (u_j - u_i) d_j (7 per position)."""
-    rec = 1.5 * n * (n - 1) + n - 3
-    sums = 1.5 * (n - 1) * (n - 2) + (n - 1)
-    con = 4.0 * n * (n - 1)
-    f = rec + sums + con + n
+    2, a product into a zero sum = 1), in the unshifted, dispersion-free case:
+    the moment recursion over the moments that can be non-zero (_moment_terms;
+    plus the scaled diffusion coefficient per order from order 2), the two
+    moment sums per order (exponential: adds; phi1: multiply-adds), the
+    contraction with the table rows (2 n multiply-adds per order), the dt
+    scaling of W1, and with fusion the derivative at the node (n multiplies +
+    n multiply-adds) and the stencil sum W0.u + W1.N with
+    N_j = -g (u_j - u_i) d_j (7 per position)."""
+    f = 0.0
+    for K, (c, t) in enumerate(_moment_terms(n), start=1):
+        f += 2 * t - c + (1 if K >= 2 else 0)   # every entry's first term is a product
+        f += (c - 1) + (2 * c - 1)               # the exponential and phi1 sums
+        f += 4.0 * n                             # contraction
+    f += n
     if fused:
         f += 3.0 * n + 7.0 * n
     return f
@@ -213,17 +234,16 @@ def pair_pade_flops(m: int, squarings: float) -> float:
 
 def adj_taylor_flops(n: int, p: int) -> float:
     """Algorithmic flops of one node of the finite-Taylor reverse-step kernel
-    (2 per multiply-add; unshifted): the moment recursion with its diffusion
-    and dispersion terms (orders 1..n-1, order K having K entries: one
-    multiply, then a multiply-add each from order 2 and from order 3, plus two
-    coefficient multiplies per order), the three moment sums per order
-    (M(1), its integral and its first moment: 5K - 3), the contractions per
-    order with the table row (W0 and tau, and for ETD1 W1 and nu: 2n each),
-    the three derivative terms per order (5 each, 2.5 for LINEAR), the
-    window's N values (3 per position, ETD1), and the scaled outputs."""
-    orders = range(1, n)
-    rec = sum(K + (2 * K if K >= 2 else 0) + (2 * K if K >= 3 else 0) + 2 for K in orders)
-    sums = sum(5 * K - 3 for K in orders)
+    (2 per multiply-add; unshifted, dispersion-free): the moment recursion over
+    the moments that can be non-zero (_moment_terms; plus one coefficient
+    multiply per order), the three moment sums per order (M(1), its integral
+    and its first moment: 5c - 3 for c entries), the contractions per order
+    with the table row (W0 and tau, and for ETD1 W1 and nu: 2n each), the
+    three derivative terms per order (5 each, 2.5 for LINEAR), the window's N
+    values (3 per position, ETD1), and the scaled outputs."""
+    mt = _moment_terms(n)
+    rec = sum(2 * t - c + 1 for c, t in mt)
+    sums = sum(5 * c - 3 for c, t in mt)
     con = (n - 1) * (2 * n) * (4 if p >= 1 else 2)
     der = (n - 1) * 3 * (5 if p >= 1 else 2.5)
     nval = 3 * n if p >= 1 else 0
