@@ -58,10 +58,10 @@ def taylor_flops(n: int, fused: bool) -> float:
     the moment recursion over the moments that can be non-zero (_moment_terms;
     plus the scaled diffusion coefficient per order from order 2), the two
     moment sums per order (exponential: adds; phi1: multiply-adds), the
-    contraction with the table rows (2 n multiply-adds per order), the dt
-    scaling of W1, and with fusion the derivative at the node (n multiplies +
-    n multiply-adds) and the stencil sum W0.u + W1.N with
-    N_j = -g (u_j - u_i) d_j (7 per position)."""
+    contraction with the table rows (2 n multiply-adds per order), the
+    scaling of W1 (by dt, or with fusion by -g dt), and with fusion the
+    derivative at the node (n multiplies + n multiply-adds) and the stencil sum
+    W0.u + W1.N' with N'_j = (u_j - u_i) d_j (6 per position)."""
     f = 0.0
     for K, (c, t) in enumerate(_moment_terms(n), start=1):
         f += 2 * t - c + (1 if K >= 2 else 0)   # every entry's first term is a product
@@ -69,7 +69,7 @@ def taylor_flops(n: int, fused: bool) -> float:
         f += 4.0 * n                             # contraction
     f += n
     if fused:
-        f += 3.0 * n + 7.0 * n
+        f += 3.0 * n + 6.0 * n
     return f
 
 

@@ -39,8 +39,9 @@
 // derivative (du/dx)_j (from each position's own window, as in the Pade
 // kernel's fused step) for its nodes and a halo of n - 1 positions on each side
 // in LDS; each node then forms u+_i = sum_j W0[j] u_j + W1[j] N_j with
-// N_j = -g (u_j - u_i) (du/dx)_j over its window, and the weights never leave
-// registers.  Without FUSE the weights are written in the per-node layout.
+// N_j = -g (u_j - u_i) (du/dx)_j over its window (the factor -g rides on W1
+// with dt), and the weights never leave registers.  Without FUSE the weights
+// are written in the per-node layout.
 #include "lmep_device.hpp"
 
 namespace lmep {
@@ -235,8 +236,10 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
 
     double W0[NN], W1[NN];
     node_weights<NN>(active, r, sh, disp, a, b, e, taylor, nullptr, W0, W1);
+    // fused: W1 carries -g dt, so the window term is (u_j - u_i) d_j
+    const double w1s = FUSE ? -g * dt : dt;
 #pragma unroll
-    for (int j = 0; j < NN; ++j) W1[j] *= dt;
+    for (int j = 0; j < NN; ++j) W1[j] *= w1s;
 
     if constexpr (FUSE) {
         const int base = tid + H - r;  // slot of window position 0
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
             const double uj = su[base + j];
-            const double Nj = -g * (uj - ui) * sd[base + j];
+            const double Nj = (uj - ui) * sd[base + j];
             acc = fma(W0[j], uj, acc);
             acc = fma(W1[j], Nj, acc);
         }
@@ -365,13 +368,14 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
             const int sh = (int)rint(half);
             double W0[NN], W1[NN];
             node_weights<NN>(active, r, sh, disp, a, b, e, taylor, dir ? lt : nullptr, W0, W1);
+            const double w1s = -g * dt;  // as in the one-step kernel
 #pragma unroll
-            for (int j = 0; j < NN; ++j) W1[j] *= dt;
+            for (int j = 0; j < NN; ++j) W1[j] *= w1s;
             double acc = 0.0;
 #pragma unroll
             for (int j = 0; j < NN; ++j) {
                 const double uj = lds[cu + te + o + j];
-                const double Nj = -g * (uj - ui) * lds[cd + te + o + j];
+                const double Nj = (uj - ui) * lds[cd + te + o + j];
                 acc = fma(W0[j], uj, acc);
                 acc = fma(W1[j], Nj, acc);
             }
