@@ -47,10 +47,37 @@
 namespace lmep {
 namespace {
 
+// The recursion's per-order coefficients 2 k b and 3 k (k - 1) e.  They are
+// fixed for an instance and step size: the multi-step kernel forms them once
+// per launch (CoefTable); elsewhere each is formed where it is used
+// (CoefAtUse), which keeps fewer registers live.  Same values either way.
+struct CoefAtUse {
+    double b, e;
+    __device__ __forceinline__ double bk(int k) const { return (double)(2 * k) * b; }
+    __device__ __forceinline__ double ek(int k) const { return (double)(3 * k * (k - 1)) * e; }
+};
+template <int NN>
+struct CoefTable {
+    double bk_[NN], ek_[NN];
+    __device__ __forceinline__ double bk(int k) const { return bk_[k]; }
+    __device__ __forceinline__ double ek(int k) const { return ek_[k]; }
+};
+template <int NN>
+__device__ __forceinline__ CoefTable<NN> coef_table(double b, double e) {
+    const CoefAtUse u{b, e};
+    CoefTable<NN> c;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+        c.bk_[k] = u.bk(k);
+        c.ek_[k] = u.ek(k);
+    }
+    return c;
+}
+
 // Weights of one node from table row T (T[k * TS + j] = T_k[r'][j]).
 // SHIFT: s != 0; DISP: e != 0.
-template <int NN, bool SHIFT, bool DISP, int TS>
-__device__ __forceinline__ void taylor_weights(double a, double b, double e, double s,
+template <int NN, bool SHIFT, bool DISP, int TS, class CF>
+__device__ __forceinline__ void taylor_weights(double a, const CF& cf, double s,
                                                const double* __restrict__ T, double (&W0)[NN], double (&W1)[NN]) {
     double m2[NN], m1[NN], m0[NN];  // mu[k-2][.], mu[k-1][.], mu[k][.]
 #pragma unroll
@@ -73,8 +100,8 @@ __device__ __forceinline__ void taylor_weights(double a, double b, double e, dou
     constexpr auto lo = [](int k) constexpr { return SHIFT ? 0 : (DISP ? (k + 2) / 3 : (k + 1) / 2); };
 #pragma unroll
     for (int k = 0; k + 1 < NN; ++k) {
-        const double bk = (double)(2 * k) * b;
-        const double ek = (double)(3 * k * (k - 1)) * e;
+        const double bk = cf.bk(k);
+        const double ek = cf.ek(k);
         double nx[NN];
 #pragma unroll
         for (int m = 0; m < NN; ++m) {
@@ -110,13 +137,13 @@ __device__ __forceinline__ void taylor_weights(double a, double b, double e, dou
     }
 }
 
-template <int NN, bool SHIFT, int TS = kMaxN>
-__device__ __forceinline__ void taylor_weights_d(bool disp, double a, double b, double e, double s,
+template <int NN, bool SHIFT, int TS = kMaxN, class CF>
+__device__ __forceinline__ void taylor_weights_d(bool disp, double a, const CF& cf, double s,
                                                  const double* __restrict__ T, double (&W0)[NN], double (&W1)[NN]) {
     if (disp)
-        taylor_weights<NN, SHIFT, true, TS>(a, b, e, s, T, W0, W1);
+        taylor_weights<NN, SHIFT, true, TS, CF>(a, cf, s, T, W0, W1);
     else
-        taylor_weights<NN, SHIFT, false, TS>(a, b, e, s, T, W0, W1);
+        taylor_weights<NN, SHIFT, false, TS, CF>(a, cf, s, T, W0, W1);
 }
 
 // The n x n x n block of the table for this stencil size, copied to LDS as
@@ -135,8 +162,8 @@ __device__ __forceinline__ void stage_taylor_block(const double* __restrict__ ta
 // table block when the kernel holds one (lt != nullptr), else from the table
 // in global memory.  Lanes with the same (r, sh) get the same values either
 // way.
-template <int NN>
-__device__ __forceinline__ void node_weights(bool active, int r, int sh, bool disp, double a, double b, double e,
+template <int NN, class CF>
+__device__ __forceinline__ void node_weights(bool active, int r, int sh, bool disp, double a, const CF& cf,
                                              const double* __restrict__ taylor, const double* lt, double (&W0)[NN],
                                              double (&W1)[NN]) {
     const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
@@ -146,9 +173,9 @@ __device__ __forceinline__ void node_weights(bool active, int r, int sh, bool di
     if (__ballot(active && (r != r0 || rp != rp0)) == 0) {
         const double* __restrict__ T = tb + rp0 * (kMaxN * kMaxN);
         if (rp0 == r0)
-            taylor_weights_d<NN, false>(disp, a, b, e, 0.0, T, W0, W1);
+            taylor_weights_d<NN, false>(disp, a, cf, 0.0, T, W0, W1);
         else
-            taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp0 - r0), T, W0, W1);
+            taylor_weights_d<NN, true>(disp, a, cf, (double)(rp0 - r0), T, W0, W1);
     } else if (lt) {
         const double* lr = lt + rp * (NN * NN);
         if constexpr (NN <= 7) {
@@ -157,12 +184,12 @@ __device__ __forceinline__ void node_weights(bool active, int r, int sh, bool di
             double Tl[NN * NN];
 #pragma unroll
             for (int i = 0; i < NN * NN; ++i) Tl[i] = lr[i];
-            taylor_weights_d<NN, true, NN>(disp, a, b, e, (double)(rp - r), Tl, W0, W1);
+            taylor_weights_d<NN, true, NN>(disp, a, cf, (double)(rp - r), Tl, W0, W1);
         } else {
-            taylor_weights_d<NN, true, NN>(disp, a, b, e, (double)(rp - r), lr, W0, W1);
+            taylor_weights_d<NN, true, NN>(disp, a, cf, (double)(rp - r), lr, W0, W1);
         }
     } else {
-        taylor_weights_d<NN, true>(disp, a, b, e, (double)(rp - r), tb + rp * (kMaxN * kMaxN), W0, W1);
+        taylor_weights_d<NN, true>(disp, a, cf, (double)(rp - r), tb + rp * (kMaxN * kMaxN), W0, W1);
     }
 }
 
@@ -235,7 +262,7 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
     const int sh = (int)rint(half);
 
     double W0[NN], W1[NN];
-    node_weights<NN>(active, r, sh, disp, a, b, e, taylor, nullptr, W0, W1);
+    node_weights<NN>(active, r, sh, disp, a, CoefAtUse{b, e}, taylor, nullptr, W0, W1);
     // fused: W1 carries -g dt, so the window term is (u_j - u_i) d_j
     const double w1s = FUSE ? -g * dt : dt;
 #pragma unroll
@@ -334,6 +361,15 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
     for (int i = tid; i < NN * NN; i += nt) lfd[i] = fd[fd_index(NN, 0, i / NN, i % NN)] * ih;
     __syncthreads();
     int lo = g_lo, hi = g_hi;  // slots whose current u is valid
+    // loop invariants, formed by the same expressions as in the one-step
+    // kernel; held in registers across the steps up to n = 9 (beyond, they
+    // would spill and are formed at each use instead)
+    constexpr bool HOIST = NN <= 9;
+    const CoefTable<NN> cf0 =
+        coef_table<NN>(HOIST ? P.nu * ih * ih * dt : 0.0, HOIST ? -P.delta * ih * ih * ih * dt : 0.0);
+    double fdc[NN];  // centred first-derivative row
+#pragma unroll
+    for (int l = 0; l < NN; ++l) fdc[l] = HOIST ? fd[fd_index(NN, 0, R, l)] * ih : 0.0;
     for (int st = 0; st < ksteps; ++st) {
         const bool lend = dir && v0 + lo == 0, rend = dir && v0 + hi == N;  // grid ends: nothing spoilt
         const int nlo = lend ? lo : lo + 2 * rw, nhi = rend ? hi : hi - 2 * rw;  // slots updated this step
@@ -342,9 +378,10 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
             const int64_t j = map_index(v0 + t, N, bc);
             const int oj = (int)window_offset(j, N, NN, bc, P.window, P.c + g * lds[cu + t]);
             double dv = 0.0;
-            if (oj == -R) {  // centred: a compile-time row, loaded once outside the step loop
+            if (oj == -R) {  // centred row
 #pragma unroll
-                for (int l = 0; l < NN; ++l) dv += (fd[fd_index(NN, 0, R, l)] * ih) * lds[cu + t - R + l];
+                for (int l = 0; l < NN; ++l)
+                    dv += (HOIST ? fdc[l] : fd[fd_index(NN, 0, R, l)] * ih) * lds[cu + t - R + l];
             } else {
                 const double* fr = lfd + (-oj) * NN;
 #pragma unroll
@@ -363,11 +400,15 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
             const double ceff = P.c + g * ui;
             const int o = (int)window_offset(i, N, NN, bc, P.window, ceff);
             const int r = -o;
-            const double a = -ceff * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
+            const double a = -ceff * ih * dt;
             const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
             const int sh = (int)rint(half);
             double W0[NN], W1[NN];
-            node_weights<NN>(active, r, sh, disp, a, b, e, taylor, dir ? lt : nullptr, W0, W1);
+            if constexpr (HOIST)
+                node_weights<NN>(active, r, sh, disp, a, cf0, taylor, dir ? lt : nullptr, W0, W1);
+            else
+                node_weights<NN>(active, r, sh, disp, a, CoefAtUse{P.nu * ih * ih * dt, -P.delta * ih * ih * ih * dt},
+                                 taylor, dir ? lt : nullptr, W0, W1);
             const double w1s = -g * dt;  // as in the one-step kernel
 #pragma unroll
             for (int j = 0; j < NN; ++j) W1[j] *= w1s;
