@@ -203,9 +203,11 @@ def plain_forward(problems, states, steps, max_instances=None):
     return sum(int(p["N"]) for p in problems[:k]) * steps / el, k
 
 
-def bench_adjoint(problems, states, steps, every=50):
+def bench_adjoint(problems, states, steps, every=None):
     """Forward with checkpoints + reverse through lmep_adjoint_step; returns
-    (seconds, node-steps) with node-steps = nodes x steps."""
+    (seconds, node-steps, checkpoint interval) with node-steps = nodes x steps.
+    every=None: autograd's choice (every state when they fit in half the free
+    device memory)."""
     import torch
     import paper_2603_15964_amd as lmep
     from paper_2603_15964_amd import autograd as lad
@@ -213,13 +215,15 @@ def bench_adjoint(problems, states, steps, every=50):
     u0 = batch.pack(states).requires_grad_(True)
     nu = torch.tensor([p["nu"] for p in problems], dtype=torch.float64, device="cuda:0", requires_grad=True)
     target = torch.zeros_like(u0)
+    if every is None:
+        every = lad.auto_checkpoint_every(batch, steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     uT = lad.solve(batch, u0, steps, nu=nu, checkpoint_every=every)
     loss = 0.5 * torch.sum((uT - target) ** 2)
     loss.backward()
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, batch.state_size * steps
+    return time.perf_counter() - t0, batch.state_size * steps, every
 
 
 def pair_pade_flops(m: int, squarings: float) -> float:
@@ -389,13 +393,13 @@ def main():
     if args.workload == "burgers_adjoint":
         wu = max(1, min(args.warmup, 10))  # a short warm-up: its checkpoint segment holds every state
         bench_adjoint(problems, states, wu, every=wu)
-        secs, node_steps = bench_adjoint(problems, states, args.steps)
+        secs, node_steps, every = bench_adjoint(problems, states, args.steps)
         out = {"metric": "node-steps/s (weight build+apply, FP64), adjoint: forward + checkpointed reverse",
                "value": node_steps / secs, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
                "warmup": args.warmup, "ms_per_step": secs * 1e3 / args.steps, "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
                "config": {"workload": desc, "instances": len(problems), "nodes": sum(p["N"] for p in problems),
-                          "checkpoint_every": 50},
+                          "checkpoint_every": every},
                "roofline": adjoint_roofline(problems, states)}
         if not args.no_plain:
             pv, pk = plain_forward(problems, states, min(args.steps, 50))

@@ -1,17 +1,21 @@
 """Differentiable LMEP time stepping: torch.autograd.Function over the C ABI.
 
 Forward: ``lmep_step`` over ``steps`` steps, keeping the state every
-``checkpoint_every`` steps.  Backward: for each segment, last first, the
-states of the segment are recomputed from its checkpoint one step at a time
-and ``lmep_adjoint_step`` (Frechet derivative of every local exponential
-from the block-triangular exponential, plus the transposed banded apply) is
-applied backwards through them.  The result is the gradient with respect to
+``checkpoint_every`` steps (by default every step when all states fit in half
+the free device memory, which on a 288 GB GPU is the common case, so nothing
+is recomputed).  Backward: for each segment, last first, the states of the
+segment are recomputed from its checkpoint one step at a time and
+``lmep_adjoint_step`` (derivative of every node's weights -- by the finite
+Taylor series where it applies, else by the block-triangular Pade exponential
+-- plus the transposed banded apply) is applied backwards through them.  The result is the gradient with respect to
 the initial state and to the per-instance coefficients nu, c and delta.
 
 Only the bookkeeping (which state to recompute, which adjoint to pass on)
 happens here; every derivative is computed by the library's kernels.
 """
 from __future__ import annotations
+
+import math
 
 import torch
 
@@ -59,13 +63,33 @@ class _Solve(torch.autograd.Function):
         return lam, g[:, 0].clone(), g[:, 1].clone(), g[:, 2].clone(), None, None, None
 
 
-def solve(batch: Batch, u0: torch.Tensor, steps: int, nu=None, c=None, delta=None, checkpoint_every: int = 50):
+def checkpoint_interval(steps: int, state_bytes: int, free_bytes: int, budget: float = 0.5) -> int:
+    """Checkpoint interval: 1 (keep every state, no recomputation in the
+    backward pass) when all `steps` states fit in `budget` of the free device
+    memory, else ceil(sqrt(steps)), which keeps about 2 sqrt(steps) states
+    alive (the checkpoints plus one recomputed segment)."""
+    steps = max(1, int(steps))
+    if steps * state_bytes <= budget * free_bytes:
+        return 1
+    return math.isqrt(steps - 1) + 1
+
+
+def auto_checkpoint_every(batch: Batch, steps: int) -> int:
+    """checkpoint_interval() for this batch on its device's free memory now."""
+    free, _ = torch.cuda.mem_get_info(torch.device(batch.device))
+    return checkpoint_interval(steps, batch.state_size * 8, free)
+
+
+def solve(batch: Batch, u0: torch.Tensor, steps: int, nu=None, c=None, delta=None, checkpoint_every=None):
     """Advance the batch `steps` steps from the packed state u0, differentiably.
 
     nu, c, delta are optional per-instance tensors (shape [count]); when
     omitted, the batch's own coefficients are used (with zero gradient).
+    checkpoint_every=None picks the interval by auto_checkpoint_every().
     """
     dev = batch.device
+    if checkpoint_every is None:
+        checkpoint_every = auto_checkpoint_every(batch, steps)
 
     def coef(x, key):
         if x is not None:

@@ -97,7 +97,7 @@ def test_batched_reverse_step_equals_single():
         assert np.array_equal(g1.cpu().numpy(), gr[k])
 
 
-@pytest.mark.parametrize("every", [1, 4, 50])
+@pytest.mark.parametrize("every", [1, 4, 50, None])
 def test_checkpointed_gradient_matches_oracle_and_fd(every):
     """loss = 0.5 ||u(T) - target||^2, target made with nu * 1.1 (C5 recipe,
     small grid): gradients w.r.t. u0 and nu against the oracle's adjoint run
