@@ -347,7 +347,7 @@ def main():
                          "otherwise; --persistent is the same as --launch persistent")
     ap.add_argument("--steps-per-launch", type=int, default=None, choices=(1, 2, 4, 8),
                     help="steps per launch of the multi-step path (default 8; for --launch auto on frozen "
-                         "velocity the deepest whose half-size region keeps 128 written nodes)")
+                         "velocity the deepest whose largest region (512 positions) keeps 128 written nodes)")
     ap.add_argument("--tune", action="store_true",
                     help="let the autotuner pick fusion / steps per launch / apply tile (cached per GPU and shape)")
     ap.add_argument("--exp-method", choices=("auto", "pade"), default="auto",
@@ -382,10 +382,11 @@ def main():
         small = sum(int(p["N"]) for p in problems) < (1 << 20)
         args.persistent = frozen_all and covered and small and args.exp_method == "auto"
         if args.persistent and args.steps_per_launch is None:
-            # deepest launch whose 256-position region still writes 128 nodes per block
-            # (the halo grows by n - 1 per step, 2 (n - 1) for one-sided windows)
+            # deepest launch whose largest region (512 positions; the library sizes
+            # regions per CU up to that) still writes 128 nodes per block (the halo
+            # grows by n - 1 per step, 2 (n - 1) for one-sided windows)
             reach = max((2 if p.get("window", "centred") == "upwind" else 1) * (int(p["n"]) - 1) for p in problems)
-            args.steps_per_launch = next((kb for kb in (8, 4, 2) if 256 - 2 * kb * reach >= 128), 1)
+            args.steps_per_launch = next((kb for kb in (8, 4, 2) if 512 - 2 * kb * reach >= 128), 1)
     if args.steps_per_launch is None:
         args.steps_per_launch = 8
     lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD,
