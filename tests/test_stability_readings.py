@@ -80,7 +80,7 @@ def test_burgers_dirichlet_reading_is_stable():
 
 
 def test_burgers_literal_cfl8_is_unstable():
-    """CFL 8 with a centred n = 7 stencil amplifies (survey reading of 'CFL up to 8')."""
+    """CFL 8 with a centred n = 7 stencil amplifies (the reading of the paper's 'CFL up to 8')."""
     h = 0.04
     p = make_problem(N=256, n=7, bc="periodic", h=h, c=1.0, nu=1e-2, dt=8 * h)
     g, _ = max_amplification(p)
