@@ -249,3 +249,54 @@ def test_fused_reverse_step_edges_match_oracle(name, p):
     for k in range(3):
         scale = max(abs(wgrad[k]), 1e-12 * np.max(np.abs(wgrad)), 1e-300)
         assert abs(gr[0][k] - wgrad[k]) <= 1e-10 * scale, (k, gr[0][k], wgrad[k])
+
+
+def test_checkpointed_gradient_in_c_and_along_u0():
+    """The C5 recipe on a small grid with a per-instance advection speed c
+    (0.05 and -0.03): the gradients w.r.t. u0, nu and c against the oracle's
+    adjoint run (1e-10), and against central differences of the oracle's own
+    loss (h = 1e-6) in c, along 4 seeded unit directions of u0 per instance and
+    at 8 single coordinates.  Rounding in the oracle's loss enters a difference
+    as about sqrt(N) |u(T) - target|_inf eps / h (below 1e-12 here) and the
+    O(h^2) truncation is smaller still, so 1e-6 of each derivative bounds the
+    difference with margin."""
+    _case("checkpointed gradient in c and along u0")
+    p, pt, u0s = workloads.burgers_adjoint_batch(batch=2, N=600)
+    steps, every, hfd = 9, 4, 1e-6
+    cs = [0.05, -0.03]
+    probs = [dict(p, c=c) for c in cs]
+    targets = [oracle.run(dict(pt, c=c), u0, steps) for c, u0 in zip(cs, u0s)]
+    b = lmep.Batch(probs, device=DEV)
+    u0 = b.pack(u0s).requires_grad_(True)
+    nu = torch.full((2,), p["nu"], dtype=torch.float64, device=DEV, requires_grad=True)
+    c = torch.tensor(cs, dtype=torch.float64, device=DEV, requires_grad=True)
+    uT = lad.solve(b, u0, steps, nu=nu, c=c, checkpoint_every=every)
+    loss = 0.5 * torch.sum((uT - b.pack(targets)) ** 2)
+    loss.backward()
+    gu = b.unpack(u0.grad)
+    gnu, gc = nu.grad.cpu().numpy(), c.grad.cpu().numpy()
+
+    def oloss(k, q=None, du=None):
+        x0 = u0s[k] if du is None else u0s[k] + du
+        return 0.5 * np.sum((oracle.run(probs[k] if q is None else q, x0, steps) - targets[k]) ** 2)
+
+    g = workloads.rng(9)
+    N = int(p["N"])
+    for k in range(2):
+        _, wgu, wg = oracle.adjoint_run(probs[k], u0s[k], targets[k], steps)
+        assert _rel(gu[k], wgu) <= 1e-10
+        assert abs(gnu[k] - wg[0]) <= 1e-10 * abs(wg[0])
+        assert abs(gc[k] - wg[1]) <= 1e-10 * abs(wg[1])
+        fd = (oloss(k, q=dict(probs[k], c=cs[k] + hfd)) - oloss(k, q=dict(probs[k], c=cs[k] - hfd))) / (2 * hfd)
+        assert abs(gc[k] - fd) <= 1e-6 * abs(fd), (k, gc[k], fd)
+        for _ in range(4):
+            d = g.normal(size=N)
+            d[0] = d[-1] = 0.0  # Dirichlet ends are held, not state
+            d /= np.linalg.norm(d)
+            fd = (oloss(k, du=hfd * d) - oloss(k, du=-hfd * d)) / (2 * hfd)
+            assert abs(gu[k] @ d - fd) <= 1e-6 * abs(fd), (k, gu[k] @ d, fd)
+        for i in g.integers(1, N - 1, size=4):
+            e = np.zeros(N)
+            e[i] = 1.0
+            fd = (oloss(k, du=hfd * e) - oloss(k, du=-hfd * e)) / (2 * hfd)
+            assert abs(gu[k][i] - fd) <= 1e-6 * abs(fd), (k, i, gu[k][i], fd)
