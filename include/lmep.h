@@ -184,6 +184,28 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
               double* d_u_out, int32_t n_steps, uint32_t flags, void* d_scratch,
               size_t scratch_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory or hand over a workspace
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): lmep_step without the scratch argument.  Same arguments, checks
+ * and results, bit for bit, as lmep_step with the same flags.  The scratch is
+ * a static array of LMEP_NOALLOC_SCRATCH_BYTES in each device's memory, which
+ * the library holds from the first call on that device until the process
+ * ends; the call allocates nothing (no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating routine) and passes the problem tables to the device
+ * through kernel arguments, so nothing in host memory has to outlive it.
+ *  - flags: 0 or LMEP_F_PERSISTENT; any other bit is LMEP_ERR_ARG.
+ *  - A batch whose lmep_scratch_bytes(prob, count, 1) exceeds
+ *    LMEP_NOALLOC_SCRATCH_BYTES returns LMEP_ERR_SCRATCH (the step needs 8
+ *    bytes per node of the packed state extent plus about 0.5 KB per instance,
+ *    so about 8 million nodes at most).
+ *  - Every call on a device uses that device's one array, which keeps the
+ *    last call's contents; nothing in it has to start at zero.  Calls ordered
+ *    on one stream are safe; calls that overlap on one device (other streams,
+ *    or other threads without ordering) race and give wrong results. */
+#define LMEP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lmep_step_noalloc(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in,
+                      double* d_u_out, int32_t n_steps, uint32_t flags, void* hip_stream);
+
 /* Reverse of one LINEAR or ETD1 step (not ETD2RK / ETDRK4 / KDV).  Given the forward
  * state d_u_k = u^k and d_lambda_next = d loss / d u^{k+1}, write
  * d_lambda_k = d loss / d u^k and add this step's parameter derivatives to

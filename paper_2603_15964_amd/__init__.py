@@ -27,7 +27,7 @@ from ._native import (  # noqa: F401  (re-exported names of the C ABI)
     LMEP_OPT_EXP_METHOD, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_PROFILE_ADJOINT, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_WIN_CENTRED,
     LMEP_WIN_UPWIND, OP_ADJOINT, OP_BUILD, OP_STEP, LmepError, library, lmep_adjoint_step, lmep_build_weights,
     lmep_get_option, lmep_last_error, lmep_problem, lmep_profile_last, lmep_scratch_bytes, lmep_set_option, lmep_step,
-    lmep_weight_count, problem_array, to_struct)
+    lmep_step_noalloc, lmep_weight_count, problem_array, to_struct, LMEP_NOALLOC_SCRATCH_BYTES)
 
 _KINDS = {"linear": 1, "etd1": 2, "etd2rk": 3, "etdrk4": 6}
 
@@ -141,5 +141,5 @@ class Batch:
 
 
 __all__ = ["Batch", "LmepError", "lmep_problem", "lmep_build_weights", "lmep_step", "lmep_adjoint_step",
-           "lmep_scratch_bytes", "lmep_weight_count", "lmep_last_error", "lmep_profile_last", "lmep_set_option",
+           "lmep_step_noalloc", "lmep_scratch_bytes", "lmep_weight_count", "lmep_last_error", "lmep_profile_last", "lmep_set_option",
            "lmep_get_option", "library"]

@@ -68,6 +68,7 @@ _lib.lmep_scratch_bytes.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
 _lib.lmep_scratch_bytes.restype = ctypes.c_size_t
 _lib.lmep_build_weights.argtypes = [_P, ctypes.c_int32, _V, _V, _V, ctypes.c_size_t, _V]
 _lib.lmep_step.argtypes = [_P, ctypes.c_int32, _V, _V, _V, ctypes.c_int32, ctypes.c_uint32, _V, ctypes.c_size_t, _V]
+_lib.lmep_step_noalloc.argtypes = [_P, ctypes.c_int32, _V, _V, _V, ctypes.c_int32, ctypes.c_uint32, _V]
 _lib.lmep_adjoint_step.argtypes = [_P, ctypes.c_int32, _V, _V, _V, _V, _V, ctypes.c_size_t, _V]
 _lib.lmep_profile_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
@@ -77,8 +78,9 @@ _lib.lmep_set_option.argtypes = [ctypes.c_int32, ctypes.c_int32]
 _lib.lmep_get_option.argtypes = [ctypes.c_int32]
 _lib.lmep_get_option.restype = ctypes.c_int32
 
-EXPORTED = ("lmep_weight_count", "lmep_scratch_bytes", "lmep_build_weights", "lmep_step", "lmep_adjoint_step",
-            "lmep_profile_last", "lmep_last_error", "lmep_set_option", "lmep_get_option")
+EXPORTED = ("lmep_weight_count", "lmep_scratch_bytes", "lmep_build_weights", "lmep_step", "lmep_step_noalloc",
+            "lmep_adjoint_step", "lmep_profile_last", "lmep_last_error", "lmep_set_option", "lmep_get_option")
+LMEP_NOALLOC_SCRATCH_BYTES = 64 << 20
 LMEP_OPT_STEPS_PER_LAUNCH = 1
 LMEP_OPT_PROFILE_ADJOINT = 2
 LMEP_OPT_FUSE_FROZEN = 3
@@ -147,6 +149,10 @@ def lmep_build_weights(probs, count, d_u, d_w, d_scratch, scratch_bytes, stream)
 
 def lmep_step(probs, count, d_w, d_u_in, d_u_out, n_steps, flags, d_scratch, scratch_bytes, stream) -> None:
     _check(_lib.lmep_step(probs, count, d_w, d_u_in, d_u_out, n_steps, flags, d_scratch, scratch_bytes, stream))
+
+
+def lmep_step_noalloc(probs, count, d_w, d_u_in, d_u_out, n_steps, flags, stream) -> None:
+    _check(_lib.lmep_step_noalloc(probs, count, d_w, d_u_in, d_u_out, n_steps, flags, stream))
 
 
 def lmep_adjoint_step(probs, count, d_u_k, d_lambda_next, d_lambda_k, d_grad, d_scratch, scratch_bytes,

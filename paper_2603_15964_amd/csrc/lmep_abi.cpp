@@ -22,6 +22,7 @@
 using namespace lmep;
 
 // The Python binding mirrors this layout field by field.
+static_assert(LMEP_NOALLOC_SCRATCH_BYTES == kStaticScratchBytes, "static scratch size");
 static_assert(offsetof(lmep_problem, window) == 112 && offsetof(lmep_problem, x) == 120 &&
                   sizeof(lmep_problem) == 128,
               "lmep_problem layout");
@@ -383,10 +384,18 @@ struct Staging {
 };
 thread_local Staging t_stage;
 
+// by_args: write the tables through kernel arguments (upload_by_args) instead,
+// which needs no pinned host buffer (lmep_step_noalloc).
 int upload(const std::vector<DevProb>& a, const std::vector<DevProb>& b, void* d_a, void* d_b, hipStream_t s,
-           const std::vector<int>* c = nullptr, void* d_c = nullptr) {
+           const std::vector<int>* c = nullptr, void* d_c = nullptr, bool by_args = false) {
     const size_t na = a.size() * sizeof(DevProb), nb = b.size() * sizeof(DevProb);
     const size_t nc = c ? c->size() * sizeof(int) : 0;
+    if (by_args) {
+        if (na) HIP_TRY(upload_by_args(d_a, a.data(), na, s));
+        if (nb) HIP_TRY(upload_by_args(d_b, b.data(), nb, s));
+        if (nc) HIP_TRY(upload_by_args(d_c, c->data(), nc, s));
+        return LMEP_OK;
+    }
     Staging& st = t_stage;
     if (!st.done) HIP_TRY(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     if (st.pending) {
@@ -564,8 +573,16 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
     return LMEP_OK;
 }
 
-int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
-              int32_t n_steps, uint32_t flags, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// lmep_step and lmep_step_noalloc.  noalloc: the scratch is this device's
+// static array (d_scratch and scratch_bytes are ignored) and the tables go in
+// through kernel arguments.
+int step_impl(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
+              int32_t n_steps, uint32_t flags, void* d_scratch, size_t scratch_bytes, void* hip_stream,
+              bool noalloc) {
     int rc = check_all(prob, count, true);
     if (rc) return rc;
     if (!d_w || !d_u_in || !d_u_out) return fail(LMEP_ERR_ARG, "NULL weight or state pointer");
@@ -594,7 +611,16 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
         if (a < b + bytes && b < a + bytes) return fail(LMEP_ERR_ARG, "d_u_in and d_u_out overlap");
     }
     const Layout L = layout(prob, count, 1);
-    if ((rc = entry_checks(d_scratch, scratch_bytes, L.total))) return rc;
+    if (noalloc) {
+        if (L.total > kStaticScratchBytes)
+            return fail(LMEP_ERR_SCRATCH, "this batch needs %zu bytes of scratch; the static array holds %zu",
+                        L.total, kStaticScratchBytes);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "earlier device error: %s", hipGetErrorString(e));
+        HIP_TRY(static_scratch(&d_scratch));
+    } else if ((rc = entry_checks(d_scratch, scratch_bytes, L.total))) {
+        return rc;
+    }
     hipStream_t s = (hipStream_t)hip_stream;
     const double* fd = nullptr;
     HIP_TRY(fd_table_init(&fd));
@@ -614,7 +640,8 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
     for (auto& gr : agroups) all_resident &= gr.resident;
     const int launches = all_resident ? 1 : (n_steps + kb - 1) / kb;  // apply launches per group
     char* base = (char*)d_scratch;
-    if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s, &tile_inst, base + L.tile_inst)))
+    if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s, &tile_inst, base + L.tile_inst,
+                     noalloc)))
         return rc;
     const DevProb* dbt = (const DevProb*)(base + L.build_tab);
     const DevProb* dat = (const DevProb*)(base + L.apply_tab);
@@ -747,6 +774,22 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
         if (hflag) return fail(LMEP_ERR_NONFINITE, "non-finite value in the result");
     }
     return LMEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
+              int32_t n_steps, uint32_t flags, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
+    return step_impl(prob, count, d_w, d_u_in, d_u_out, n_steps, flags, d_scratch, scratch_bytes, hip_stream, false);
+}
+
+int lmep_step_noalloc(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
+                      int32_t n_steps, uint32_t flags, void* hip_stream) {
+    if (flags & ~LMEP_F_PERSISTENT)
+        return fail(LMEP_ERR_ARG, "lmep_step_noalloc takes LMEP_F_PERSISTENT only, got flags 0x%x", flags);
+    return step_impl(prob, count, d_w, d_u_in, d_u_out, n_steps, flags, nullptr, 0, hip_stream, true);
 }
 
 int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u_k, const double* d_lambda_next,

@@ -196,6 +196,16 @@ hipError_t launch_adj_fused(const AdjointLaunch& a, hipStream_t stream);
 __host__ __device__ constexpr int adj_fused_tile(int n) { return kAdjTile - 4 * (n - 1); }
 static_assert(adj_fused_tile(15) >= 128, "fused reverse-step tile");
 
+// Scratch of lmep_step_noalloc (static_scratch.hip): a static array of
+// kStaticScratchBytes in every device's memory.  static_scratch() returns the
+// current device's address of it (looked up once per device);
+// upload_by_args() writes `bytes` (a multiple of 4) of host data to d_dst on
+// `stream` through the kernel arguments of small copy kernels, so nothing is
+// staged in host memory that would have to outlive the call.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+hipError_t static_scratch(void** d_out);
+hipError_t upload_by_args(void* d_dst, const void* host, size_t bytes, hipStream_t stream);
+
 // Finite check: writes 1 into *d_flag if any of the count doubles is not finite.
 hipError_t launch_check_finite(const double* d_x, int64_t count, int* d_flag, hipStream_t stream);
 

@@ -204,3 +204,18 @@ def test_nonuniform_checks():
     rc = lib.lmep_adjoint_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20),
                                ctypes.c_void_p(1 << 24), ctypes.c_void_p(256), 1 << 30, None)
     assert rc == lmep.LMEP_ERR_UNSUPPORTED
+
+
+def test_noalloc_step_checks_before_device_work():
+    """lmep_step_noalloc rejects flags other than LMEP_F_PERSISTENT and batches
+    whose scratch exceeds its static array, before touching a device."""
+    s = _structs()
+    rc = lmep.library().lmep_step_noalloc(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20),
+                                          ctypes.c_void_p(1 << 24), 1, lmep.LMEP_F_GRAPH, None)
+    assert rc == lmep.LMEP_ERR_ARG and "LMEP_F_PERSISTENT" in lmep.lmep_last_error()
+    big = lmep.problem_array([workloads.make_problem(N=9 << 20, n=5, bc="periodic", h=1e-3, dt=1e-4, c=1.0,
+                                                     scheme="linear")])
+    assert lmep.lmep_scratch_bytes(big, 1, lmep.OP_STEP) > lmep.LMEP_NOALLOC_SCRATCH_BYTES
+    rc = lmep.library().lmep_step_noalloc(big, 1, ctypes.c_void_p(8), ctypes.c_void_p(1 << 40),
+                                          ctypes.c_void_p(1 << 41), 1, 0, None)
+    assert rc == lmep.LMEP_ERR_SCRATCH and "static array" in lmep.lmep_last_error()
