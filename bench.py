@@ -1,16 +1,31 @@
 """Throughput of the LMEP hot path on one MI355X.
 
-Default workload: viscous Burgers u_t + u u_x = nu u_xx, N = 65536 nodes,
-Dirichlet ends with one-sided edge stencils, n = 7, ETD1 with the phi1 weights
-of the augmented local matrix rebuilt every step from the frozen local
-velocity (one FP64 Pade scaling-and-squaring exponential of an 8x8 local
-matrix per node per step), 1000 steps.  A "step" is one time step of the whole
-hot path: weight build for every node + banded apply.
+Default workload: the batched path -- 4096 independent Allen-Cahn instances
+(N_k uniform in [512, 65536], stencil n_k in {5, 7, 9, 11}, periodic or Neumann
+ends, ETD1 with phi1 weights of the augmented local matrix built once per
+instance) advanced 8 steps per launch.  A "step" is one time step of the whole
+hot path for every instance: the weights are stationary, so after the first
+build a step is the banded apply.
 
-Prints one JSON line: node-steps/s of the timed K steps (inputs resident in
-HBM), the roofline of the dominant kernel (the weight build, FP64 vector ALU)
-from HIP events recorded around each build launch in a second, profiled pass
-over the same K steps, and the CPU oracle timed on a bounded sample.
+Printed, one JSON line:
+  value     node-steps/s of the timed K steps of the batch (inputs resident in
+            HBM, wall clock between synchronisations);
+  roofline  the dominant kernel of those steps: algorithmic work per launch
+            over its average launch duration, from HIP events recorded around
+            each of its launches on the library's stream in a profiled pass
+            over the same K steps;
+  plain     the same instances one at a time through the single-instance
+            forward (one lmep_step per instance, one step per launch);
+  adjoint   the adjoint workload (64 Burgers trajectories of 262144 nodes,
+            500 steps, a checkpoint every 50, loss against the state reached
+            with nu * 1.1): forward + checkpointed reverse, beside its own
+            plain single-instance forward, with the roofline of the reverse
+            kernel;
+  single_instance  the viscous-Burgers workload (N = 65536, n = 7, weights
+            rebuilt every step from the frozen velocity), 1000 steps;
+  cpu_baseline  the oracle on a bounded sample of the batch, on the host's
+            cores and on one thread.
+Other workloads: --workload NAME (see make_workload).
 """
 from __future__ import annotations
 
@@ -203,27 +218,39 @@ def plain_forward(problems, states, steps, max_instances=None):
     return sum(int(p["N"]) for p in problems[:k]) * steps / el, k
 
 
-def bench_adjoint(problems, states, steps, every=None):
-    """Forward with checkpoints + reverse through lmep_adjoint_step; returns
-    (seconds, node-steps, checkpoint interval) with node-steps = nodes x steps.
-    every=None: autograd's choice (every state when they fit in half the free
-    device memory)."""
+def bench_adjoint(problems, states, steps, every, target=None):
+    """Forward with a checkpoint every `every` steps + reverse through
+    lmep_adjoint_step, loss 0.5 ||u(T) - target||^2 (target: the state the
+    same u0 reaches with nu * 1.1, or zeros); gradients w.r.t. u0 and nu.
+    Returns the wall seconds of forward + backward."""
     import torch
     import paper_2603_15964_amd as lmep
     from paper_2603_15964_amd import autograd as lad
     batch = lmep.Batch(problems, device="cuda:0")
     u0 = batch.pack(states).requires_grad_(True)
     nu = torch.tensor([p["nu"] for p in problems], dtype=torch.float64, device="cuda:0", requires_grad=True)
-    target = torch.zeros_like(u0)
-    if every is None:
-        every = lad.auto_checkpoint_every(batch, steps)
+    if target is None:
+        target = torch.zeros_like(u0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     uT = lad.solve(batch, u0, steps, nu=nu, checkpoint_every=every)
     loss = 0.5 * torch.sum((uT - target) ** 2)
     loss.backward()
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, batch.state_size * steps, every
+    return time.perf_counter() - t0
+
+
+def adjoint_target(problems, target_problems, states, steps):
+    """The state the same u0 reaches after `steps` steps with the target
+    problems (nu * 1.1)."""
+    import torch
+    import paper_2603_15964_amd as lmep
+    tb = lmep.Batch(target_problems, device="cuda:0")
+    w = tb.empty_weights()
+    with torch.no_grad():
+        out = tb.step(w, tb.pack(states), steps)
+    torch.cuda.synchronize()
+    return out
 
 
 def pair_pade_flops(m: int, squarings: float) -> float:
@@ -282,79 +309,262 @@ def adjoint_roofline(problems, states, reps: int = 5):
     mean_s = cnt["squarings"] / max(1, cnt["matrices"])
     batch.adjoint_step(u0, lam)  # warm-up
     lmep.lmep_set_option(lmep.LMEP_OPT_PROFILE_ADJOINT, 1)
-    fre_ms, launches, rest_ms = 0.0, 0, 0.0
+    fre_ms, launches, rest_ms, name = 0.0, 0, 0.0, None
     try:
+        pb = lmep.Batch(problems, device="cuda:0")  # a plan made with the profiling option
         for _ in range(reps):
-            batch.adjoint_step(u0, lam)
+            pb.adjoint_step(u0, lam)
             prof = lmep.lmep_profile_last()
             fre_ms += prof["build_ms"]
             launches += prof["build_launches"]
             rest_ms += prof["apply_ms"]
+            name = lmep.lmep_profile_kernels()[0][0]
     finally:
         lmep.lmep_set_option(lmep.LMEP_OPT_PROFILE_ADJOINT, 0)
     p0 = problems[0]
     m = p0["n"] + {"linear": 0, "etd1": 1}[p0["scheme"]]
-    taylor = (lmep.lmep_get_option(lmep.LMEP_OPT_EXP_METHOD) == lmep.LMEP_EXP_AUTO and
-              all(p.get("react", 0.0) == 0.0 for p in problems))
-    if taylor:
+    if name.startswith("adj_fused_kernel"):
         # the whole reverse step of a tile in one kernel (per-node part and gathers)
         flops = batch.state_size * adj_fused_flops(p0["n"], m - p0["n"]) * reps
-        kname = f"adj_fused_kernel<{p0['n']},{m - p0['n']}>"
         mean_s = 0.0
     else:
         flops = batch.state_size * pair_pade_flops(m, mean_s) * reps
-        kname = f"adj_frechet_kernel<{p0['n']},{m - p0['n']}>"
     tf = flops / (fre_ms / 1e3) / 1e12
     return {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": tf / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname], "burgers_adjoint"), "kernel": kname,
+            "frac": tf / PEAK_FP64_TFLOPS, "traffic": measured_traffic([name], "burgers_adjoint"), "kernel": name,
             "avg_launch_us": fre_ms * 1e3 / max(1, launches), "flops_per_launch": flops / max(1, launches),
+            "duration_from": "HIP events around each launch of the kernel",
             "mean_squarings": mean_s, "rest_of_reverse_step_us": rest_ms * 1e3 / reps}
 
 
-def cpu_baseline(problem, u0, budget_s: float = 15.0):
-    """The oracle as it stands, on a bounded number of steps of the same workload."""
+def _cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def _omp_threads(k=None):
+    """OpenMP threads of the oracle's runtime (libgomp), set to k if given."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    if k is not None:
+        gomp.omp_set_num_threads(int(k))
+    return int(gomp.omp_get_max_threads())
+
+
+def cpu_baseline(problems, states, budget_s: float = 12.0, one_thread_s: float = 6.0):
+    """The oracle as it stands, on a bounded sample of the workload: the first
+    instances of the batch (whole instances, weights built and applied by the
+    oracle's own run) for as many steps as fit the budget, on all the threads
+    its OpenMP runtime uses, then on one thread."""
     import oracle
-    t = time.perf_counter()
-    u = oracle.run(problem, u0, 1)
-    one = time.perf_counter() - t
-    steps = max(1, min(1000, int(budget_s / max(one, 1e-6))))
-    t = time.perf_counter()
-    oracle.run(problem, u, steps)
-    el = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": problem["N"] * steps / el, "unit": "node-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} steps of the same workload (N={problem['N']}) after 1 warm step"}
+
+    def sample(budget, steps=50):
+        # the first instance, timed at one and at three steps, gives the
+        # oracle's cost per node of its weight build and of a step
+        t = time.perf_counter()
+        oracle.run(problems[0], states[0], 1)
+        t1 = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.run(problems[0], states[0], 3)
+        t3 = time.perf_counter() - t
+        n0 = problems[0]["N"]
+        step_pn = max((t3 - t1) / 2, 1e-9) / n0
+        build_pn = max(t1 - (t3 - t1) / 2, 0.0) / n0
+        per_node = build_pn + steps * step_pn
+        k, nodes = 0, 0
+        while k < len(problems) and (nodes + problems[k]["N"]) * per_node <= budget:
+            nodes += problems[k]["N"]
+            k += 1
+        k = max(k, 1)
+        nodes = sum(int(p["N"]) for p in problems[:k])
+        t = time.perf_counter()
+        for p, u in zip(problems[:k], states[:k]):
+            oracle.run(p, u, steps)
+        el = time.perf_counter() - t
+        return nodes * steps / el, k, steps, nodes
+
+    model, nproc, usable = _cpu_info()
+    threads = _omp_threads()
+    v, k, steps, nodes = sample(budget_s)
+    out = {"value": v, "unit": "node-steps/s", "cores": threads or usable, "kind": "oracle",
+           "sample": f"first {k} of {len(problems)} instances ({nodes} nodes), {steps} steps each (weights built "
+                     f"by the oracle's own run)",
+           "cpu_model": model, "nproc": nproc, "usable_cpus": usable, "omp_threads": threads}
+    if threads and threads > 1:
+        _omp_threads(1)
+        try:
+            v1, k1, s1, n1 = sample(one_thread_s)
+        finally:
+            _omp_threads(threads)
+        out["one_thread"] = {"value": v1, "unit": "node-steps/s",
+                             "sample": f"first {k1} instances ({n1} nodes), {s1} steps each"}
+    return out
+
+
+def _parse_kernel(name):
+    """(base name, [template integers or booleans]) of a kernel name."""
+    if "<" not in name:
+        return name, []
+    base, args = name.split("<", 1)
+    vals = []
+    for t in args.rstrip(">").split(","):
+        t = t.strip()
+        vals.append(t == "true" if t in ("true", "false") else int(t))
+    return base, vals
+
+
+def kernel_work(name, problems, steps):
+    """(bound, algorithmic work over `steps` steps, unit of work) of a kernel:
+    FP64 flops for the builds and the multi-step kernels, HBM bytes for the
+    one-step apply, LDS bytes for the resident kernel; None if unknown."""
+    base, v = _parse_kernel(name)
+
+    def group(pred):
+        return [p for p in problems if pred(p)]
+
+    def nl_id(p):
+        return NONLIN_ID[p.get("nonlin", "none")] if p["scheme"] != "linear" else 0
+
+    frozen = lambda p: p.get("nonlin") == "burgers_frozen"
+    if base == "taylor_stepk_kernel":
+        g = group(lambda p: frozen(p) and p["n"] == v[0])
+        return "alu", taylor_flops(v[0], True) * sum(p["N"] for p in g) * steps, "flop"
+    if base == "build_taylor_kernel":
+        g = group(lambda p: frozen(p) and p["n"] == v[0])
+        return "alu", taylor_flops(v[0], v[1]) * sum(p["N"] for p in g) * steps, "flop"
+    if base in ("stepk_kernel", "stepk_rk4_kernel"):
+        if base == "stepk_kernel":
+            g = group(lambda p: p["n"] == v[0] and SCHEME_ID[p["scheme"]] == v[1] and nl_id(p) == v[2]
+                      and not frozen(p) and p.get("x") is None)
+        else:
+            g = group(lambda p: p["n"] == v[0] and p["scheme"] == "etdrk4")
+        return "alu", sum(stationary_flops(p) * p["N"] for p in g) * steps, "flop"
+    if base == "apply_kernel":
+        g = group(lambda p: p["n"] == v[0] and SCHEME_ID[p["scheme"]] == v[1] and nl_id(p) == v[2])
+        per = 0.0
+        for p in g:
+            if p.get("x") is not None:
+                per += p["N"] * (16.0 + 8.0 * KINDS[p["scheme"]] * p["n"])
+            elif frozen(p):
+                per += p["N"] * (16.0 + 16.0 * p["n"])
+            else:
+                per += p["N"] * 16.0
+        return "hbm", per * steps, "byte"
+    if base == "resident_kernel":
+        g = group(lambda p: p["n"] == v[0] and p.get("x") is not None)
+
+        def lds_reads(p):
+            has_n = p["scheme"] != "linear" and p.get("nonlin", "none") != "none"
+            return p["n"] * (1 + (2 if has_n and p["scheme"] == "etd2rk" else 0))
+        return "lds", sum(p["N"] * 8.0 * lds_reads(p) for p in g) * steps, "byte"
+    return None
+
+
+def kernel_rooflines(batch, w, u, steps, flags, problems, workload):
+    """A profiled pass over the same `steps` steps (HIP events around every
+    launch, per kernel): per kernel its average launch time and algorithmic
+    rate against its roofline; the dominant kernel (largest total time)
+    first."""
+    import paper_2603_15964_amd as lmep
+    out = batch.empty_state()
+    batch.step(w, u, steps, lmep.LMEP_F_PROFILE | (flags & lmep.LMEP_F_PERSISTENT), u_out=out)
+    rows = []
+    for name, ms, launches in sorted(lmep.lmep_profile_kernels(), key=lambda t: -t[1]):
+        row = {"kernel": name, "launches": launches, "avg_launch_us": ms * 1e3 / max(1, launches),
+               "total_ms": ms}
+        wk = kernel_work(name, problems, steps)
+        if wk is not None and ms > 0:
+            bound, work, unit = wk
+            rate = work / (ms / 1e3)
+            if bound == "alu":
+                row.update(bound="alu", achieved=rate / 1e12, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                           frac=rate / 1e12 / PEAK_FP64_TFLOPS, flops_per_launch=work / launches)
+            else:
+                peak = PEAK_HBM_GBS if bound == "hbm" else PEAK_LDS_GBS
+                row.update(bound=bound, achieved=rate / 1e9, peak=peak, unit="GB/s", frac=rate / 1e9 / peak,
+                           bytes_per_launch=work / launches)
+        rows.append(row)
+    dom = dict(rows[0]) if rows else {}
+    if dom:
+        dom["traffic"] = measured_traffic([dom["kernel"]], workload)
+        dom["duration_from"] = ("HIP events recorded around each launch of this kernel on the library's stream, "
+                                "profiled pass over the timed steps")
+    return dom, rows
+
+
+def forward_line(problems, states, steps, warmup, flags, kb=None):
+    """Times `steps` steps of the batch after `warmup` untimed ones.  Returns
+    (result dict, batch, weights, state the timed steps started from)."""
+    import torch
+    import paper_2603_15964_amd as lmep
+    if kb is not None:
+        lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
+    batch = lmep.Batch(problems, device="cuda:0")
+    w = batch.empty_weights()
+    u0 = batch.pack(states)
+    ua, ub = batch.empty_state(), batch.empty_state()
+    if not all(p.get("nonlin") == "burgers_frozen" for p in problems):
+        batch.build_weights(w, u0)
+    if warmup > 0:
+        batch.step(w, u0, warmup, flags, u_out=ua)
+    else:
+        ua.copy_(u0)
+    # plans (and, with LMEP_F_GRAPH, the graph) of the timed call's shape
+    batch.step(w, ua, steps if flags & lmep.LMEP_F_GRAPH else min(steps, 2 * (kb or 1)), flags, u_out=ub)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    batch.step(w, ua, steps, flags, u_out=ub)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    node_steps = batch.state_size * steps
+    res = {"value": node_steps / wall, "unit": "node-steps/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": wall * 1e3 / steps, "gpu_event_ms": start.elapsed_time(stop), "wall_ms": wall * 1e3,
+           "instances": batch.count, "nodes": batch.state_size}
+    return res, batch, w, ua
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=200,
-                    help="untimed steps first (brings the clocks up; the timed region of the default run is short)")
-    ap.add_argument("--workload", default="burgers")
-    ap.add_argument("--graph", action="store_true", help="replay the step loop from a hipGraph")
+    ap.add_argument("--steps", type=int, default=500, help="timed steps of the headline workload")
+    ap.add_argument("--warmup", type=int, default=40, help="untimed steps first (brings the clocks up)")
+    ap.add_argument("--workload", default="allen_cahn_batch")
+    ap.add_argument("--graph", action="store_true", help="replay the step loop from a hipGraph (cached by the plan)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true",
-                    help="skip the plain single-instance comparison runs (and the Pade comparison run)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain single-instance comparison runs")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-instance Burgers workload")
+    ap.add_argument("--adjoint-steps", type=int, default=500)
+    ap.add_argument("--adjoint-every", type=int, default=50, help="checkpoint interval of the adjoint run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (calibrates byte counters)")
-    ap.add_argument("--persistent", action="store_true",
-                    help="advance several steps per launch (LMEP_F_PERSISTENT)")
     ap.add_argument("--launch", choices=("auto", "one-step", "persistent"), default="auto",
-                    help="auto: several steps per launch for frozen-velocity workloads the multi-step kernel covers "
-                         "whose batch is under 2^20 nodes (too small to fill the GPU in one step), one step "
-                         "otherwise; --persistent is the same as --launch persistent")
-    ap.add_argument("--steps-per-launch", type=int, default=None, choices=(1, 2, 4, 8),
-                    help="steps per launch of the multi-step path (default 8; for --launch auto on frozen "
-                         "velocity the deepest whose largest region (512 positions) keeps 128 written nodes)")
+                    help="auto: several steps per launch wherever the multi-step kernels cover the workload; "
+                         "--persistent is the same as --launch persistent")
+    ap.add_argument("--persistent", action="store_true", help="advance several steps per launch")
+    ap.add_argument("--steps-per-launch", type=int, default=None, choices=(1, 2, 4, 8))
     ap.add_argument("--tune", action="store_true",
-                    help="let the autotuner pick fusion / steps per launch / apply tile (cached per GPU and shape)")
+                    help="let the autotuner pick the launch configuration (cached per GPU and shape)")
     ap.add_argument("--exp-method", choices=("auto", "pade"), default="auto",
                     help="exponential of the frozen-velocity rebuild: finite Taylor series where it applies (auto) "
                          "or Pade scaling-and-squaring everywhere")
-    ap.add_argument("--skip-count", action="store_true",
-                    help="skip the squaring-count pass (its atomics would show up in a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -372,223 +582,136 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 8, "copies": 3}), flush=True)
         return
 
-    problems, states, desc = make_workload(args.workload)
-    dev = "cuda:0"
-    if args.launch == "persistent":
-        args.persistent = True
-    elif args.launch == "auto" and not args.persistent and not args.tune:
-        frozen_all = all(p.get("nonlin") == "burgers_frozen" for p in problems)
-        covered = all(p["bc"] != "neumann" and p.get("react", 0.0) == 0.0 for p in problems)
-        small = sum(int(p["N"]) for p in problems) < (1 << 20)
-        args.persistent = frozen_all and covered and small and args.exp_method == "auto"
-        if args.persistent and args.steps_per_launch is None:
-            # deepest launch whose largest region (512 positions; the library sizes
-            # regions per CU up to that) still writes 128 nodes per block (the halo
-            # grows by n - 1 per step, 2 (n - 1) for one-sided windows)
-            reach = max((2 if p.get("window", "centred") == "upwind" else 1) * (int(p["n"]) - 1) for p in problems)
-            args.steps_per_launch = next((kb for kb in (8, 4, 2) if 512 - 2 * kb * reach >= 128), 1)
-    if args.steps_per_launch is None:
-        args.steps_per_launch = 8
     lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD,
                          lmep.LMEP_EXP_PADE if args.exp_method == "pade" else lmep.LMEP_EXP_AUTO)
     if args.workload == "burgers_adjoint":
-        wu = max(1, min(args.warmup, 10))  # a short warm-up: its checkpoint segment holds every state
-        bench_adjoint(problems, states, wu, every=wu)
-        secs, node_steps, every = bench_adjoint(problems, states, args.steps)
-        out = {"metric": "node-steps/s (weight build+apply, FP64), adjoint: forward + checkpointed reverse",
-               "value": node_steps / secs, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
-               "warmup": args.warmup, "ms_per_step": secs * 1e3 / args.steps, "higher_is_better": True,
-               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-               "config": {"workload": desc, "instances": len(problems), "nodes": sum(p["N"] for p in problems),
-                          "checkpoint_every": every},
-               "roofline": adjoint_roofline(problems, states)}
-        if not args.no_plain:
-            pv, pk = plain_forward(problems, states, min(args.steps, 50))
-            out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,
-                            "kind": "single-instance forward only, instances one at a time, per-step eager launches",
-                            "ratio": out["value"] / pv}
-        print(json.dumps(out), flush=True)
-        return
-    batch = lmep.Batch(problems, device=dev)
-    w = batch.empty_weights()
-    u0 = batch.pack(states)
-    ua, ub = batch.empty_state(), batch.empty_state()
-    frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
-    if not all(p.get("nonlin") == "burgers_frozen" for p in problems):
-        batch.build_weights(w, u0)
-    flags = lmep.LMEP_F_GRAPH if args.graph else 0
-    kb = 1
+        args.no_adjoint = False
+    problems, states, desc = make_workload(args.workload)
+    flags, kb = launch_choice(problems, args)
+    if args.graph:
+        flags |= lmep.LMEP_F_GRAPH
     tuned = None
     if args.tune:
         from paper_2603_15964_amd import tune as lt
-        tuned = lt.tune(batch, w, u0, steps=max(4, min(args.steps, 50)))
-        opts = dict(tuned.choice.options)
-        for o, v in opts.items():
+        b0 = lmep.Batch(problems, device="cuda:0")
+        w0 = b0.empty_weights()
+        u00 = b0.pack(states)
+        if not all(p.get("nonlin") == "burgers_frozen" for p in problems):
+            b0.build_weights(w0, u00)
+        tuned = lt.tune(b0, w0, u00, steps=max(4, min(args.steps, 50)))
+        for o, v in tuned.choice.options.items():
             lmep.lmep_set_option(o, v)
-        flags |= tuned.choice.flags
-        args.persistent = bool(tuned.choice.flags & lmep.LMEP_F_PERSISTENT)
-        if args.persistent:
-            kb = opts[lmep.LMEP_OPT_STEPS_PER_LAUNCH]
-    elif args.persistent:
-        flags |= lmep.LMEP_F_PERSISTENT
-        kb = args.steps_per_launch
-        lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
+        flags = (flags & lmep.LMEP_F_GRAPH) | tuned.choice.flags
+        kb = tuned.choice.options.get(lmep.LMEP_OPT_STEPS_PER_LAUNCH, 1) if flags & lmep.LMEP_F_PERSISTENT else 1
 
-    if args.warmup > 0:
-        batch.step(w, u0, args.warmup, flags, u_out=ua)
+    out = {"metric": "node-steps/s (weight build+apply, FP64) batched/adjoint vs plain @1e-10 err"}
+    if args.workload == "burgers_adjoint":
+        res = adjoint_line(problems, states, args)
+        out.update(value=res.pop("value"), unit="node-steps/s", n_gpus=1, steps=args.adjoint_steps,
+                   warmup=0, ms_per_step=res.pop("ms_per_step"), higher_is_better=True, scaling="weak",
+                   vs_baseline=None, dtype="f64", data="synthetic",
+                   config={"workload": desc, **res.pop("config")}, roofline=res.pop("roofline"))
+        out.update(res)
     else:
-        ua.copy_(u0)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record()
-    batch.step(w, ua, args.steps, flags, u_out=ub)
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = start.elapsed_time(stop)
-    node_steps = batch.state_size * args.steps
-    value = node_steps / wall
-
-    # profiled pass: HIP events around every build / apply launch, same K steps
-    # from the same state; then an untimed pass over the same steps that counts
-    # the squarings each local exponential took (for the algorithmic flops)
-    batch.step(w, ua, args.steps, lmep.LMEP_F_PROFILE | (flags & lmep.LMEP_F_PERSISTENT), u_out=ub)
-    if frozen and not args.skip_count:
-        batch.step(w, ua, args.steps, lmep.LMEP_F_COUNT, u_out=ub)
-    prof = lmep.lmep_profile_last()
-    roof = None
-    extra = {"gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3}
-    apply_bytes = {"burgers": 128.0, "burgers_upwind": 128.0, "kdv": 16.0, "allen_cahn_batch": 16.0, "advection_diffusion": 16.0}
-    taylor = frozen and args.exp_method == "auto" and all(p.get("react", 0.0) == 0.0 for p in problems)
-    if frozen and prof["build_launches"] > 0 and prof["matrices"] > 0:
-        p0 = problems[0]
-        m = p0["n"] + {"linear": 0, "etd1": 1, "etd2rk": 2}[p0["scheme"]]
-        fused = lmep.lmep_get_option(lmep.LMEP_OPT_FUSE_FROZEN) == 1
-        if taylor and args.persistent:
-            # node-steps of the launches (the halo each block recomputes is not counted)
-            flops = taylor_flops(p0["n"], True) * prof["matrices"]
-            kname = f"taylor_stepk_kernel<{p0['n']}>"
-        elif taylor:
-            flops = taylor_flops(p0["n"], fused) * prof["matrices"]
-            kname = f"build_taylor_kernel<{p0['n']},{'true' if fused else 'false'}>"
-        else:
-            flops = pade_flops(m, prof["matrices"], prof["squarings"])
-            kname = f"build_pade_kernel<{p0['n']},{m - p0['n']},{'true' if fused else 'false'}>"
-        # When every launch of the timed region is this kernel (fused steps, one
-        # stencil size, no separate apply launches), its average duration is the
-        # timed region's GPU event time over its launches (back-to-back gaps
-        # included); otherwise the profiled pass's events around each launch,
-        # which add their own overhead to every launch.
-        only = prof["apply_launches"] == 0 and len({p["n"] for p in problems}) == 1
-        build_s = gpu_ms / 1e3 if only else prof["build_ms"] / 1e3
-        achieved = flops / build_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic([kname], args.workload),
-                "kernel": kname,
-                "avg_launch_us": build_s * 1e6 / prof["build_launches"],
-                "duration_from": "timed region events" if only else "events around each launch",
-                "avg_launch_us_events_each": prof["build_ms"] * 1e3 / prof["build_launches"],
-                "flops_per_launch": flops / prof["build_launches"],
-                "mean_squarings": prof["squarings"] / max(1, prof["matrices"])}
-    nonuniform = any(p.get("x") is not None for p in problems)
-    if prof["apply_launches"] > 0:
-        apply_s = prof["apply_ms"] / 1e3
-        avg_us = prof["apply_ms"] * 1e3 / prof["apply_launches"]
-        # algorithmic HBM bytes: per node and launch, u in + u out (16 B), plus
-        # the per-node weights of the frozen-velocity path (read every step) or
-        # of a non-uniform grid (read once per launch)
-        if nonuniform:
-            per_node = sum(p["N"] * (16.0 + 8.0 * KINDS[p["scheme"]] * p["n"]) for p in problems) / batch.state_size
-            if args.persistent:  # whole instances per block: every step of the call in one launch
-                kb = args.steps
-            ab = per_node * node_steps / kb
-        else:
-            ab = apply_bytes.get(args.workload, 16.0) * node_steps / kb
-        gbs = ab / apply_s / 1e9
-        extra["apply"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                          "frac": gbs / PEAK_HBM_GBS, "avg_launch_us": avg_us, "steps_per_launch": kb,
-                          "bytes_per_launch": ab / prof["apply_launches"]}
-        if not frozen:
-            fl = sum(stationary_flops(p) * p["N"] for p in problems) * args.steps
-            tf = fl / apply_s / 1e12
-            extra["apply_alu"] = {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": tf / PEAK_FP64_TFLOPS, "flops_per_launch": fl / prof["apply_launches"]}
-        if roof is None:
-            # one step per launch: HBM-bound; several: the traffic is paid once
-            # per launch and the FP64 work of the steps bounds the kernel
-            def kname(p):
-                nl = NONLIN_ID[p.get("nonlin", "none")] if p["scheme"] != "linear" else 0
-                if p.get("x") is not None:
-                    return f"resident_kernel<{p['n']},{SCHEME_ID[p['scheme']]},{nl}>"
-                if p["scheme"] == "etdrk4":
-                    return f"stepk_rk4_kernel<{p['n']},{nl},{kb}>"
-                return f"stepk_kernel<{p['n']},{SCHEME_ID[p['scheme']]},{nl},{kb}>"
-            if kb > 1 or any(p["scheme"] == "etdrk4" for p in problems) or (nonuniform and args.persistent):
-                names = sorted({kname(p) for p in problems})
-            elif nonuniform and all(p["N"] <= 64 for p in problems):
-                names = sorted({f"apply_kernel<{p['n']},{SCHEME_ID[p['scheme']]},"
-                                f"{NONLIN_ID[p.get('nonlin', 'none')] if p['scheme'] != 'linear' else 0},true,64>"
-                                for p in problems})
-            else:
-                names = ["apply_kernel"]
-            if nonuniform and args.persistent:
-                # one block holds an instance: per node-step the kernel reads its
-                # window of u from LDS (N is formed from it), and for ETD2RK with
-                # a nonlinearity the windows of N(a) and N(u) as well
-                def lds_reads(p):
-                    has_n = p["scheme"] != "linear" and p.get("nonlin", "none") != "none"
-                    return p["n"] * (1 + (2 if has_n and p["scheme"] == "etd2rk" else 0))
-                lb = sum(p["N"] * 8.0 * lds_reads(p) for p in problems) * args.steps
-                gbs_lds = lb / apply_s / 1e9
-                extra["lds"] = {"bound": "lds", "achieved": gbs_lds, "peak": PEAK_LDS_GBS, "unit": "GB/s",
-                                "frac": gbs_lds / PEAK_LDS_GBS, "bytes_per_launch": lb / prof["apply_launches"]}
-            roof = dict(extra["lds"] if (nonuniform and args.persistent) else
-                        (extra["apply_alu"] if kb > 1 else extra["apply"]),
-                        traffic=measured_traffic(names, args.workload) if (kb > 1 or nonuniform) else None,
-                        kernel=" + ".join(names), avg_launch_us=avg_us)
-    out = {
-        "metric": "node-steps/s (weight build+apply, FP64)",
-        "value": value,
-        "unit": "node-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": desc, "instances": batch.count, "nodes": batch.state_size,
-                   "graph": bool(args.graph), "steps_per_launch": kb,
-                   "exponential": ("finite Taylor" if taylor else "Pade") if frozen else "Pade (weights built once)",
-                   "tuned": (dict(tuned.choice.describe(), from_cache=tuned.from_cache) if tuned else None)},
-        "roofline": roof,
-        "detail": extra,
-    }
-    if taylor and not args.no_plain:
-        # the same steps through the Pade build, for comparison
-        lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_PADE)
-        pflags = flags & ~lmep.LMEP_F_PERSISTENT  # the Pade build runs one step per launch
-        batch.step(w, ua, 2, pflags, u_out=ub)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        batch.step(w, ua, args.steps, pflags, u_out=ub)
-        torch.cuda.synchronize()
-        pw = time.perf_counter() - t1
-        lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_AUTO)
-        out["pade_path"] = {"value": node_steps / pw, "unit": "node-steps/s",
-                            "kind": "same steps, frozen-velocity weights by Pade scaling-and-squaring",
-                            "ratio": value / (node_steps / pw)}
-    if len(problems) > 1 and not args.no_plain:
-        pv, pk = plain_forward(problems, states, min(args.steps, 20))
-        out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk,
-                        "kind": "single-instance forward, instances one at a time, per-step eager launches",
-                        "ratio": value / pv}
+        res, batch, w, ua = forward_line(problems, states, args.steps, args.warmup, flags, kb)
+        roof, rows = kernel_rooflines(batch, w, ua, args.steps, flags, problems, args.workload)
+        frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
+        out.update(value=res["value"], unit="node-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                   ms_per_step=res["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+                   dtype="f64", data="synthetic",
+                   config={"workload": desc, "path": "batched" if len(problems) > 1 else "single instance",
+                           "instances": res["instances"], "nodes": res["nodes"],
+                           "steps_per_launch": kb, "graph": bool(flags & lmep.LMEP_F_GRAPH),
+                           "exponential": ("finite Taylor" if args.exp_method == "auto" else "Pade") if frozen
+                           else "Pade (weights built once)",
+                           "tuned": (dict(tuned.choice.describe(), from_cache=tuned.from_cache) if tuned else None)},
+                   roofline=roof, kernels=rows,
+                   detail={"gpu_event_ms": res["gpu_event_ms"], "wall_ms": res["wall_ms"]})
+        if len(problems) > 1 and not args.no_plain:
+            pv, pk = plain_forward(problems, states, min(args.steps, 20))
+            out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk, "steps": min(args.steps, 20),
+                            "kind": "single-instance forward: instances one at a time, one lmep_step call each, "
+                                    "one step per launch",
+                            "ratio": res["value"] / pv}
+        if args.workload == "allen_cahn_batch":
+            lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, 8)
+            if not args.no_adjoint:
+                ap_, as_, _ = make_workload("burgers_adjoint")
+                out["adjoint"] = adjoint_line(ap_, as_, args)
+            if not args.no_single:
+                sp, ss, sdesc = make_workload("burgers")
+                sflags, skb = launch_choice(sp, argparse.Namespace(launch="auto", persistent=False,
+                                                                   steps_per_launch=None, exp_method="auto"))
+                sres, sb, sw, su = forward_line(sp, ss, 1000, 100, sflags, skb)
+                sroof, _ = kernel_rooflines(sb, sw, su, 1000, sflags, sp, "burgers")
+                out["single_instance"] = {"workload": sdesc, "value": sres["value"], "unit": "node-steps/s",
+                                          "steps": 1000, "warmup": 100, "ms_per_step": sres["ms_per_step"],
+                                          "steps_per_launch": skb, "roofline": sroof}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(problems[0], states[0])
+        out["cpu_baseline"] = cpu_baseline(problems, states)
     print(json.dumps(out), flush=True)
+
+
+def launch_choice(problems, args):
+    """(flags, steps per launch): several steps per launch wherever the
+    multi-step kernels cover every instance (stationary centred windows;
+    frozen velocity by the finite-Taylor kernel on Dirichlet or periodic grids
+    under 2^20 nodes -- larger batches fill the GPU in one step), else one."""
+    import paper_2603_15964_amd as lmep
+    if args.launch == "one-step" and not args.persistent:
+        return 0, 1
+    frozen = [p.get("nonlin") == "burgers_frozen" for p in problems]
+    if all(frozen):
+        covered = all(p["bc"] != "neumann" and p.get("react", 0.0) == 0.0 for p in problems) and \
+            args.exp_method == "auto"
+        small = sum(int(p["N"]) for p in problems) < (1 << 20)
+        multi = covered and (small or args.persistent or args.launch == "persistent")
+        if not multi:
+            return 0, 1
+        kb = args.steps_per_launch
+        if kb is None:
+            # deepest launch whose largest region (512 positions) still writes
+            # 128 nodes per block (the halo grows by n - 1 per step, 2 (n - 1)
+            # for one-sided windows)
+            reach = max((2 if p.get("window", "centred") == "upwind" else 1) * (int(p["n"]) - 1) for p in problems)
+            kb = next((k for k in (8, 4, 2) if 512 - 2 * k * reach >= 128), 1)
+        return lmep.LMEP_F_PERSISTENT, kb
+    if any(frozen):
+        return 0, 1
+    centred = all(p.get("window", "centred") == "centred" for p in problems)
+    nonuniform_small = all(p.get("x") is None or p["N"] <= 512 for p in problems)
+    if centred and nonuniform_small:
+        return lmep.LMEP_F_PERSISTENT, (args.steps_per_launch or 8)
+    return 0, 1
+
+
+def adjoint_line(problems, states, args):
+    """The adjoint workload: forward + checkpointed reverse, against the plain
+    single-instance forward of the same trajectories."""
+    import torch
+    import paper_2603_15964_amd as lmep
+    import workloads
+    _, pt, _ = workloads.burgers_adjoint_batch()
+    tprobs = [dict(pt)] * len(problems)
+    steps, every = args.adjoint_steps, args.adjoint_every
+    target = adjoint_target(problems, tprobs, states, steps)
+    bench_adjoint(problems, states, min(steps, 10), min(steps, 10), target=None)  # warm-up: plans, code objects
+    secs = bench_adjoint(problems, states, steps, every, target=target)
+    nodes = sum(int(p["N"]) for p in problems)
+    res = {"workload": "64 Burgers trajectories N=262144 n=9, ETD1 frozen velocity, forward + checkpointed reverse, "
+                       "loss against the state reached with nu*1.1",
+           "value": 2.0 * nodes * steps / secs, "unit": "node-steps/s",
+           "node_steps": "forward and reverse steps, sum N x steps each (recomputation not counted)",
+           "steps": steps, "ms_per_step": secs * 1e3 / steps, "wall_s": secs,
+           "config": {"instances": len(problems), "nodes": nodes, "checkpoint_every": every},
+           "roofline": adjoint_roofline(problems, states)}
+    if not args.no_plain:
+        pv, pk = plain_forward(problems, states, min(steps, 20))
+        res["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk, "steps": min(steps, 20),
+                        "kind": "single-instance forward only: trajectories one at a time, one step per launch"}
+        res["ratio"] = res["value"] / pv
+    torch.cuda.synchronize()
+    return res
 
 
 if __name__ == "__main__":

@@ -18,9 +18,10 @@
  *
  * Conventions for every entry point:
  *  - Pointers named d_* are device memory owned by the caller; prob is host
- *    memory.  Nothing is retained after return, except inside a graph that a
- *    call captured itself (LMEP_F_GRAPH), which is replayed and destroyed
- *    within that same call.
+ *    memory.  The plain entry points retain nothing after return (a graph
+ *    that lmep_step captures for LMEP_F_GRAPH is replayed and destroyed
+ *    within the call); a plan (lmep_plan_create) keeps its scratch buffer and
+ *    the pointers of the graphs it captured until lmep_plan_destroy.
  *  - All argument checks run before any device work; on failure the call
  *    returns a negative lmep_status, writes nothing and lmep_last_error()
  *    describes the problem.
@@ -206,6 +207,44 @@ int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double
 int lmep_step_noalloc(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in,
                       double* d_u_out, int32_t n_steps, uint32_t flags, void* hip_stream);
 
+/* Plans: the grouping, option values and device tables of one batch, made
+ * once and reused by many calls, so that a call enqueues kernels only (no
+ * host-to-device copy, no host synchronisation) and a step loop captured with
+ * LMEP_F_GRAPH is replayed on later calls instead of being captured again.
+ *
+ * lmep_plan_create checks the batch as the entry point of `op` does (op 1:
+ * lmep_step, op 2: lmep_adjoint_step), copies what it needs from prob (prob
+ * may be freed afterwards), and uploads the device tables into d_scratch
+ * (lmep_scratch_bytes(prob, count, op) bytes, 256-byte aligned) on
+ * hip_stream.  The scratch buffer belongs to the plan until lmep_plan_destroy:
+ * the caller keeps it allocated and does not write it.
+ *  - flags: for op 1, LMEP_F_PERSISTENT or 0 (fixed for the plan); for op 2, 0.
+ *  - options: n_options pairs (option, value) of the LMEP_OPT_* below that
+ *    override, for this plan only, the process-wide values, which the plan
+ *    copies at creation; later lmep_set_option calls do not change it.  NULL
+ *    with n_options = 0 takes the process-wide values.
+ *  - The plan records an event after its upload; calls on another stream wait
+ *    for it on the device.
+ * lmep_plan_step and lmep_plan_adjoint_step take the pointers of one call and
+ * follow lmep_step and lmep_adjoint_step (same checks, results bit for bit).
+ * lmep_plan_step's flags must contain LMEP_F_PERSISTENT exactly when the plan
+ * was made with it; with LMEP_F_GRAPH the plan captures the step loop the
+ * first time a (d_w, d_u_in, d_u_out, n_steps) combination is seen and replays
+ * that graph afterwards (the last four combinations are kept), so the graph
+ * keeps those pointers: they must stay valid while the plan lives.
+ * A plan is not thread-safe: calls on one plan must not overlap in time.
+ * lmep_plan_destroy waits for the plan's last graph launch and frees the
+ * plan's host memory and graphs (not the scratch buffer); NULL is ignored. */
+typedef struct lmep_plan_s* lmep_plan;
+int lmep_plan_create(lmep_plan* plan, const lmep_problem* prob, int32_t count, int32_t op, uint32_t flags,
+                     const int32_t* options, int32_t n_options, void* d_scratch, size_t scratch_bytes,
+                     void* hip_stream);
+int lmep_plan_step(lmep_plan plan, double* d_w, const double* d_u_in, double* d_u_out, int32_t n_steps,
+                   uint32_t flags, void* hip_stream);
+int lmep_plan_adjoint_step(lmep_plan plan, const double* d_u_k, const double* d_lambda_next, double* d_lambda_k,
+                           double* d_grad, void* hip_stream);
+int lmep_plan_destroy(lmep_plan plan);
+
 /* Reverse of one LINEAR or ETD1 step (not ETD2RK / ETDRK4 / KDV).  Given the forward
  * state d_u_k = u^k and d_lambda_next = d loss / d u^{k+1}, write
  * d_lambda_k = d loss / d u^k and add this step's parameter derivatives to
@@ -231,6 +270,16 @@ int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u
  * squarings).  Any pointer may be NULL. */
 int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_ms,
                       int32_t* apply_launches, int64_t* matrices, int64_t* squarings);
+
+/* Per kernel of the last call on this thread that timed its kernels
+ * (LMEP_F_PROFILE, or a reverse step under LMEP_OPT_PROFILE_ADJOINT): returns
+ * the number K of distinct kernels it launched and, for 0 <= k < K, writes the
+ * kernel's name as a kernel trace shows it without namespace and argument
+ * list (e.g. "stepk_kernel<11,1,3,8>", truncated to name_len - 1
+ * characters), its time summed over its launches in milliseconds (HIP events
+ * recorded around each launch on the call's stream) and its number of
+ * launches.  For k outside [0, K) it writes nothing.  Any pointer may be NULL. */
+int32_t lmep_profile_kernel(int32_t k, char* name, size_t name_len, double* ms, int32_t* launches);
 
 /* Thread-local description of the last non-OK status. */
 const char* lmep_last_error(void);

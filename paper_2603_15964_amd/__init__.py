@@ -9,8 +9,11 @@ arguments through the C ABI of ``include/lmep.h``.  PyTorch provides device
 memory and streams.
 
 ``Batch`` packs a list of problem dicts (keys as in ``workloads``) into flat
-device buffers and calls the three entry points ``lmep_build_weights``,
-``lmep_step`` and ``lmep_adjoint_step``.
+device buffers and calls the entry points: ``lmep_build_weights``, and
+``lmep_step`` / ``lmep_adjoint_step`` through plans (``lmep_plan_*``) that it
+keeps per operation and option values, each with its own scratch buffer, so
+repeated calls enqueue kernels only; ``use_plans=False`` calls the plain entry
+points instead.
 """
 from __future__ import annotations
 
@@ -27,7 +30,11 @@ from ._native import (  # noqa: F401  (re-exported names of the C ABI)
     LMEP_OPT_EXP_METHOD, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_PROFILE_ADJOINT, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_WIN_CENTRED,
     LMEP_WIN_UPWIND, OP_ADJOINT, OP_BUILD, OP_STEP, LmepError, library, lmep_adjoint_step, lmep_build_weights,
     lmep_get_option, lmep_last_error, lmep_problem, lmep_profile_last, lmep_scratch_bytes, lmep_set_option, lmep_step,
-    lmep_step_noalloc, lmep_weight_count, problem_array, to_struct, LMEP_NOALLOC_SCRATCH_BYTES)
+    lmep_step_noalloc, lmep_weight_count, problem_array, to_struct, LMEP_NOALLOC_SCRATCH_BYTES, lmep_plan_create,
+    lmep_plan_step, lmep_plan_adjoint_step, lmep_plan_destroy, lmep_profile_kernels, option_generation)
+
+_OPTIONS = (LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_PROFILE_ADJOINT, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_APPLY_TILE,
+            LMEP_OPT_EXP_METHOD)
 
 _KINDS = {"linear": 1, "etd1": 2, "etd2rk": 3, "etdrk4": 6}
 
@@ -44,7 +51,9 @@ class Batch:
     (layouts in include/lmep.h).
     """
 
-    def __init__(self, problems, device="cuda:0"):
+    def __init__(self, problems, device="cuda:0", use_plans: bool = True):
+        self.use_plans = use_plans
+        self._plans = {}
         self.problems = [dict(p) for p in problems]
         self.device = torch.device(device)
         self.count = len(self.problems)
@@ -74,6 +83,37 @@ class Batch:
         self.state_size = so
         self.weight_size = wo
         self._scratch = {}
+
+    def __del__(self):
+        self.release_plans()
+
+    def release_plans(self):
+        """Destroy the cached plans (their scratch tensors go with them)."""
+        plans, self._plans = getattr(self, "_plans", {}), {}
+        for handle, _ in plans.values():
+            try:
+                lmep_plan_destroy(handle)
+            except Exception:  # noqa: BLE001 -- interpreter shutdown
+                pass
+
+    def plan(self, op: int, flags: int = 0) -> int:
+        """The cached plan of op (OP_STEP or OP_ADJOINT) for the current
+        process-wide option values; LMEP_F_PERSISTENT in flags selects the
+        multi-step step plan."""
+        persistent = int(flags) & LMEP_F_PERSISTENT if op == OP_STEP else 0
+        gen = option_generation()
+        if getattr(self, "_opts_gen", None) != gen:
+            self._opts = tuple(lmep_get_option(o) for o in _OPTIONS)
+            self._opts_gen = gen
+        key = (op, persistent, self._opts)
+        if key not in self._plans:
+            nbytes = lmep_scratch_bytes(self.structs, self.count, op)
+            t = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            assert t.data_ptr() % 256 == 0
+            h = lmep_plan_create(self.structs, self.count, op, persistent, None, t.data_ptr(), nbytes,
+                                 _stream_handle(self.device))
+            self._plans[key] = (h, t)
+        return self._plans[key][0]
 
     # ------------------------------------------------------------ buffers --
     def scratch(self, op: int):
@@ -123,6 +163,10 @@ class Batch:
              u_out: torch.Tensor = None) -> torch.Tensor:
         if u_out is None:
             u_out = self.empty_state()
+        if self.use_plans:
+            lmep_plan_step(self.plan(OP_STEP, flags), w.data_ptr(), u_in.data_ptr(), u_out.data_ptr(), int(n_steps),
+                           int(flags), _stream_handle(self.device))
+            return u_out
         sp, sb = self.scratch(OP_STEP)
         lmep_step(self.structs, self.count, w.data_ptr(), u_in.data_ptr(), u_out.data_ptr(), int(n_steps),
                   int(flags), sp, sb, _stream_handle(self.device))
@@ -134,6 +178,10 @@ class Batch:
             lam_k = self.empty_state()
         if grad is None:
             grad = torch.zeros(3 * self.count, dtype=torch.float64, device=self.device)
+        if self.use_plans:
+            lmep_plan_adjoint_step(self.plan(OP_ADJOINT), u_k.data_ptr(), lam_next.data_ptr(), lam_k.data_ptr(),
+                                   grad.data_ptr(), _stream_handle(self.device))
+            return lam_k, grad
         sp, sb = self.scratch(OP_ADJOINT)
         lmep_adjoint_step(self.structs, self.count, u_k.data_ptr(), lam_next.data_ptr(), lam_k.data_ptr(),
                           grad.data_ptr(), sp, sb, _stream_handle(self.device))
@@ -141,5 +189,7 @@ class Batch:
 
 
 __all__ = ["Batch", "LmepError", "lmep_problem", "lmep_build_weights", "lmep_step", "lmep_adjoint_step",
+           "lmep_plan_create", "lmep_plan_step", "lmep_plan_adjoint_step", "lmep_plan_destroy",
+           "lmep_profile_kernels",
            "lmep_step_noalloc", "lmep_scratch_bytes", "lmep_weight_count", "lmep_last_error", "lmep_profile_last", "lmep_set_option",
            "lmep_get_option", "library"]

@@ -70,6 +70,14 @@ _lib.lmep_build_weights.argtypes = [_P, ctypes.c_int32, _V, _V, _V, ctypes.c_siz
 _lib.lmep_step.argtypes = [_P, ctypes.c_int32, _V, _V, _V, ctypes.c_int32, ctypes.c_uint32, _V, ctypes.c_size_t, _V]
 _lib.lmep_step_noalloc.argtypes = [_P, ctypes.c_int32, _V, _V, _V, ctypes.c_int32, ctypes.c_uint32, _V]
 _lib.lmep_adjoint_step.argtypes = [_P, ctypes.c_int32, _V, _V, _V, _V, _V, ctypes.c_size_t, _V]
+_lib.lmep_plan_create.argtypes = [ctypes.POINTER(_V), _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, _V, ctypes.c_size_t, _V]
+_lib.lmep_plan_step.argtypes = [_V, _V, _V, _V, ctypes.c_int32, ctypes.c_uint32, _V]
+_lib.lmep_plan_adjoint_step.argtypes = [_V, _V, _V, _V, _V, _V]
+_lib.lmep_plan_destroy.argtypes = [_V]
+_lib.lmep_profile_kernel.argtypes = [ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+_lib.lmep_profile_kernel.restype = ctypes.c_int32
 _lib.lmep_profile_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -79,7 +87,8 @@ _lib.lmep_get_option.argtypes = [ctypes.c_int32]
 _lib.lmep_get_option.restype = ctypes.c_int32
 
 EXPORTED = ("lmep_weight_count", "lmep_scratch_bytes", "lmep_build_weights", "lmep_step", "lmep_step_noalloc",
-            "lmep_adjoint_step", "lmep_profile_last", "lmep_last_error", "lmep_set_option", "lmep_get_option")
+            "lmep_adjoint_step", "lmep_plan_create", "lmep_plan_step", "lmep_plan_adjoint_step", "lmep_plan_destroy",
+            "lmep_profile_last", "lmep_profile_kernel", "lmep_last_error", "lmep_set_option", "lmep_get_option")
 LMEP_NOALLOC_SCRATCH_BYTES = 64 << 20
 LMEP_OPT_STEPS_PER_LAUNCH = 1
 LMEP_OPT_PROFILE_ADJOINT = 2
@@ -161,6 +170,41 @@ def lmep_adjoint_step(probs, count, d_u_k, d_lambda_next, d_lambda_k, d_grad, d_
                                   scratch_bytes, stream))
 
 
+def lmep_plan_create(probs, count, op, flags, options, d_scratch, scratch_bytes, stream) -> int:
+    """options: dict {LMEP_OPT_*: value} overriding the process-wide values for
+    this plan.  Returns the plan handle (an integer)."""
+    pairs = [int(v) for kv in sorted((options or {}).items()) for v in kv]
+    arr = (ctypes.c_int32 * max(1, len(pairs)))(*pairs)
+    h = _V()
+    _check(_lib.lmep_plan_create(ctypes.byref(h), probs, count, op, flags, arr if pairs else None, len(pairs) // 2,
+                                 d_scratch, scratch_bytes, stream))
+    return h.value
+
+
+def lmep_plan_step(plan, d_w, d_u_in, d_u_out, n_steps, flags, stream) -> None:
+    _check(_lib.lmep_plan_step(plan, d_w, d_u_in, d_u_out, n_steps, flags, stream))
+
+
+def lmep_plan_adjoint_step(plan, d_u_k, d_lambda_next, d_lambda_k, d_grad, stream) -> None:
+    _check(_lib.lmep_plan_adjoint_step(plan, d_u_k, d_lambda_next, d_lambda_k, d_grad, stream))
+
+
+def lmep_plan_destroy(plan) -> None:
+    _check(_lib.lmep_plan_destroy(plan))
+
+
+def lmep_profile_kernels() -> list:
+    """[(name, ms, launches)] of every kernel the last timed call launched."""
+    out = []
+    count = _lib.lmep_profile_kernel(-1, None, 0, None, None)
+    for k in range(count):
+        name = ctypes.create_string_buffer(128)
+        ms, n = ctypes.c_double(), ctypes.c_int32()
+        _lib.lmep_profile_kernel(k, name, 128, ctypes.byref(ms), ctypes.byref(n))
+        out.append((name.value.decode(), ms.value, n.value))
+    return out
+
+
 def lmep_profile_last() -> dict:
     b, a = ctypes.c_double(), ctypes.c_double()
     nb, na = ctypes.c_int32(), ctypes.c_int32()
@@ -171,8 +215,18 @@ def lmep_profile_last() -> dict:
                 matrices=m.value, squarings=sq.value)
 
 
+_option_generation = [0]
+
+
 def lmep_set_option(option: int, value: int) -> None:
     _check(_lib.lmep_set_option(int(option), int(value)))
+    _option_generation[0] += 1
+
+
+def option_generation() -> int:
+    """Count of lmep_set_option calls made through this module (lets callers
+    cache the process-wide option values between changes)."""
+    return _option_generation[0]
 
 
 def lmep_get_option(option: int) -> int:

@@ -1,7 +1,10 @@
 // C-ABI of liblmep (declared in include/lmep.h): argument checks, grouping of
 // instances by kernel variant, scratch layout, upload of the device problem
-// tables, and the launch sequence of each entry point.  All arithmetic of the
-// method runs in the kernels; this file only plans and enqueues.
+// tables, and the launch sequence of each entry point.  A plan
+// (lmep_plan_create) keeps the grouping and the uploaded tables of one batch
+// for many calls; the plain entry points make a plan for one call.  All
+// arithmetic of the method runs in the kernels; this file only plans and
+// enqueues.
 #include "lmep.h"
 
 #include <hip/hip_runtime.h>
@@ -14,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -33,11 +37,36 @@ thread_local char t_err[512] = "";
 thread_local double t_prof_build_ms = 0.0, t_prof_apply_ms = 0.0;
 thread_local int32_t t_prof_build_n = 0, t_prof_apply_n = 0;
 thread_local int64_t t_prof_matrices = 0, t_prof_squarings = 0;
-std::atomic<int> t_steps_per_launch{8};  // LMEP_OPT_STEPS_PER_LAUNCH, process-wide
-std::atomic<int> t_profile_adjoint{0};   // LMEP_OPT_PROFILE_ADJOINT, process-wide
-std::atomic<int> t_fuse_frozen{1};       // LMEP_OPT_FUSE_FROZEN, process-wide
-std::atomic<int> t_apply_tile{0};        // LMEP_OPT_APPLY_TILE, process-wide (0 = by size)
-std::atomic<int> t_exp_method{LMEP_EXP_AUTO};  // LMEP_OPT_EXP_METHOD, process-wide
+
+// Kernel times of the last profiled call on this thread, per kernel name.
+struct KernelTime {
+    std::string name;
+    double ms = 0.0;
+    int32_t launches = 0;
+};
+thread_local std::vector<KernelTime> t_prof_kernels;
+
+// Tuning options.  The process-wide values (lmep_set_option) are what a plan
+// takes unless its creation overrides them; a plan keeps its own copy.
+struct Opts {
+    int steps_per_launch = 8;   // LMEP_OPT_STEPS_PER_LAUNCH
+    int profile_adjoint = 0;    // LMEP_OPT_PROFILE_ADJOINT
+    int fuse_frozen = 1;        // LMEP_OPT_FUSE_FROZEN
+    int apply_tile = 0;         // LMEP_OPT_APPLY_TILE (0 = by size)
+    int exp_method = LMEP_EXP_AUTO;  // LMEP_OPT_EXP_METHOD
+};
+std::atomic<int> g_steps_per_launch{8}, g_profile_adjoint{0}, g_fuse_frozen{1}, g_apply_tile{0},
+    g_exp_method{LMEP_EXP_AUTO};
+
+Opts process_opts() {
+    Opts o;
+    o.steps_per_launch = g_steps_per_launch.load();
+    o.profile_adjoint = g_profile_adjoint.load();
+    o.fuse_frozen = g_fuse_frozen.load();
+    o.apply_tile = g_apply_tile.load();
+    o.exp_method = g_exp_method.load();
+    return o;
+}
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -53,6 +82,35 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(LMEP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// Validate one option value and store it in o.
+int set_opt(Opts& o, int32_t option, int32_t value) {
+    switch (option) {
+        case LMEP_OPT_STEPS_PER_LAUNCH:
+            if (value != 1 && value != 2 && value != 4 && value != 8)
+                return fail(LMEP_ERR_ARG, "steps per launch must be 1, 2, 4 or 8, got %d", value);
+            o.steps_per_launch = value;
+            return LMEP_OK;
+        case LMEP_OPT_PROFILE_ADJOINT:
+        case LMEP_OPT_FUSE_FROZEN:
+            if (value != 0 && value != 1) return fail(LMEP_ERR_ARG, "option %d takes 0 or 1, got %d", option, value);
+            (option == LMEP_OPT_PROFILE_ADJOINT ? o.profile_adjoint : o.fuse_frozen) = value;
+            return LMEP_OK;
+        case LMEP_OPT_EXP_METHOD:
+            if (value != LMEP_EXP_AUTO && value != LMEP_EXP_PADE)
+                return fail(LMEP_ERR_ARG, "exponential method must be LMEP_EXP_AUTO (0) or LMEP_EXP_PADE (1), got %d",
+                            value);
+            o.exp_method = value;
+            return LMEP_OK;
+        case LMEP_OPT_APPLY_TILE:
+            if (value != 0 && value != 64 && value != kApplyTileSmall && value != kApplyTile)
+                return fail(LMEP_ERR_ARG, "apply tile must be 0, 64, %d or %d, got %d", kApplyTileSmall, kApplyTile,
+                            value);
+            o.apply_tile = value;
+            return LMEP_OK;
+        default: return fail(LMEP_ERR_ARG, "unknown option %d", option);
+    }
+}
+
 int scheme_p(int scheme) {
     return scheme == LMEP_ETDRK4 ? 3 : (scheme == LMEP_ETD2RK ? 2 : (scheme == LMEP_ETD1 ? 1 : 0));
 }
@@ -63,8 +121,8 @@ bool pernode(const lmep_problem& q) { return frozen(q) || nonuniform(q); }
 // Frozen-velocity instances whose weights the finite-Taylor kernel builds: a
 // polynomial operator in the first-derivative matrix (uniform grid, no
 // reaction term), unless LMEP_OPT_EXP_METHOD asks for Pade.
-bool taylor(const lmep_problem& q) {
-    return frozen(q) && !nonuniform(q) && q.react == 0.0 && t_exp_method.load() == LMEP_EXP_AUTO;
+bool taylor(const lmep_problem& q, const Opts& o) {
+    return frozen(q) && !nonuniform(q) && q.react == 0.0 && o.exp_method == LMEP_EXP_AUTO;
 }
 
 int64_t weight_count(const lmep_problem& q) {
@@ -241,6 +299,7 @@ struct Group {
     bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
+    int64_t nodes = 0;         // nodes of the group's instances
 };
 
 // Compute units of the current device (cached per device; 256 on MI355X).
@@ -261,7 +320,7 @@ int cu_count() {
 // taylor_stepk_tile(n, frozen_kb) nodes instead of kTaylorTile).
 template <class Want>
 std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want, std::vector<DevProb>& tab,
-                              int frozen_kb = 0) {
+                              const Opts& o, int frozen_kb = 0) {
     // one build part per exponential: ETDRK4 needs two (p = 3 at dt, p = 1 at dt/2)
     struct Part {
         int k, harvest;
@@ -270,7 +329,7 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
     std::map<std::tuple<int, int, int>, std::vector<Part>> by;
     for (int k = 0; k < count; ++k) {
         if (!want(prob[k])) continue;
-        const int kind = nonuniform(prob[k]) ? 1 : (taylor(prob[k]) ? 2 : 0);
+        const int kind = nonuniform(prob[k]) ? 1 : (taylor(prob[k], o) ? 2 : 0);
         if (prob[k].scheme == LMEP_ETDRK4) {
             by[{prob[k].n, 3, kind}].push_back({k, HARVEST_RK4_FULL});
             by[{prob[k].n, 1, kind}].push_back({k, HARVEST_RK4_HALF});
@@ -285,19 +344,16 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         g.p = std::get<1>(kv.first);
         g.nonuniform = std::get<2>(kv.first) == 1;
         g.taylor = std::get<2>(kv.first) == 2;
+        for (const Part& part : kv.second) g.nodes += prob[part.k].N;
         if (g.taylor && frozen_kb > 0) {
             // staged positions per block (= threads): about one block per CU for
             // groups too small to fill the GPU -- a step then costs the latency of
             // one block, not of the two or three an uneven spread puts on some
             // CUs -- and the full region for larger ones
-            int64_t nodes = 0;
             bool upwind = false;
-            for (const Part& part : kv.second) {
-                nodes += prob[part.k].N;
-                upwind |= prob[part.k].window == LMEP_WIN_UPWIND;
-            }
+            for (const Part& part : kv.second) upwind |= prob[part.k].window == LMEP_WIN_UPWIND;
             const int64_t halo = (int64_t)frozen_kb * taylor_stepk_reach(g.n, upwind);
-            const int64_t want_tile = std::max<int64_t>((nodes + cu_count() - 1) / cu_count(), 64);
+            const int64_t want_tile = std::max<int64_t>((g.nodes + cu_count() - 1) / cu_count(), 64);
             g.reg = (int)std::min<int64_t>((want_tile + 2 * halo + 63) / 64 * 64, kTaylorRegion);
         }
         g.first = (int)tab.size();
@@ -325,7 +381,7 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
 // Apply groups: keyed by kernel variant; also fills the block -> table-row map.
 // multi_kb > 0: tiles of the multi-step kernel advancing multi_kb steps per launch.
 std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab,
-                              std::vector<int>& tile_inst, int multi_kb = 0) {
+                              std::vector<int>& tile_inst, const Opts& o, int multi_kb = 0) {
     // weight kind: 0 stationary table, 1 frozen velocity, 2 non-uniform grid
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < count; ++k)
@@ -339,19 +395,18 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         g.frozen = std::get<3>(kv.first) == 1;
         g.nonuniform = std::get<3>(kv.first) == 2;
         g.first = (int)tab.size();
-        int64_t nodes = 0;
-        for (int k : kv.second) nodes += prob[k].N;
+        for (int k : kv.second) g.nodes += prob[k].N;
         g.stepk = !g.nonuniform && (multi_kb > 0 || g.scheme == LMEP_ETDRK4);
         g.resident = g.nonuniform && multi_kb > 0;
         for (int k : kv.second) g.max_nodes = std::max(g.max_nodes, prob[k].N);
-        const int64_t avg = nodes / (int64_t)kv.second.size();
-        const int forced = t_apply_tile.load();  // 0, 64 (non-uniform groups only), 256 or 1024
+        const int64_t avg = g.nodes / (int64_t)kv.second.size();
+        const int forced = o.apply_tile;  // 0, 64 (non-uniform groups only), 256 or 1024
         g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb > 0 ? multi_kb : 1)
                  : (forced != 0 && (forced != kApplyTileTiny || g.nonuniform))
                      ? forced
                      : (g.nonuniform && avg <= kApplyTileTiny)
                            ? kApplyTileTiny
-                           : ((nodes < kSmallGroupNodes || avg <= kApplyTileSmall) ? kApplyTileSmall : kApplyTile);
+                           : ((g.nodes < kSmallGroupNodes || avg <= kApplyTileSmall) ? kApplyTileSmall : kApplyTile);
         int64_t tiles = 0;
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
@@ -368,58 +423,97 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
     return groups;
 }
 
-// Host staging for the device tables: pinned memory owned by the calling
-// thread, reused across calls; an event guards reuse until the previous copy
-// has been consumed.
+// Names of the kernels a group launches, as a kernel trace shows them
+// (namespace and argument list left out).
+std::string bool_s(bool b) { return b ? "true" : "false"; }
+std::string build_kernel_name(const Group& g, bool fused, bool multi, int kb) {
+    char b[96];
+    if (g.nonuniform) return "build_wide_kernel";
+    if (g.taylor && multi) snprintf(b, sizeof(b), "taylor_stepk_kernel<%d>", g.n);
+    else if (g.taylor) snprintf(b, sizeof(b), "build_taylor_kernel<%d,%s>", g.n, bool_s(fused).c_str());
+    else snprintf(b, sizeof(b), "build_pade_kernel<%d,%d,%s>", g.n, g.p, bool_s(fused).c_str());
+    (void)kb;
+    return b;
+}
+std::string apply_kernel_name(const Group& g, int kb) {
+    char b[96];
+    const int nl = g.scheme == LMEP_LINEAR ? 0 : g.nonlin;
+    if (g.stepk && g.scheme == LMEP_ETDRK4) snprintf(b, sizeof(b), "stepk_rk4_kernel<%d,%d,%d>", g.n, g.nonlin, kb);
+    else if (g.stepk) snprintf(b, sizeof(b), "stepk_kernel<%d,%d,%d,%d>", g.n, g.scheme, nl, kb);
+    else if (g.resident) snprintf(b, sizeof(b), "resident_kernel<%d,%d,%d>", g.n, g.scheme, nl);
+    else snprintf(b, sizeof(b), "apply_kernel<%d,%d,%d,%s,%d>", g.n, g.scheme, nl, bool_s(g.pernode).c_str(), g.tile);
+    return b;
+}
+
+// Host staging for uploads of device tables: a ring of pinned buffers owned by
+// the calling thread, each guarded by an event until its copy has been
+// consumed, so that consecutive calls do not wait for each other's copies.
 struct Staging {
-    void* host = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-    bool pending = false;
+    static constexpr int kSlots = 8;
+    struct Slot {
+        void* host = nullptr;
+        size_t cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    } slot[kSlots];
+    int next = 0;
     ~Staging() {
-        if (pending && done) hipEventSynchronize(done);
-        if (host) hipHostFree(host);
-        if (done) hipEventDestroy(done);
+        for (Slot& s : slot) {
+            if (s.pending && s.done) (void)hipEventSynchronize(s.done);
+            if (s.host) (void)hipHostFree(s.host);
+            if (s.done) (void)hipEventDestroy(s.done);
+        }
     }
 };
 thread_local Staging t_stage;
 
-// by_args: write the tables through kernel arguments (upload_by_args) instead,
-// which needs no pinned host buffer (lmep_step_noalloc).
-int upload(const std::vector<DevProb>& a, const std::vector<DevProb>& b, void* d_a, void* d_b, hipStream_t s,
-           const std::vector<int>* c = nullptr, void* d_c = nullptr, bool by_args = false) {
-    const size_t na = a.size() * sizeof(DevProb), nb = b.size() * sizeof(DevProb);
-    const size_t nc = c ? c->size() * sizeof(int) : 0;
-    if (by_args) {
-        if (na) HIP_TRY(upload_by_args(d_a, a.data(), na, s));
-        if (nb) HIP_TRY(upload_by_args(d_b, b.data(), nb, s));
-        if (nc) HIP_TRY(upload_by_args(d_c, c->data(), nc, s));
-        return LMEP_OK;
-    }
-    Staging& st = t_stage;
+// One host-to-device copy of `bytes` from `image` to d_dst on s.
+int upload_image(const void* image, size_t bytes, void* d_dst, hipStream_t s) {
+    if (bytes == 0) return LMEP_OK;
+    Staging::Slot& st = t_stage.slot[t_stage.next];
+    t_stage.next = (t_stage.next + 1) % Staging::kSlots;
     if (!st.done) HIP_TRY(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     if (st.pending) {
         HIP_TRY(hipEventSynchronize(st.done));
         st.pending = false;
     }
-    if (st.cap < na + nb + nc) {
+    if (st.cap < bytes) {
         if (st.host) HIP_TRY(hipHostFree(st.host));
         st.host = nullptr;
         st.cap = 0;
-        const size_t cap = std::max<size_t>(na + nb + nc, 1 << 16);
+        const size_t cap = std::max<size_t>(bytes, 1 << 16);
         HIP_TRY(hipHostMalloc(&st.host, cap, hipHostMallocDefault));
         st.cap = cap;
     }
-    char* h = (char*)st.host;
-    if (na) std::memcpy(h, a.data(), na);
-    if (nb) std::memcpy(h + na, b.data(), nb);
-    if (nc) std::memcpy(h + na + nb, c->data(), nc);
-    if (na) HIP_TRY(hipMemcpyAsync(d_a, h, na, hipMemcpyHostToDevice, s));
-    if (nb) HIP_TRY(hipMemcpyAsync(d_b, h + na, nb, hipMemcpyHostToDevice, s));
-    if (nc) HIP_TRY(hipMemcpyAsync(d_c, h + na + nb, nc, hipMemcpyHostToDevice, s));
+    std::memcpy(st.host, image, bytes);
+    HIP_TRY(hipMemcpyAsync(d_dst, st.host, bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(st.done, s));
     st.pending = true;
     return LMEP_OK;
+}
+
+// Device tables of a call, laid out as in the scratch buffer from offset 0:
+// pieces (scratch offset, bytes, data) go into one host image and one copy,
+// or, by_args, through kernel arguments (lmep_step_noalloc).
+struct Piece {
+    size_t off;
+    size_t bytes;
+    const void* data;
+};
+int upload_pieces(const std::vector<Piece>& pieces, char* base, hipStream_t s, bool by_args) {
+    if (by_args) {
+        for (const Piece& p : pieces)
+            if (p.bytes) HIP_TRY(upload_by_args(base + p.off, p.data, p.bytes, s));
+        return LMEP_OK;
+    }
+    size_t end = 0;
+    for (const Piece& p : pieces)
+        if (p.bytes) end = std::max(end, p.off + p.bytes);
+    if (end == 0) return LMEP_OK;
+    std::vector<char> image(end, 0);
+    for (const Piece& p : pieces)
+        if (p.bytes) std::memcpy(image.data() + p.off, p.data, p.bytes);
+    return upload_image(image.data(), end, base, s);
 }
 
 // Scratch checks first (host only), then pick up any pending device error.
@@ -432,39 +526,86 @@ int entry_checks(void* d_scratch, size_t scratch_bytes, size_t need) {
     return LMEP_OK;
 }
 
-// HIP events bracketing every build and apply launch (LMEP_F_PROFILE).  All
-// events are created before the first launch so that recording them costs
-// the host little and the host stays ahead of the device.
+// HIP events bracketing every launch of the profiled kernels, one list per
+// kernel name.  All events are created before the first launch so that
+// recording them costs the host little and the host stays ahead of the device.
 struct Timer {
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> build, apply;
-    size_t nb = 0, na = 0;
+    struct Span {
+        int kernel;    // index into names
+        bool build;    // weight-build (or fused build + step) launch, else apply
+        hipEvent_t a = nullptr, b = nullptr;
+    };
+    std::vector<std::string> names;
+    std::vector<Span> spans;
+    size_t used = 0;
     ~Timer() {
-        for (auto& v : {&build, &apply})
-            for (auto& ev : *v) {
-                if (ev.first) hipEventDestroy(ev.first);
-                if (ev.second) hipEventDestroy(ev.second);
-            }
+        for (Span& sp : spans) {
+            if (sp.a) (void)hipEventDestroy(sp.a);
+            if (sp.b) (void)hipEventDestroy(sp.b);
+        }
     }
-    hipError_t reserve(size_t builds, size_t applies) {
+    hipError_t reserve(size_t launches) {
         if (!on) return hipSuccess;
-        build.assign(builds, {nullptr, nullptr});
-        apply.assign(applies, {nullptr, nullptr});
+        spans.assign(launches, Span{});
         hipError_t e;
-        for (auto& v : {&build, &apply})
-            for (auto& ev : *v) {
-                if ((e = hipEventCreate(&ev.first)) != hipSuccess) return e;
-                if ((e = hipEventCreate(&ev.second)) != hipSuccess) return e;
-            }
+        for (Span& sp : spans) {
+            if ((e = hipEventCreate(&sp.a)) != hipSuccess) return e;
+            if ((e = hipEventCreate(&sp.b)) != hipSuccess) return e;
+        }
         return hipSuccess;
     }
-    hipError_t mark(bool is_build, hipStream_t s, bool begin) {
-        if (!on) return hipSuccess;
-        auto& v = is_build ? build : apply;
-        size_t& k = is_build ? nb : na;
-        if (k >= v.size()) return hipErrorInvalidValue;
-        if (begin) return hipEventRecord(v[k].first, s);
-        return hipEventRecord(v[k++].second, s);
+    int kernel_index(const std::string& name) {
+        for (size_t k = 0; k < names.size(); ++k)
+            if (names[k] == name) return (int)k;
+        names.push_back(name);
+        return (int)names.size() - 1;
+    }
+    // begin(): returns the span index (or -1 when off); end(idx) records its end
+    int begin(const std::string& name, bool build, hipStream_t s, hipError_t& e) {
+        e = hipSuccess;
+        if (!on) return -1;
+        if (used >= spans.size()) {
+            e = hipErrorInvalidValue;
+            return -1;
+        }
+        Span& sp = spans[used];
+        sp.kernel = kernel_index(name);
+        sp.build = build;
+        e = hipEventRecord(sp.a, s);
+        return (int)used++;
+    }
+    hipError_t end(int idx, hipStream_t s) {
+        if (!on || idx < 0) return hipSuccess;
+        return hipEventRecord(spans[idx].b, s);
+    }
+    // waits for the events; totals into the thread's profile records
+    int collect(hipStream_t s) {
+        if (!on) return LMEP_OK;
+        HIP_TRY(hipStreamSynchronize(s));
+        double bms = 0.0, ams = 0.0;
+        int32_t bn = 0, an = 0;
+        std::vector<KernelTime> per(names.size());
+        for (size_t k = 0; k < names.size(); ++k) per[k].name = names[k];
+        for (size_t k = 0; k < used; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, spans[k].a, spans[k].b));
+            per[spans[k].kernel].ms += ms;
+            per[spans[k].kernel].launches += 1;
+            if (spans[k].build) {
+                bms += ms;
+                ++bn;
+            } else {
+                ams += ms;
+                ++an;
+            }
+        }
+        t_prof_build_ms = bms;
+        t_prof_apply_ms = ams;
+        t_prof_build_n = bn;
+        t_prof_apply_n = an;
+        t_prof_kernels = per;
+        return LMEP_OK;
     }
 };
 
@@ -474,11 +615,486 @@ struct Timer {
 struct CaptureStream {
     hipStream_t s = nullptr;
     ~CaptureStream() {
-        if (s) hipStreamDestroy(s);
+        if (s) (void)hipStreamDestroy(s);
     }
 };
 thread_local CaptureStream t_capture;
 
+// ------------------------------------------------------------- step plans --
+// Everything lmep_step needs besides the pointers of one call: the checked
+// batch, the option values, the launch groups and their device tables (their
+// place in the scratch buffer given by the layout).
+struct StepPlan {
+    Opts o;
+    bool multi = false;  // LMEP_F_PERSISTENT
+    int kb = 1;          // steps per launch
+    bool fuse = true;    // frozen-velocity steps in one kernel per launch
+    int count = 0;
+    std::vector<Group> bgroups, agroups;
+    std::vector<DevProb> btab, atab;
+    std::vector<int> tile_inst;
+    bool all_resident = false;    // every group advances all steps in its first launch
+    bool apply_launched = false;  // any apply kernel besides the fused ones
+    bool need_taylor = false;
+    Layout L;
+    int64_t ext = 0;
+};
+
+int make_step_plan(StepPlan& P, const lmep_problem* prob, int32_t count, bool multi, const Opts& o) {
+    int rc = check_all(prob, count, true);
+    if (rc) return rc;
+    if (multi)
+        for (int k = 0; k < count; ++k) {
+            if (frozen(prob[k]) && (!taylor(prob[k], o) || prob[k].bc == LMEP_BC_NEUMANN))
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with BURGERS_FROZEN (instance %d) needs the "
+                            "finite-Taylor build (react = 0, LMEP_EXP_AUTO) on a Dirichlet or periodic grid", k);
+            if (prob[k].window != LMEP_WIN_CENTRED && !frozen(prob[k]))
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with stationary weights needs centred windows "
+                            "(instance %d)", k);
+            if (nonuniform(prob[k]) && prob[k].N > kResidentMaxN)
+                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT on a non-uniform grid needs N <= %d "
+                            "(instance %d)", kResidentMaxN, k);
+        }
+    P.o = o;
+    P.multi = multi;
+    P.kb = multi ? o.steps_per_launch : 1;
+    P.fuse = o.fuse_frozen != 0 || multi;  // the multi-step frozen-velocity kernel is always fused
+    P.count = count;
+    P.bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, P.btab, o, multi ? P.kb : 0);
+    P.agroups = plan_apply(prob, count, P.atab, P.tile_inst, o, multi ? P.kb : 0);
+    for (auto& g : P.bgroups) P.need_taylor |= g.taylor;
+    P.all_resident = P.bgroups.empty();
+    for (auto& g : P.agroups) P.all_resident &= g.resident;
+    for (auto& g : P.agroups) P.apply_launched |= !(g.frozen && P.fuse);
+    P.L = layout(prob, count, 1);
+    P.ext = state_extent(prob, count);
+    return LMEP_OK;
+}
+
+std::vector<Piece> step_pieces(const StepPlan& P) {
+    return {{P.L.build_tab, P.btab.size() * sizeof(DevProb), P.btab.data()},
+            {P.L.apply_tab, P.atab.size() * sizeof(DevProb), P.atab.data()},
+            {P.L.tile_inst, P.tile_inst.size() * sizeof(int), P.tile_inst.data()}};
+}
+
+// Apply-kernel launches per group for n_steps steps.
+int step_launches(const StepPlan& P, int n_steps) { return P.all_resident ? 1 : (n_steps + P.kb - 1) / P.kb; }
+
+// The launch sequence of n_steps steps (kernels only: capturable).
+int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double* tay, double* d_w,
+                  const double* d_u_in, double* d_u_out, int n_steps, unsigned long long* counters, Timer& timer,
+                  hipStream_t s) {
+    const DevProb* dbt = (const DevProb*)(base + P.L.build_tab);
+    const DevProb* dat = (const DevProb*)(base + P.L.apply_tab);
+    const int* dti = (const int*)(base + P.L.tile_inst);
+    double* bufA = (double*)(base + P.L.state);
+    const int launches = step_launches(P, n_steps);
+    const int kb = P.kb;
+    hipError_t e = hipSuccess;
+    // destinations alternate between the scratch state and d_u_out so that
+    // the last step lands in d_u_out and no step works in place
+    for (int st = 0; st < launches; ++st) {
+        const double* src = (st == 0) ? d_u_in : (((launches - st) % 2 == 0) ? d_u_out : bufA);
+        double* dst = ((launches - 1 - st) % 2 == 0) ? d_u_out : bufA;
+        // frozen-velocity groups: weights rebuilt, and with fusion applied in
+        // the same kernel (their apply groups are then skipped)
+        for (auto& gr : P.bgroups) {
+            const int t = timer.on ? timer.begin(build_kernel_name(gr, P.fuse, P.multi, kb), true, s, e) : -1;
+            HIP_TRY(e);
+            if (gr.taylor && P.multi)
+                HIP_TRY(launch_taylor_stepk(gr.n, kb, std::min(kb, n_steps - st * kb), gr.reg, dbt + gr.first,
+                                            gr.count, gr.items, fd, tay, src, dst, counters, s));
+            else if (gr.taylor)
+                HIP_TRY(launch_build_taylor(gr.n, dbt + gr.first, gr.count, gr.items, fd, tay, src, d_w, counters, s,
+                                            P.fuse ? dst : nullptr));
+            else
+                HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters, s,
+                                     P.fuse ? dst : nullptr));
+            HIP_TRY(timer.end(t, s));
+        }
+        int64_t tile0 = 0;
+        for (auto& gr : P.agroups) {
+            const bool fused = gr.frozen && P.fuse;  // already advanced by its build kernel
+            if (!fused) {
+                const int t = timer.on ? timer.begin(apply_kernel_name(gr, kb), false, s, e) : -1;
+                HIP_TRY(e);
+                if (gr.stepk)
+                    HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
+                                         dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
+                else if (gr.resident) {
+                    // in place after the first chunk: a block reads its whole
+                    // instance before it writes any of it
+                    for (int done = 0; st == 0 && done < n_steps; done += kResidentMaxSteps)
+                        HIP_TRY(launch_resident(gr.n, gr.scheme, gr.nonlin, dat + gr.first, gr.count, gr.max_nodes,
+                                                d_w, done == 0 ? d_u_in : d_u_out, d_u_out,
+                                                std::min(kResidentMaxSteps, n_steps - done), s));
+                } else if (gr.nonuniform)
+                    HIP_TRY(launch_apply_nonuniform(gr.n, gr.tile, gr.scheme, gr.nonlin, dat + gr.first, dti + tile0,
+                                                    gr.items, fd, d_w, src, dst, s));
+                else
+                    HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first,
+                                         dti + tile0, gr.items, fd, d_w, src, dst, s));
+                HIP_TRY(timer.end(t, s));
+            }
+            tile0 += gr.items;
+        }
+    }
+    return LMEP_OK;
+}
+
+// Instantiated graphs of a plan's step loop, keyed by the pointers and the
+// step count they were captured with; the oldest is dropped beyond kMax.
+struct GraphCache {
+    static constexpr size_t kMax = 4;
+    struct Entry {
+        const void *w, *in, *out;
+        int steps;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> entries;
+    void clear() {
+        for (Entry& e : entries) (void)hipGraphExecDestroy(e.exec);
+        entries.clear();
+    }
+    ~GraphCache() { clear(); }
+};
+
+// Capture the step loop on this thread's capture stream and instantiate it.
+int capture_steps(const StepPlan& P, char* base, const double* fd, const double* tay, double* d_w,
+                  const double* d_u_in, double* d_u_out, int n_steps, hipGraphExec_t* exec) {
+    if (!t_capture.s) HIP_TRY(hipStreamCreateWithFlags(&t_capture.s, hipStreamNonBlocking));
+    hipStream_t cs = t_capture.s;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    Timer off;
+    int rc = enqueue_steps(P, base, fd, tay, d_w, d_u_in, d_u_out, n_steps, nullptr, off, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return LMEP_OK;
+}
+
+// n_steps steps of a planned batch whose tables are in place at `base`.
+// cache: graphs kept across calls (plans), or nullptr (captured, replayed and
+// destroyed within the call).
+int run_step(const StepPlan& P, char* base, double* d_w, const double* d_u_in, double* d_u_out, int n_steps,
+             uint32_t flags, hipStream_t s, GraphCache* cache) {
+    const double* fd = nullptr;
+    const double* tay = nullptr;
+    HIP_TRY(fd_table_init(&fd));
+    if (P.need_taylor) HIP_TRY(taylor_table_init(&tay));
+    Timer timer;
+    timer.on = (flags & LMEP_F_PROFILE) != 0;
+    const size_t per_launch = P.bgroups.size() + P.agroups.size();
+    HIP_TRY(timer.reserve(per_launch * (size_t)step_launches(P, n_steps)));
+    unsigned long long* counters = (flags & LMEP_F_COUNT) ? (unsigned long long*)(base + P.L.flag + 64) : nullptr;
+    if (counters) HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(unsigned long long), s));
+    int rc;
+    if (flags & LMEP_F_GRAPH) {
+        hipGraphExec_t exec = nullptr;
+        if (cache)
+            for (auto& en : cache->entries)
+                if (en.w == d_w && en.in == d_u_in && en.out == d_u_out && en.steps == n_steps) exec = en.exec;
+        const bool fresh = exec == nullptr;
+        if (fresh && (rc = capture_steps(P, base, fd, tay, d_w, d_u_in, d_u_out, n_steps, &exec))) return rc;
+        hipError_t e = hipGraphLaunch(exec, s);
+        if (fresh) {
+            if (cache) {
+                if (cache->entries.size() >= GraphCache::kMax) {
+                    (void)hipGraphExecDestroy(cache->entries.front().exec);
+                    cache->entries.erase(cache->entries.begin());
+                }
+                cache->entries.push_back({d_w, d_u_in, d_u_out, n_steps, exec});
+            } else {
+                (void)hipGraphExecDestroy(exec);
+            }
+        }
+        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "graph launch: %s", hipGetErrorString(e));
+    } else if ((rc = enqueue_steps(P, base, fd, tay, d_w, d_u_in, d_u_out, n_steps, counters, timer, s))) {
+        return rc;
+    }
+    if ((rc = timer.collect(s))) return rc;
+    if (counters) {
+        unsigned long long hc[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        t_prof_matrices = (int64_t)hc[0];
+        t_prof_squarings = (int64_t)hc[1];
+    }
+    if (flags & LMEP_F_CHECK_FINITE) {
+        int* dflag = (int*)(base + P.L.flag);
+        HIP_TRY(hipMemsetAsync(dflag, 0, sizeof(int), s));
+        for (const DevProb& d : P.atab) HIP_TRY(launch_check_finite(d_u_out + d.state_off, d.N, dflag, s));
+        int hflag = 0;
+        HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hflag) return fail(LMEP_ERR_NONFINITE, "non-finite value in the result");
+    }
+    return LMEP_OK;
+}
+
+// Checks of one lmep_step call's pointers and flags (the batch is checked by
+// make_step_plan).
+int check_step_call(double* d_w, const double* d_u_in, double* d_u_out, int32_t n_steps, uint32_t flags,
+                    int64_t ext) {
+    if (!d_w || !d_u_in || !d_u_out) return fail(LMEP_ERR_ARG, "NULL weight or state pointer");
+    if (n_steps < 1) return fail(LMEP_ERR_ARG, "n_steps must be >= 1");
+    if (flags & ~(LMEP_F_GRAPH | LMEP_F_PERSISTENT | LMEP_F_CHECK_FINITE | LMEP_F_PROFILE | LMEP_F_COUNT))
+        return fail(LMEP_ERR_ARG, "unknown flag bits 0x%x", flags);
+    if ((flags & LMEP_F_GRAPH) && (flags & (LMEP_F_PROFILE | LMEP_F_COUNT)))
+        return fail(LMEP_ERR_ARG, "LMEP_F_PROFILE / LMEP_F_COUNT cannot be combined with LMEP_F_GRAPH");
+    const char *a = (const char*)d_u_in, *b = (const char*)d_u_out;
+    const size_t bytes = sizeof(double) * (size_t)ext;
+    if (a < b + bytes && b < a + bytes) return fail(LMEP_ERR_ARG, "d_u_in and d_u_out overlap");
+    return LMEP_OK;
+}
+
+// lmep_step and lmep_step_noalloc.  noalloc: the scratch is this device's
+// static array (d_scratch and scratch_bytes are ignored) and the tables go in
+// through kernel arguments.
+int step_impl(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
+              int32_t n_steps, uint32_t flags, void* d_scratch, size_t scratch_bytes, void* hip_stream,
+              bool noalloc) {
+    StepPlan P;
+    int rc = make_step_plan(P, prob, count, (flags & LMEP_F_PERSISTENT) != 0, process_opts());
+    if (rc) return rc;
+    if ((rc = check_step_call(d_w, d_u_in, d_u_out, n_steps, flags, P.ext))) return rc;
+    if (noalloc) {
+        if (P.L.total > kStaticScratchBytes)
+            return fail(LMEP_ERR_SCRATCH, "this batch needs %zu bytes of scratch; the static array holds %zu",
+                        P.L.total, kStaticScratchBytes);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "earlier device error: %s", hipGetErrorString(e));
+        HIP_TRY(static_scratch(&d_scratch));
+    } else if ((rc = entry_checks(d_scratch, scratch_bytes, P.L.total))) {
+        return rc;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    char* base = (char*)d_scratch;
+    if ((rc = upload_pieces(step_pieces(P), base, s, noalloc))) return rc;
+    return run_step(P, base, d_w, d_u_in, d_u_out, n_steps, flags, s, nullptr);
+}
+
+// ---------------------------------------------------------- adjoint plans --
+struct AdjGroup {
+    int n = 0, p = 0, first = 0, cnt = 0;
+    int64_t nodes = 0, tiles = 0;
+    bool taylor = false;
+    bool fused = false;  // whole step in one kernel (finite Taylor, tiles of adj_fused_tile(n) nodes)
+    int64_t ftiles = 0;
+};
+struct AdjPlan {
+    Opts o;
+    int count = 0;
+    std::vector<AdjGroup> groups;
+    std::vector<DevProb> nftab, ttab;  // node table then fused-tile table; 256-node tile table
+    size_t ntab = 0;                   // node-table entries (first part of nftab)
+    bool need_taylor = false;
+    Layout L;
+    int64_t ext = 0;
+};
+
+int make_adj_plan(AdjPlan& P, const lmep_problem* prob, int32_t count, const Opts& o) {
+    int rc = check_all(prob, count, false);
+    if (rc) return rc;
+    for (int k = 0; k < count; ++k) {
+        const lmep_problem& q = prob[k];
+        if (q.scheme == LMEP_ETD2RK || q.scheme == LMEP_ETDRK4 || q.nonlin == LMEP_NL_KDV ||
+            q.window != LMEP_WIN_CENTRED || nonuniform(q))
+            return fail(LMEP_ERR_UNSUPPORTED,
+                        "instance %d: the reverse step covers LINEAR and ETD1 without KdV, centred windows, "
+                        "uniform grids", k);
+    }
+    P.o = o;
+    P.count = count;
+    // groups by (n, p, method): a node table and a tile table with the same
+    // instance order; instances without a reaction term take the finite
+    // Taylor series unless LMEP_OPT_EXP_METHOD asks for Pade
+    const bool auto_method = o.exp_method == LMEP_EXP_AUTO;
+    std::map<std::tuple<int, int, int>, std::vector<int>> by;
+    for (int k = 0; k < count; ++k)
+        by[{prob[k].n, scheme_p(prob[k].scheme), (auto_method && prob[k].react == 0.0) ? 1 : 0}].push_back(k);
+    std::vector<DevProb> ntab, ftab;
+    for (auto& kv : by) {
+        AdjGroup g;
+        g.n = std::get<0>(kv.first);
+        g.p = std::get<1>(kv.first);
+        g.first = (int)ntab.size();
+        g.cnt = (int)kv.second.size();
+        g.taylor = std::get<2>(kv.first) == 1;
+        g.fused = g.taylor;
+        P.need_taylor |= g.taylor;
+        for (int k : kv.second) {
+            DevProb d = to_dev(prob[k], k);
+            d.item_begin = g.nodes;
+            ntab.push_back(d);
+            d.item_begin = g.tiles;  // tile tables are searched from the group's first tile
+            P.ttab.push_back(d);
+            d.item_begin = g.ftiles;
+            ftab.push_back(d);
+            g.nodes += prob[k].N;
+            g.tiles += (prob[k].N + kAdjTile - 1) / kAdjTile;
+            g.ftiles += (prob[k].N + adj_fused_tile(g.n) - 1) / adj_fused_tile(g.n);
+        }
+        P.groups.push_back(g);
+    }
+    P.ntab = ntab.size();
+    P.nftab = ntab;
+    P.nftab.insert(P.nftab.end(), ftab.begin(), ftab.end());
+    P.L = layout(prob, count, 2);
+    P.ext = state_extent(prob, count);
+    return LMEP_OK;
+}
+
+std::vector<Piece> adj_pieces(const AdjPlan& P) {
+    return {{P.L.build_tab, P.nftab.size() * sizeof(DevProb), P.nftab.data()},
+            {P.L.apply_tab, P.ttab.size() * sizeof(DevProb), P.ttab.data()}};
+}
+
+int check_adj_call(const double* d_u_k, const double* d_lambda_next, double* d_lambda_k, double* d_grad,
+                   int64_t ext) {
+    if (!d_u_k || !d_lambda_next || !d_lambda_k || !d_grad) return fail(LMEP_ERR_ARG, "NULL pointer argument");
+    const char *a = (const char*)d_lambda_next, *b = (const char*)d_lambda_k;
+    const size_t bytes = sizeof(double) * (size_t)ext;
+    if (a < b + bytes && b < a + bytes) return fail(LMEP_ERR_ARG, "d_lambda_next and d_lambda_k overlap");
+    return LMEP_OK;
+}
+
+int run_adjoint(const AdjPlan& P, char* base, const double* d_u_k, const double* d_lambda_next, double* d_lambda_k,
+                double* d_grad, hipStream_t s) {
+    const double* fd = nullptr;
+    const double* tay = nullptr;
+    HIP_TRY(fd_table_init(&fd));
+    if (P.need_taylor) HIP_TRY(taylor_table_init(&tay));
+    const DevProb* dn = (const DevProb*)(base + P.L.build_tab);
+    const DevProb* df = dn + P.ntab;
+    const DevProb* dtt = (const DevProb*)(base + P.L.apply_tab);
+    // optional profiling: events around each group's per-node kernel and around the whole step
+    const bool prof = P.o.profile_adjoint != 0;
+    std::vector<hipEvent_t> ev;
+    auto make_event = [&](hipEvent_t* e) -> hipError_t {
+        hipError_t r = hipEventCreate(e);
+        if (r == hipSuccess) ev.push_back(*e);
+        return r;
+    };
+    struct Cleanup {
+        std::vector<hipEvent_t>& ev;
+        ~Cleanup() {
+            for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        }
+    } cleanup{ev};
+    hipEvent_t all_a = nullptr, all_b = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> per(P.groups.size(), {nullptr, nullptr});
+    if (prof) {
+        HIP_TRY(make_event(&all_a));
+        HIP_TRY(make_event(&all_b));
+        for (auto& pe : per) {
+            HIP_TRY(make_event(&pe.first));
+            HIP_TRY(make_event(&pe.second));
+        }
+        HIP_TRY(hipEventRecord(all_a, s));
+    }
+    int64_t part_base = 0;
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+        const AdjGroup& g = P.groups[gi];
+        AdjointLaunch a;
+        a.n = g.n;
+        a.p = g.p;
+        a.node_probs = dn + g.first;
+        a.tile_probs = dtt + g.first;
+        a.nprob = g.cnt;
+        a.tiles = g.tiles;
+        a.nodes = g.nodes;
+        a.fd = fd;
+        a.u = d_u_k;
+        a.lam = d_lambda_next;
+        a.lam_out = d_lambda_k;
+        a.grad = d_grad;
+        a.g = (double*)(base + P.L.g);
+        a.ghat = (double*)(base + P.L.ghat);
+        a.ws = (double*)(base + P.L.ws);
+        a.ws_stride = P.L.ws_stride;
+        a.dparam = (double*)(base + P.L.dparam);
+        // per-tile partial sums: the group's own rows of the partial-sum array
+        a.part = (double*)(base + P.L.part) + 3 * part_base;
+        a.taylor = g.taylor ? tay : nullptr;
+        if (g.fused) {
+            a.fused_probs = df + g.first;
+            a.fused_tiles = g.ftiles;
+        }
+        if (prof) {
+            a.frechet_begin = per[gi].first;
+            a.frechet_end = per[gi].second;
+        }
+        HIP_TRY(launch_adjoint(a, s));
+        part_base += g.fused ? g.ftiles : g.tiles;
+    }
+    if (prof) {
+        HIP_TRY(hipEventRecord(all_b, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double fms = 0.0;
+        std::vector<KernelTime> kt;
+        for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, per[gi].first, per[gi].second));
+            fms += ms;
+            char nm[64];
+            snprintf(nm, sizeof(nm), "%s<%d,%d>", P.groups[gi].fused ? "adj_fused_kernel" : "adj_frechet_kernel",
+                     P.groups[gi].n, P.groups[gi].p);
+            bool found = false;
+            for (auto& k : kt)
+                if (k.name == nm) {
+                    k.ms += ms;
+                    k.launches += 1;
+                    found = true;
+                }
+            if (!found) kt.push_back({nm, (double)ms, 1});
+        }
+        float all = 0.f;
+        HIP_TRY(hipEventElapsedTime(&all, all_a, all_b));
+        t_prof_build_ms = fms;
+        t_prof_build_n = (int32_t)P.groups.size();
+        t_prof_apply_ms = (double)all - fms;
+        t_prof_apply_n = 1;
+        t_prof_kernels = kt;
+    }
+    return LMEP_OK;
+}
+
+}  // namespace
+
+// A plan: one batch's checked problems, launch groups and option values, its
+// device tables uploaded once into the caller's scratch buffer, and the graphs
+// captured for it.
+struct lmep_plan_s {
+    int op = 0;
+    char* base = nullptr;
+    hipEvent_t ready = nullptr;        // recorded after the table upload
+    hipStream_t created_on = nullptr;  // stream of the upload
+    std::vector<hipStream_t> waited;   // other streams made to wait for `ready`
+    hipEvent_t last = nullptr;         // recorded after each graph launch
+    bool launched_graph = false;
+    StepPlan step;
+    AdjPlan adj;
+    GraphCache graphs;
+};
+
+namespace {
+// Order work on stream s after the plan's table upload.
+int plan_order(lmep_plan_s* P, hipStream_t s) {
+    if (s == P->created_on) return LMEP_OK;
+    for (hipStream_t w : P->waited)
+        if (w == s) return LMEP_OK;
+    HIP_TRY(hipStreamWaitEvent(s, P->ready, 0));
+    P->waited.push_back(s);
+    return LMEP_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -496,40 +1112,27 @@ size_t lmep_scratch_bytes(const lmep_problem* prob, int32_t count, int32_t op) {
 const char* lmep_last_error(void) { return t_err; }
 
 int lmep_set_option(int32_t option, int32_t value) {
-    if (option == LMEP_OPT_STEPS_PER_LAUNCH) {
-        if (value != 1 && value != 2 && value != 4 && value != 8)
-            return fail(LMEP_ERR_ARG, "steps per launch must be 1, 2, 4 or 8, got %d", value);
-        t_steps_per_launch.store(value);
-        return LMEP_OK;
-    }
-    if (option == LMEP_OPT_PROFILE_ADJOINT || option == LMEP_OPT_FUSE_FROZEN) {
-        if (value != 0 && value != 1) return fail(LMEP_ERR_ARG, "option %d takes 0 or 1, got %d", option, value);
-        (option == LMEP_OPT_PROFILE_ADJOINT ? t_profile_adjoint : t_fuse_frozen).store(value);
-        return LMEP_OK;
-    }
-    if (option == LMEP_OPT_EXP_METHOD) {
-        if (value != LMEP_EXP_AUTO && value != LMEP_EXP_PADE)
-            return fail(LMEP_ERR_ARG, "exponential method must be LMEP_EXP_AUTO (0) or LMEP_EXP_PADE (1), got %d",
-                        value);
-        t_exp_method.store(value);
-        return LMEP_OK;
-    }
-    if (option == LMEP_OPT_APPLY_TILE) {
-        if (value != 0 && value != 64 && value != kApplyTileSmall && value != kApplyTile)
-            return fail(LMEP_ERR_ARG, "apply tile must be 0, 64, %d or %d, got %d", kApplyTileSmall, kApplyTile, value);
-        t_apply_tile.store(value);
-        return LMEP_OK;
-    }
-    return fail(LMEP_ERR_ARG, "unknown option %d", option);
+    Opts o = process_opts();
+    int rc = set_opt(o, option, value);
+    if (rc) return rc;
+    g_steps_per_launch.store(o.steps_per_launch);
+    g_profile_adjoint.store(o.profile_adjoint);
+    g_fuse_frozen.store(o.fuse_frozen);
+    g_apply_tile.store(o.apply_tile);
+    g_exp_method.store(o.exp_method);
+    return LMEP_OK;
 }
 
 int32_t lmep_get_option(int32_t option) {
-    if (option == LMEP_OPT_STEPS_PER_LAUNCH) return t_steps_per_launch.load();
-    if (option == LMEP_OPT_PROFILE_ADJOINT) return t_profile_adjoint.load();
-    if (option == LMEP_OPT_FUSE_FROZEN) return t_fuse_frozen.load();
-    if (option == LMEP_OPT_APPLY_TILE) return t_apply_tile.load();
-    if (option == LMEP_OPT_EXP_METHOD) return t_exp_method.load();
-    return fail(LMEP_ERR_ARG, "unknown option %d", option);
+    const Opts o = process_opts();
+    switch (option) {
+        case LMEP_OPT_STEPS_PER_LAUNCH: return o.steps_per_launch;
+        case LMEP_OPT_PROFILE_ADJOINT: return o.profile_adjoint;
+        case LMEP_OPT_FUSE_FROZEN: return o.fuse_frozen;
+        case LMEP_OPT_APPLY_TILE: return o.apply_tile;
+        case LMEP_OPT_EXP_METHOD: return o.exp_method;
+        default: return fail(LMEP_ERR_ARG, "unknown option %d", option);
+    }
 }
 
 int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_ms, int32_t* apply_launches,
@@ -541,6 +1144,16 @@ int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_m
     if (matrices) *matrices = t_prof_matrices;
     if (squarings) *squarings = t_prof_squarings;
     return LMEP_OK;
+}
+
+int32_t lmep_profile_kernel(int32_t k, char* name, size_t name_len, double* ms, int32_t* launches) {
+    const int32_t count = (int32_t)t_prof_kernels.size();
+    if (k < 0 || k >= count) return count;
+    const KernelTime& kt = t_prof_kernels[k];
+    if (name && name_len > 0) snprintf(name, name_len, "%s", kt.name.c_str());
+    if (ms) *ms = kt.ms;
+    if (launches) *launches = kt.launches;
+    return count;
 }
 
 int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_u, double* d_w, void* d_scratch,
@@ -555,11 +1168,12 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
     hipStream_t s = (hipStream_t)hip_stream;
     const double* fd = nullptr;
     HIP_TRY(fd_table_init(&fd));
-    std::vector<DevProb> btab, none;
+    std::vector<DevProb> btab;
     const double* tay = nullptr;
-    auto groups = plan_build(prob, count, [](const lmep_problem&) { return true; }, btab);
+    const Opts o = process_opts();
+    auto groups = plan_build(prob, count, [](const lmep_problem&) { return true; }, btab, o);
     char* base = (char*)d_scratch;
-    if ((rc = upload(btab, none, base + L.build_tab, nullptr, s))) return rc;
+    if ((rc = upload_pieces({{L.build_tab, btab.size() * sizeof(DevProb), btab.data()}}, base, s, false))) return rc;
     const DevProb* dtab = (const DevProb*)(base + L.build_tab);
     for (auto& g : groups) {
         if (g.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
@@ -572,213 +1186,6 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
     }
     return LMEP_OK;
 }
-
-}  // extern "C"
-
-namespace {
-
-// lmep_step and lmep_step_noalloc.  noalloc: the scratch is this device's
-// static array (d_scratch and scratch_bytes are ignored) and the tables go in
-// through kernel arguments.
-int step_impl(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
-              int32_t n_steps, uint32_t flags, void* d_scratch, size_t scratch_bytes, void* hip_stream,
-              bool noalloc) {
-    int rc = check_all(prob, count, true);
-    if (rc) return rc;
-    if (!d_w || !d_u_in || !d_u_out) return fail(LMEP_ERR_ARG, "NULL weight or state pointer");
-    if (n_steps < 1) return fail(LMEP_ERR_ARG, "n_steps must be >= 1");
-    if (flags & ~(LMEP_F_GRAPH | LMEP_F_PERSISTENT | LMEP_F_CHECK_FINITE | LMEP_F_PROFILE | LMEP_F_COUNT))
-        return fail(LMEP_ERR_ARG, "unknown flag bits 0x%x", flags);
-    const bool multi = (flags & LMEP_F_PERSISTENT) != 0;
-    if (multi)
-        for (int k = 0; k < count; ++k) {
-            if (frozen(prob[k]) && (!taylor(prob[k]) || prob[k].bc == LMEP_BC_NEUMANN))
-                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with BURGERS_FROZEN (instance %d) needs the "
-                            "finite-Taylor build (react = 0, LMEP_EXP_AUTO) on a Dirichlet or periodic grid", k);
-            if (prob[k].window != LMEP_WIN_CENTRED && !frozen(prob[k]))
-                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with stationary weights needs centred windows "
-                            "(instance %d)", k);
-            if (nonuniform(prob[k]) && prob[k].N > kResidentMaxN)
-                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT on a non-uniform grid needs N <= %d "
-                            "(instance %d)", kResidentMaxN, k);
-        }
-    if ((flags & LMEP_F_GRAPH) && (flags & (LMEP_F_PROFILE | LMEP_F_COUNT)))
-        return fail(LMEP_ERR_ARG, "LMEP_F_PROFILE / LMEP_F_COUNT cannot be combined with LMEP_F_GRAPH");
-    const int64_t ext = state_extent(prob, count);
-    {
-        const char *a = (const char*)d_u_in, *b = (const char*)d_u_out;
-        const size_t bytes = sizeof(double) * (size_t)ext;
-        if (a < b + bytes && b < a + bytes) return fail(LMEP_ERR_ARG, "d_u_in and d_u_out overlap");
-    }
-    const Layout L = layout(prob, count, 1);
-    if (noalloc) {
-        if (L.total > kStaticScratchBytes)
-            return fail(LMEP_ERR_SCRATCH, "this batch needs %zu bytes of scratch; the static array holds %zu",
-                        L.total, kStaticScratchBytes);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "earlier device error: %s", hipGetErrorString(e));
-        HIP_TRY(static_scratch(&d_scratch));
-    } else if ((rc = entry_checks(d_scratch, scratch_bytes, L.total))) {
-        return rc;
-    }
-    hipStream_t s = (hipStream_t)hip_stream;
-    const double* fd = nullptr;
-    HIP_TRY(fd_table_init(&fd));
-
-    std::vector<DevProb> btab, atab;
-    std::vector<int> tile_inst;
-    const int kb = multi ? t_steps_per_launch.load() : 1;
-    auto bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, btab, multi ? kb : 0);
-    const double* tay = nullptr;
-    for (auto& gr : bgroups)
-        if (gr.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
-    auto agroups = plan_apply(prob, count, atab, tile_inst, multi ? kb : 0);
-    // resident groups (small non-uniform instances) advance all n_steps from
-    // d_u_in to d_u_out in the first iteration; when nothing else is in the
-    // batch that iteration is all there is
-    bool all_resident = bgroups.empty();
-    for (auto& gr : agroups) all_resident &= gr.resident;
-    const int launches = all_resident ? 1 : (n_steps + kb - 1) / kb;  // apply launches per group
-    char* base = (char*)d_scratch;
-    if ((rc = upload(btab, atab, base + L.build_tab, base + L.apply_tab, s, &tile_inst, base + L.tile_inst,
-                     noalloc)))
-        return rc;
-    const DevProb* dbt = (const DevProb*)(base + L.build_tab);
-    const DevProb* dat = (const DevProb*)(base + L.apply_tab);
-    const int* dti = (const int*)(base + L.tile_inst);
-    double* bufA = (double*)(base + L.state);
-
-    Timer timer;
-    timer.on = (flags & LMEP_F_PROFILE) != 0;
-    HIP_TRY(timer.reserve(bgroups.empty() ? 0 : (size_t)launches, (size_t)launches));
-    unsigned long long* counters = (flags & LMEP_F_COUNT) ? (unsigned long long*)(base + L.flag + 64) : nullptr;
-    if (counters) HIP_TRY(hipMemsetAsync(counters, 0, 2 * sizeof(unsigned long long), s));
-    const bool graph = (flags & LMEP_F_GRAPH) != 0;
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    hipStream_t launch_stream = s;
-    if (graph) {
-        if (!t_capture.s) HIP_TRY(hipStreamCreateWithFlags(&t_capture.s, hipStreamNonBlocking));
-        s = t_capture.s;
-        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    }
-
-    // frozen-velocity groups under LMEP_F_PERSISTENT always take the fused multi-step kernel
-    const bool fuse = t_fuse_frozen.load() != 0 || multi;
-    bool apply_launched = false;  // any apply kernel besides the fused ones
-    for (auto& gr : agroups) apply_launched |= !(gr.frozen && fuse);
-    auto enqueue = [&]() -> int {
-        // destinations alternate between the scratch state and d_u_out so that
-        // the last step lands in d_u_out and no step works in place
-        for (int st = 0; st < launches; ++st) {
-            const double* src = (st == 0) ? d_u_in : (((launches - st) % 2 == 0) ? d_u_out : bufA);
-            double* dst = ((launches - 1 - st) % 2 == 0) ? d_u_out : bufA;
-            if (!bgroups.empty()) {
-                // frozen-velocity groups: weights rebuilt, and with fusion applied
-                // in the same kernel (their apply groups are then skipped)
-                HIP_TRY(timer.mark(true, s, true));
-                for (auto& gr : bgroups) {
-                    if (gr.taylor && multi)
-                        HIP_TRY(launch_taylor_stepk(gr.n, kb, std::min(kb, n_steps - st * kb), gr.reg, dbt + gr.first,
-                                                    gr.count, gr.items, fd, tay, src, dst, counters, s));
-                    else if (gr.taylor)
-                        HIP_TRY(launch_build_taylor(gr.n, dbt + gr.first, gr.count, gr.items, fd, tay, src, d_w,
-                                                    counters, s, fuse ? dst : nullptr));
-                    else
-                        HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters,
-                                             s, fuse ? dst : nullptr));
-                }
-                HIP_TRY(timer.mark(true, s, false));
-            }
-            if (apply_launched) HIP_TRY(timer.mark(false, s, true));
-            int64_t tile0 = 0;
-            for (auto& gr : agroups) {
-                const bool fused = gr.frozen && fuse;  // already advanced by its build kernel
-                if (!fused && gr.stepk)
-                    HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
-                                         dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
-                else if (gr.resident) {
-                    // in place after the first chunk: a block reads its whole
-                    // instance before it writes any of it
-                    for (int done = 0; st == 0 && done < n_steps; done += kResidentMaxSteps)
-                        HIP_TRY(launch_resident(gr.n, gr.scheme, gr.nonlin, dat + gr.first, gr.count, gr.max_nodes,
-                                                d_w, done == 0 ? d_u_in : d_u_out, d_u_out,
-                                                std::min(kResidentMaxSteps, n_steps - done), s));
-                }
-                else if (gr.nonuniform)
-                    HIP_TRY(launch_apply_nonuniform(gr.n, gr.tile, gr.scheme, gr.nonlin, dat + gr.first, dti + tile0,
-                                                    gr.items, fd, d_w, src, dst, s));
-                else if (!fused)
-                    HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first,
-                                         dti + tile0, gr.items, fd, d_w, src, dst, s));
-                tile0 += gr.items;
-            }
-            if (apply_launched) HIP_TRY(timer.mark(false, s, false));
-        }
-        return LMEP_OK;
-    };
-    rc = enqueue();
-    if (graph) {
-        hipError_t e = hipStreamEndCapture(s, &g);
-        if (rc) {
-            if (g) hipGraphDestroy(g);
-            return rc;
-        }
-        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-        s = launch_stream;
-        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphLaunch(ge, s);
-        if (ge) hipGraphExecDestroy(ge);
-        hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "graph launch: %s", hipGetErrorString(e));
-    } else if (rc) {
-        return rc;
-    }
-
-    if (timer.on) {
-        HIP_TRY(hipStreamSynchronize(s));
-        double bms = 0.0, ams = 0.0;
-        for (size_t k = 0; k < timer.nb; ++k) {
-            const auto& ev = timer.build[k];
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
-            bms += ms;
-        }
-        for (size_t k = 0; k < timer.na; ++k) {
-            const auto& ev = timer.apply[k];
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
-            ams += ms;
-        }
-        t_prof_build_ms = bms;
-        t_prof_apply_ms = ams;
-        t_prof_build_n = (int32_t)timer.nb;
-        t_prof_apply_n = (int32_t)timer.na;
-    }
-    if (counters) {
-        unsigned long long hc[2] = {0, 0};
-        HIP_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        t_prof_matrices = (int64_t)hc[0];
-        t_prof_squarings = (int64_t)hc[1];
-    }
-
-    if (flags & LMEP_F_CHECK_FINITE) {
-        int* dflag = (int*)(base + L.flag);
-        HIP_TRY(hipMemsetAsync(dflag, 0, sizeof(int), s));
-        for (int k = 0; k < count; ++k)
-            HIP_TRY(launch_check_finite(d_u_out + prob[k].state_off, prob[k].N, dflag, s));
-        int hflag = 0;
-        HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (hflag) return fail(LMEP_ERR_NONFINITE, "non-finite value in the result");
-    }
-    return LMEP_OK;
-}
-
-}  // namespace
-
-extern "C" {
 
 int lmep_step(const lmep_problem* prob, int32_t count, double* d_w, const double* d_u_in, double* d_u_out,
               int32_t n_steps, uint32_t flags, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
@@ -794,133 +1201,105 @@ int lmep_step_noalloc(const lmep_problem* prob, int32_t count, double* d_w, cons
 
 int lmep_adjoint_step(const lmep_problem* prob, int32_t count, const double* d_u_k, const double* d_lambda_next,
                       double* d_lambda_k, double* d_grad, void* d_scratch, size_t scratch_bytes, void* hip_stream) {
-    int rc = check_all(prob, count, false);
+    AdjPlan P;
+    int rc = make_adj_plan(P, prob, count, process_opts());
     if (rc) return rc;
-    for (int k = 0; k < count; ++k) {
-        const lmep_problem& q = prob[k];
-        if (q.scheme == LMEP_ETD2RK || q.scheme == LMEP_ETDRK4 || q.nonlin == LMEP_NL_KDV ||
-            q.window != LMEP_WIN_CENTRED || nonuniform(q))
-            return fail(LMEP_ERR_UNSUPPORTED,
-                        "instance %d: the reverse step covers LINEAR and ETD1 without KdV, centred windows, "
-                        "uniform grids", k);
-    }
-    if (!d_u_k || !d_lambda_next || !d_lambda_k || !d_grad) return fail(LMEP_ERR_ARG, "NULL pointer argument");
-    const int64_t ext = state_extent(prob, count);
-    {
-        const char *a = (const char*)d_lambda_next, *b = (const char*)d_lambda_k;
-        const size_t bytes = sizeof(double) * (size_t)ext;
-        if (a < b + bytes && b < a + bytes) return fail(LMEP_ERR_ARG, "d_lambda_next and d_lambda_k overlap");
-    }
-    const Layout L = layout(prob, count, 2);
-    if ((rc = entry_checks(d_scratch, scratch_bytes, L.total))) return rc;
+    if ((rc = check_adj_call(d_u_k, d_lambda_next, d_lambda_k, d_grad, P.ext))) return rc;
+    if ((rc = entry_checks(d_scratch, scratch_bytes, P.L.total))) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    const double* fd = nullptr;
-    HIP_TRY(fd_table_init(&fd));
-
-    // groups by (n, p, method): a node table and a tile table with the same
-    // instance order; instances without a reaction term take the finite
-    // Taylor series unless LMEP_OPT_EXP_METHOD asks for Pade
-    const bool auto_method = t_exp_method.load() == LMEP_EXP_AUTO;
-    std::map<std::tuple<int, int, int>, std::vector<int>> by;
-    for (int k = 0; k < count; ++k)
-        by[{prob[k].n, scheme_p(prob[k].scheme), (auto_method && prob[k].react == 0.0) ? 1 : 0}].push_back(k);
-    std::vector<DevProb> ntab, ttab, ftab;
-    struct G {
-        int n, p, first, cnt;
-        int64_t nodes, tiles;
-        bool taylor;
-        bool fused = false;  // whole step in one kernel (finite Taylor, tiles of adj_fused_tile(n) nodes)
-        int64_t ftiles = 0;
-    };
-    std::vector<G> groups;
-    const double* tay = nullptr;
-    int64_t tile_base = 0;
-    for (auto& kv : by) {
-        G g{std::get<0>(kv.first), std::get<1>(kv.first), (int)ntab.size(), (int)kv.second.size(), 0, 0,
-            std::get<2>(kv.first) == 1};
-        if (g.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
-        g.fused = g.taylor;
-        for (int k : kv.second) {
-            DevProb d = to_dev(prob[k], k);
-            d.item_begin = g.nodes;
-            ntab.push_back(d);
-            d.item_begin = tile_base + g.tiles;  // global tile index: rows of the partial-sum array
-            ttab.push_back(d);
-            d.item_begin = g.ftiles;
-            ftab.push_back(d);
-            g.nodes += prob[k].N;
-            g.tiles += (prob[k].N + kAdjTile - 1) / kAdjTile;
-            g.ftiles += (prob[k].N + adj_fused_tile(g.n) - 1) / adj_fused_tile(g.n);
-        }
-        // tile tables are searched from the group's first tile
-        for (int q = g.first; q < g.first + g.cnt; ++q) ttab[q].item_begin -= tile_base;
-        groups.push_back(g);
-        tile_base += g.tiles;
-    }
     char* base = (char*)d_scratch;
-    // the build-table region holds two tables per instance: node table, then fused-tile table
-    std::vector<DevProb> nftab(ntab);
-    nftab.insert(nftab.end(), ftab.begin(), ftab.end());
-    if ((rc = upload(nftab, ttab, base + L.build_tab, base + L.apply_tab, s))) return rc;
-    const DevProb* dn = (const DevProb*)(base + L.build_tab);
-    const DevProb* df = dn + ntab.size();
-    const DevProb* dtt = (const DevProb*)(base + L.apply_tab);
-    // optional profiling: events around each group's Frechet kernel and around the whole step
-    Timer timer;
-    timer.on = t_profile_adjoint.load() != 0;
-    HIP_TRY(timer.reserve(groups.size(), 1));
-    HIP_TRY(timer.mark(false, s, true));
-    int64_t part_base = 0;
-    for (auto& g : groups) {
-        AdjointLaunch a;
-        a.n = g.n;
-        a.p = g.p;
-        a.node_probs = dn + g.first;
-        a.tile_probs = dtt + g.first;
-        a.nprob = g.cnt;
-        a.tiles = g.tiles;
-        a.nodes = g.nodes;
-        a.fd = fd;
-        a.u = d_u_k;
-        a.lam = d_lambda_next;
-        a.lam_out = d_lambda_k;
-        a.grad = d_grad;
-        a.g = (double*)(base + L.g);
-        a.ghat = (double*)(base + L.ghat);
-        a.ws = (double*)(base + L.ws);
-        a.ws_stride = L.ws_stride;
-        a.dparam = (double*)(base + L.dparam);
-        a.part = (double*)(base + L.part) + 3 * part_base;
-        a.taylor = g.taylor ? tay : nullptr;
-        if (g.fused) {
-            a.fused_probs = df + g.first;
-            a.fused_tiles = g.ftiles;
-        }
-        if (timer.on) {
-            a.frechet_begin = timer.build[timer.nb].first;
-            a.frechet_end = timer.build[timer.nb].second;
-            ++timer.nb;
-        }
-        HIP_TRY(launch_adjoint(a, s));
-        part_base += g.fused ? g.ftiles : g.tiles;
+    if ((rc = upload_pieces(adj_pieces(P), base, s, false))) return rc;
+    return run_adjoint(P, base, d_u_k, d_lambda_next, d_lambda_k, d_grad, s);
+}
+
+int lmep_plan_create(lmep_plan* plan, const lmep_problem* prob, int32_t count, int32_t op, uint32_t flags,
+                     const int32_t* options, int32_t n_options, void* d_scratch, size_t scratch_bytes,
+                     void* hip_stream) {
+    if (!plan) return fail(LMEP_ERR_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (op != 1 && op != 2) return fail(LMEP_ERR_ARG, "plans cover op 1 (lmep_step) and 2 (lmep_adjoint_step)");
+    if (n_options < 0 || (n_options > 0 && !options)) return fail(LMEP_ERR_ARG, "bad option list");
+    Opts o = process_opts();
+    for (int k = 0; k < n_options; ++k) {
+        int rc = set_opt(o, options[2 * k], options[2 * k + 1]);
+        if (rc) return rc;
     }
-    HIP_TRY(timer.mark(false, s, false));
-    if (timer.on) {
-        HIP_TRY(hipStreamSynchronize(s));
-        double fms = 0.0;
-        for (size_t k = 0; k < timer.nb; ++k) {
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, timer.build[k].first, timer.build[k].second));
-            fms += ms;
-        }
-        float all = 0.f;
-        HIP_TRY(hipEventElapsedTime(&all, timer.apply[0].first, timer.apply[0].second));
-        t_prof_build_ms = fms;
-        t_prof_build_n = (int32_t)timer.nb;
-        t_prof_apply_ms = (double)all - fms;
-        t_prof_apply_n = 1;
+    if (op == 1 && (flags & ~LMEP_F_PERSISTENT))
+        return fail(LMEP_ERR_ARG, "a step plan takes LMEP_F_PERSISTENT or 0 at creation, got 0x%x", flags);
+    if (op == 2 && flags) return fail(LMEP_ERR_ARG, "an adjoint plan takes no flags, got 0x%x", flags);
+    lmep_plan_s* P = new (std::nothrow) lmep_plan_s;
+    if (!P) return fail(LMEP_ERR_ARG, "out of host memory");
+    P->op = op;
+    int rc = op == 1 ? make_step_plan(P->step, prob, count, (flags & LMEP_F_PERSISTENT) != 0, o)
+                     : make_adj_plan(P->adj, prob, count, o);
+    const size_t need = op == 1 ? P->step.L.total : P->adj.L.total;
+    if (!rc) rc = entry_checks(d_scratch, scratch_bytes, need);
+    const double* fd = nullptr;
+    hipError_t e = hipSuccess;
+    if (!rc && (e = fd_table_init(&fd)) != hipSuccess) rc = fail(LMEP_ERR_DEVICE, "stencil table: %s", hipGetErrorString(e));
+    hipStream_t s = (hipStream_t)hip_stream;
+    P->base = (char*)d_scratch;
+    P->created_on = s;
+    if (!rc) rc = upload_pieces(op == 1 ? step_pieces(P->step) : adj_pieces(P->adj), P->base, s, false);
+    if (!rc && (e = hipEventCreateWithFlags(&P->ready, hipEventDisableTiming)) != hipSuccess)
+        rc = fail(LMEP_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    if (!rc && (e = hipEventRecord(P->ready, s)) != hipSuccess)
+        rc = fail(LMEP_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    if (!rc && (e = hipEventCreateWithFlags(&P->last, hipEventDisableTiming)) != hipSuccess)
+        rc = fail(LMEP_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    if (rc) {
+        if (P->ready) (void)hipEventDestroy(P->ready);
+        if (P->last) (void)hipEventDestroy(P->last);
+        delete P;
+        return rc;
     }
+    *plan = P;
     return LMEP_OK;
+}
+
+int lmep_plan_step(lmep_plan plan, double* d_w, const double* d_u_in, double* d_u_out, int32_t n_steps,
+                   uint32_t flags, void* hip_stream) {
+    if (!plan || plan->op != 1) return fail(LMEP_ERR_ARG, "not a step plan");
+    const StepPlan& P = plan->step;
+    int rc = check_step_call(d_w, d_u_in, d_u_out, n_steps, flags, P.ext);
+    if (rc) return rc;
+    if (((flags & LMEP_F_PERSISTENT) != 0) != P.multi)
+        return fail(LMEP_ERR_ARG, "LMEP_F_PERSISTENT must be given exactly when the plan was made with it");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "earlier device error: %s", hipGetErrorString(e));
+    hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = plan_order(plan, s))) return rc;
+    rc = run_step(P, plan->base, d_w, d_u_in, d_u_out, n_steps, flags, s, &plan->graphs);
+    if (!rc && (flags & LMEP_F_GRAPH)) {
+        HIP_TRY(hipEventRecord(plan->last, s));
+        plan->launched_graph = true;
+    }
+    return rc;
+}
+
+int lmep_plan_adjoint_step(lmep_plan plan, const double* d_u_k, const double* d_lambda_next, double* d_lambda_k,
+                           double* d_grad, void* hip_stream) {
+    if (!plan || plan->op != 2) return fail(LMEP_ERR_ARG, "not an adjoint plan");
+    int rc = check_adj_call(d_u_k, d_lambda_next, d_lambda_k, d_grad, plan->adj.ext);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "earlier device error: %s", hipGetErrorString(e));
+    hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = plan_order(plan, s))) return rc;
+    return run_adjoint(plan->adj, plan->base, d_u_k, d_lambda_next, d_lambda_k, d_grad, s);
+}
+
+int lmep_plan_destroy(lmep_plan plan) {
+    if (!plan) return LMEP_OK;
+    int rc = LMEP_OK;
+    // graph executions still in flight finish before their graphs go
+    if (plan->launched_graph && hipEventSynchronize(plan->last) != hipSuccess)
+        rc = fail(LMEP_ERR_DEVICE, "waiting for the plan's last graph launch failed");
+    plan->graphs.clear();
+    if (plan->ready) (void)hipEventDestroy(plan->ready);
+    if (plan->last) (void)hipEventDestroy(plan->last);
+    delete plan;
+    return rc;
 }
 
 }  // extern "C"
