@@ -123,11 +123,14 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
     }
     __syncthreads();
 
-    double Wc[PP + 1][NN];  // centre-row weights of each kind
+    // centre-row weights of each kind, read from global memory at a
+    // block-uniform address, so they live in scalar registers and leave the
+    // vector registers to the windows
+    double Wc[PP + 1][NN];
 #pragma unroll
     for (int kd = 0; kd <= PP; ++kd)
 #pragma unroll
-        for (int k = 0; k < NN; ++k) Wc[kd][k] = sw[(kd * NN + R) * NN + k];
+        for (int k = 0; k < NN; ++k) Wc[kd][k] = w[P.weight_off + (kd * NN + R) * NN + k];
     double D1c[S::DERIV ? NN : 1];
     if constexpr (S::DERIV) {
 #pragma unroll
@@ -320,8 +323,10 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
         stage_a(cur, snu, sa);
         edge_a(cur, snu, sa);
         __syncthreads();
-        reflect(sa);
-        __syncthreads();
+        if (neu) {  // block-uniform: only blocks that reach a Neumann end mirror
+            reflect(sa);
+            __syncthreads();
+        }
         if constexpr (S::RK2N) {
             if constexpr (S::DERIV) {
                 deriv_N(sa, sna);
@@ -332,8 +337,10 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
             stage_b(cur, snu, sa, sna, nxt);
             edge_b(cur, snu, sa, sna, nxt);
             __syncthreads();
-            reflect(nxt);
-            __syncthreads();
+            if (neu) {
+                reflect(nxt);
+                __syncthreads();
+            }
             if constexpr (!S::DERIV) {
                 double* t = cur;
                 cur = nxt;
