@@ -501,8 +501,9 @@ def kernel_rooflines(batch, w, u, steps, flags, problems, workload):
     dom = dict(rows[0]) if rows else {}
     if dom:
         dom["traffic"] = measured_traffic([dom["kernel"]], workload)
-        dom["duration_from"] = ("HIP events recorded around each launch of this kernel on the library's stream, "
-                                "profiled pass over the timed steps")
+        dom["duration_from"] = ("HIP events on the library's stream around each launch of this kernel (one pair "
+                                "around all of them when a step runs this kernel alone), profiled pass over the "
+                                "timed steps")
     return dom, rows
 
 
@@ -544,7 +545,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed steps of the headline workload")
-    ap.add_argument("--warmup", type=int, default=40, help="untimed steps first (brings the clocks up)")
+    ap.add_argument("--warmup", type=int, default=200, help="untimed steps first (brings the clocks up)")
     ap.add_argument("--workload", default="allen_cahn_batch")
     ap.add_argument("--graph", action="store_true", help="replay the step loop from a hipGraph (cached by the plan)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

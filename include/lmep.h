@@ -277,8 +277,10 @@ int lmep_profile_last(double* build_ms, int32_t* build_launches, double* apply_m
  * kernel's name as a kernel trace shows it without namespace and argument
  * list (e.g. "stepk_kernel<11,1,3,8>", truncated to name_len - 1
  * characters), its time summed over its launches in milliseconds (HIP events
- * recorded around each launch on the call's stream) and its number of
- * launches.  For k outside [0, K) it writes nothing.  Any pointer may be NULL. */
+ * recorded on the call's stream around each launch, or, when every step of
+ * the call runs a single kernel, one pair around the whole run of its
+ * back-to-back launches) and its number of launches.  For k outside [0, K)
+ * it writes nothing.  Any pointer may be NULL. */
 int32_t lmep_profile_kernel(int32_t k, char* name, size_t name_len, double* ms, int32_t* launches);
 
 /* Thread-local description of the last non-OK status. */

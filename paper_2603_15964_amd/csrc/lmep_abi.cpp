@@ -534,6 +534,7 @@ struct Timer {
     struct Span {
         int kernel;    // index into names
         bool build;    // weight-build (or fused build + step) launch, else apply
+        int launches = 1;  // back-to-back launches of the kernel the span covers
         hipEvent_t a = nullptr, b = nullptr;
     };
     std::vector<std::string> names;
@@ -575,8 +576,9 @@ struct Timer {
         e = hipEventRecord(sp.a, s);
         return (int)used++;
     }
-    hipError_t end(int idx, hipStream_t s) {
+    hipError_t end(int idx, hipStream_t s, int launches = 1) {
         if (!on || idx < 0) return hipSuccess;
+        spans[idx].launches = launches;
         return hipEventRecord(spans[idx].b, s);
     }
     // waits for the events; totals into the thread's profile records
@@ -591,13 +593,13 @@ struct Timer {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, spans[k].a, spans[k].b));
             per[spans[k].kernel].ms += ms;
-            per[spans[k].kernel].launches += 1;
+            per[spans[k].kernel].launches += spans[k].launches;
             if (spans[k].build) {
                 bms += ms;
-                ++bn;
+                bn += spans[k].launches;
             } else {
                 ams += ms;
-                ++an;
+                an += spans[k].launches;
             }
         }
         t_prof_build_ms = bms;
@@ -691,6 +693,13 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
     const int launches = step_launches(P, n_steps);
     const int kb = P.kb;
     hipError_t e = hipSuccess;
+    // When a step runs a single kernel, its launches follow each other with
+    // nothing between them: one pair of events spans them all (events around
+    // each launch would add their own cost to short kernels).
+    int per_round = (int)P.bgroups.size();
+    for (auto& gr : P.agroups) per_round += !(gr.frozen && P.fuse);
+    const bool one_span = per_round == 1;
+    int span = -1;
     // destinations alternate between the scratch state and d_u_out so that
     // the last step lands in d_u_out and no step works in place
     for (int st = 0; st < launches; ++st) {
@@ -699,8 +708,12 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
         // frozen-velocity groups: weights rebuilt, and with fusion applied in
         // the same kernel (their apply groups are then skipped)
         for (auto& gr : P.bgroups) {
-            const int t = timer.on ? timer.begin(build_kernel_name(gr, P.fuse, P.multi, kb), true, s, e) : -1;
-            HIP_TRY(e);
+            int t = -1;
+            if (timer.on && (!one_span || st == 0)) {
+                t = timer.begin(build_kernel_name(gr, P.fuse, P.multi, kb), true, s, e);
+                HIP_TRY(e);
+                if (one_span) span = t;
+            }
             if (gr.taylor && P.multi)
                 HIP_TRY(launch_taylor_stepk(gr.n, kb, std::min(kb, n_steps - st * kb), gr.reg, dbt + gr.first,
                                             gr.count, gr.items, fd, tay, src, dst, counters, s));
@@ -710,14 +723,18 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
             else
                 HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters, s,
                                      P.fuse ? dst : nullptr));
-            HIP_TRY(timer.end(t, s));
+            if (!one_span) HIP_TRY(timer.end(t, s));
         }
         int64_t tile0 = 0;
         for (auto& gr : P.agroups) {
             const bool fused = gr.frozen && P.fuse;  // already advanced by its build kernel
             if (!fused) {
-                const int t = timer.on ? timer.begin(apply_kernel_name(gr, kb), false, s, e) : -1;
-                HIP_TRY(e);
+                int t = -1;
+                if (timer.on && (!one_span || st == 0)) {
+                    t = timer.begin(apply_kernel_name(gr, kb), false, s, e);
+                    HIP_TRY(e);
+                    if (one_span) span = t;
+                }
                 if (gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
                                          dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
@@ -734,11 +751,12 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
                 else
                     HIP_TRY(launch_apply(gr.n, gr.tile, gr.scheme, gr.nonlin, gr.pernode, dat + gr.first,
                                          dti + tile0, gr.items, fd, d_w, src, dst, s));
-                HIP_TRY(timer.end(t, s));
+                if (!one_span) HIP_TRY(timer.end(t, s));
             }
             tile0 += gr.items;
         }
     }
+    if (one_span) HIP_TRY(timer.end(span, s, launches));
     return LMEP_OK;
 }
 

@@ -174,3 +174,21 @@ def test_profiled_call_names_its_kernels():
         assert n == 3 and ms > 0.0, name
     prof = lmep.lmep_profile_last()
     assert prof["build_launches"] == 3 and prof["apply_launches"] == 6
+
+
+def test_single_kernel_steps_share_one_event_span():
+    """A step that runs one kernel: one pair of events spans its back-to-back
+    launches, reported with their count."""
+    _case("one event span")
+    p, u0 = workloads.burgers(N=4000, n=7)
+    b = lmep.Batch([p], device=DEV)
+    w = b.empty_weights()
+    u = b.pack(u0)
+    ref = b.step(w, u, 20, lmep.LMEP_F_PERSISTENT)
+    got = b.step(w, u, 20, lmep.LMEP_F_PERSISTENT | lmep.LMEP_F_PROFILE)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, got)
+    ks = lmep.lmep_profile_kernels()
+    kb = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    assert len(ks) == 1 and ks[0][0] == "taylor_stepk_kernel<7>"
+    assert ks[0][2] == -(-20 // kb) and ks[0][1] > 0.0
