@@ -465,7 +465,7 @@ def kernel_work(name, problems, steps):
                 per += p["N"] * 16.0
         return "hbm", per * steps, "byte"
     if base == "resident_kernel":
-        g = group(lambda p: p["n"] == v[0] and p.get("x") is not None)
+        g = group(lambda p: p["n"] == v[0] and SCHEME_ID[p["scheme"]] == v[1] and (p.get("x") is None) == v[3])
 
         def lds_reads(p):
             has_n = p["scheme"] != "linear" and p.get("nonlin", "none") != "none"

@@ -105,7 +105,10 @@ enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
                                   /* LMEP_ERR_UNSUPPORTED.  Non-uniform instances of at         */
                                   /* most 512 nodes are held whole by one block each (weights   */
                                   /* in registers) for all n_steps (launches of up to 65536     */
-                                  /* steps); larger ones are LMEP_ERR_UNSUPPORTED.              */
+                                  /* steps); larger ones are LMEP_ERR_UNSUPPORTED.  So are      */
+                                  /* uniform stationary instances with a pointwise or no        */
+                                  /* nonlinearity (not ETDRK4) when every instance of their     */
+                                  /* kernel group has at most 512 nodes.                        */
 #define LMEP_F_CHECK_FINITE 0x4u  /* scan the result; LMEP_ERR_NONFINITE if any entry is not    */
                                   /* finite (synchronises the stream)                            */
 #define LMEP_F_PROFILE      0x8u  /* time the weight-build and apply kernels with HIP events    */

@@ -396,9 +396,14 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         g.nonuniform = std::get<3>(kv.first) == 2;
         g.first = (int)tab.size();
         for (int k : kv.second) g.nodes += prob[k].N;
-        g.stepk = !g.nonuniform && (multi_kb > 0 || g.scheme == LMEP_ETDRK4);
-        g.resident = g.nonuniform && multi_kb > 0;
         for (int k : kv.second) g.max_nodes = std::max(g.max_nodes, prob[k].N);
+        // several steps per launch: whole small instances per block (non-uniform
+        // grids always; uniform ones with a stationary table, a pointwise or no
+        // nonlinearity and at most kResidentMaxN nodes), else the tiled kernel
+        const bool small_uniform = !g.pernode && g.max_nodes <= kResidentMaxN && g.scheme != LMEP_ETDRK4 &&
+                                   (g.nonlin == LMEP_NL_NONE || g.nonlin == LMEP_NL_ALLEN_CAHN);
+        g.resident = multi_kb > 0 && (g.nonuniform || small_uniform);
+        g.stepk = !g.resident && !g.nonuniform && (multi_kb > 0 || g.scheme == LMEP_ETDRK4);
         const int64_t avg = g.nodes / (int64_t)kv.second.size();
         const int forced = o.apply_tile;  // 0, 64 (non-uniform groups only), 256 or 1024
         g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb > 0 ? multi_kb : 1)
@@ -440,7 +445,8 @@ std::string apply_kernel_name(const Group& g, int kb) {
     const int nl = g.scheme == LMEP_LINEAR ? 0 : g.nonlin;
     if (g.stepk && g.scheme == LMEP_ETDRK4) snprintf(b, sizeof(b), "stepk_rk4_kernel<%d,%d,%d>", g.n, g.nonlin, kb);
     else if (g.stepk) snprintf(b, sizeof(b), "stepk_kernel<%d,%d,%d,%d>", g.n, g.scheme, nl, kb);
-    else if (g.resident) snprintf(b, sizeof(b), "resident_kernel<%d,%d,%d>", g.n, g.scheme, nl);
+    else if (g.resident)
+        snprintf(b, sizeof(b), "resident_kernel<%d,%d,%d,%s>", g.n, g.scheme, nl, bool_s(!g.nonuniform).c_str());
     else snprintf(b, sizeof(b), "apply_kernel<%d,%d,%d,%s,%d>", g.n, g.scheme, nl, bool_s(g.pernode).c_str(), g.tile);
     return b;
 }
@@ -742,7 +748,8 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
                     // in place after the first chunk: a block reads its whole
                     // instance before it writes any of it
                     for (int done = 0; st == 0 && done < n_steps; done += kResidentMaxSteps)
-                        HIP_TRY(launch_resident(gr.n, gr.scheme, gr.nonlin, dat + gr.first, gr.count, gr.max_nodes,
+                        HIP_TRY(launch_resident(gr.n, gr.scheme, gr.nonlin, !gr.nonuniform, dat + gr.first, gr.count,
+                                                gr.max_nodes,
                                                 d_w, done == 0 ? d_u_in : d_u_out, d_u_out,
                                                 std::min(kResidentMaxSteps, n_steps - done), s));
                 } else if (gr.nonuniform)

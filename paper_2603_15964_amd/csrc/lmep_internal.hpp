@@ -114,11 +114,14 @@ size_t build_wide_lds_bytes(int n, int p);
 hipError_t launch_apply(int n, int tile, int scheme, int nonlin, bool pernode, const DevProb* d_probs,
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
                         const double* d_u_in, double* d_u_out, hipStream_t stream);
-// Several steps per launch for non-uniform instances of at most kResidentMaxN
-// nodes: one block per instance, the whole instance in the block (resident.hip).
-// max_nodes = the group's largest N.
-hipError_t launch_resident(int n, int scheme, int nonlin, const DevProb* d_probs, int count, int64_t max_nodes,
-                           const double* d_w, const double* d_u_in, double* d_u_out, int ksteps, hipStream_t stream);
+// Several steps per launch for instances of at most kResidentMaxN nodes: one
+// block per instance, the whole instance in the block (resident.hip).
+// uniform: stationary table weights on a uniform grid (any boundary, pointwise
+// or no nonlinearity, n <= kMaxN), else per-node weights of a non-uniform grid
+// (Dirichlet).  max_nodes = the group's largest N.
+hipError_t launch_resident(int n, int scheme, int nonlin, bool uniform, const DevProb* d_probs, int count,
+                           int64_t max_nodes, const double* d_w, const double* d_u_in, double* d_u_out, int ksteps,
+                           hipStream_t stream);
 
 // The same for non-uniform grids (stationary per-node weights, n <= kMaxNWide,
 // nonlinearity none or Allen-Cahn).
