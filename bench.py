@@ -162,7 +162,7 @@ def make_workload(name: str):
         return ps, us, "4096 Allen-Cahn instances N_k in [512,65536], n_k in {5,7,9,11}, ETD1, stationary weights"
     if name == "burgers_etdrk4":
         p, u0 = workloads.burgers_etdrk4()
-        return [p], [u0], ("the paper's Burgers run: periodic N=1048576 n=13, nu=0.03, stationary L = nu D2, "
+        return [p], [u0], ("the paper's Burgers run: periodic N=1048576 n=19, nu=0.03, stationary L = nu D2, "
                            "N = -u u_x, ETDRK4")
     if name == "burgers_upwind":
         p, u0 = workloads.burgers_upwind()

@@ -1,7 +1,10 @@
 // Weight build on non-uniform grids (steps a2-a6 with per-node stencils,
 // Sec. 4.3.3): every node has its own local operator, built from the
 // differentiation matrices of its own window's coordinates, and its own
-// exponential, harvested once (the weights are stationary).
+// exponential, harvested once (the weights are stationary).  The same kernel
+// builds the stationary table of a uniform instance whose augmented matrix
+// is too large for a 16-lane DPP row (ETDRK4 with n + 3 > 16): one matrix per
+// harvested row r, on the window x_a = (a - r) h, written as [kind][r][k].
 //
 // Per node:
 //   * coordinates of the window relative to the node, xs_a = x_{i+o+a} - x_i;
@@ -24,7 +27,8 @@
 //     of B, the uniform build's rule), with the linear solve done by
 //     Gauss-Jordan elimination with partial pivoting;
 //   * columns r, n, n+1 of exp(Mt) -> W0, W1, W2 of the node, stored per node
-//     ([kind][k][node]).
+//     ([kind][k][node]); for an ETDRK4 table also column n+2 (dt^3 phi3), and
+//     the rows e^{L dt}, dt alpha, dt beta, dt gamma of Sec. 3 from them.
 //
 // Orders up to 32 (stencils up to 25 points) do not fit the 16-lane DPP rows
 // of the uniform build, and these weights are built once, so the layout here
@@ -65,8 +69,9 @@ __global__ __launch_bounds__(kWaveThreads) void build_wide_kernel(const DevProb*
     const int lane = threadIdx.x;
     const int64_t item = blockIdx.x;  // one node per block
     const DevProb& P = probs[find_instance(probs, nprob, item)];
-    const int64_t node = item - P.item_begin;
+    const int64_t node = item - P.item_begin;  // node, or harvested row of a uniform table
     const int64_t N = P.N;
+    const bool uni = P.x == nullptr;
     const int n = P.n, m = n + P.p, ld = m + 1, sz = m * ld;
     double* A = lds;
     double* A2 = A + sz;
@@ -81,10 +86,10 @@ __global__ __launch_bounds__(kWaveThreads) void build_wide_kernel(const DevProb*
     double* dsc = red + m;  // balancing scale factors
     int* piv = (int*)(dsc + m);
 
-    const int64_t o = window_offset(node, N, n, P.bc);
+    const int64_t o = uni ? -node : window_offset(node, N, n, P.bc);
     const int r = (int)(-o);
     const double* __restrict__ x = P.x;
-    if (lane < n) xs[lane] = x[node + o + lane] - x[node];
+    if (lane < n) xs[lane] = uni ? (double)(lane - r) * P.h : x[node + o + lane] - x[node];
     __syncthreads();
     if (lane < n) {
         double pr = 1.0;
@@ -255,9 +260,25 @@ __global__ __launch_bounds__(kWaveThreads) void build_wide_kernel(const DevProb*
     if (lane < n) {
         double* __restrict__ wb = w + P.weight_off;
         const double dk = dsc[lane];
-        wb[(int64_t)lane * N + node] = dk * X[lane * ld + r] / dsc[r];
-        if (P.p >= 1) wb[(int64_t)(n + lane) * N + node] = dk * X[lane * ld + n] / dsc[n];
-        if (P.p >= 2) wb[(int64_t)(2 * n + lane) * N + node] = dk * X[lane * ld + n + 1] / dsc[n + 1] / dt;
+        const double w0 = dk * X[lane * ld + r] / dsc[r];
+        const double w1 = P.p >= 1 ? dk * X[lane * ld + n] / dsc[n] : 0.0;          // row of dt phi1
+        const double w2 = P.p >= 2 ? dk * X[lane * ld + n + 1] / dsc[n + 1] : 0.0;  // dt^2 phi2
+        const double w3 = P.p >= 3 ? dk * X[lane * ld + n + 2] / dsc[n + 2] : 0.0;  // dt^3 phi3
+        if (!uni) {
+            wb[(int64_t)lane * N + node] = w0;
+            if (P.p >= 1) wb[(int64_t)(n + lane) * N + node] = w1;
+            if (P.p >= 2) wb[(int64_t)(2 * n + lane) * N + node] = w2 / dt;
+        } else if (P.harvest == HARVEST_RK4_FULL) {
+            const double f1 = w1, f2 = w2 / dt, f3 = w3 / (dt * dt);
+            wb[(2 * n + r) * n + lane] = w0;
+            wb[(3 * n + r) * n + lane] = f1 - 3.0 * f2 + 4.0 * f3;
+            wb[(4 * n + r) * n + lane] = 2.0 * f2 - 4.0 * f3;
+            wb[(5 * n + r) * n + lane] = 4.0 * f3 - f2;
+        } else {  // plain rows, or the ETDRK4 half step (kinds 0, 1)
+            wb[r * n + lane] = w0;
+            if (P.p >= 1) wb[(n + r) * n + lane] = w1;
+            if (P.p >= 2) wb[(2 * n + r) * n + lane] = w2 / dt;
+        }
     }
 }
 
@@ -271,7 +292,7 @@ size_t build_wide_lds_bytes(int n, int p) {
 hipError_t launch_build_wide(int n, int p, const DevProb* d_probs, int nprob, int64_t items, double* d_w,
                              hipStream_t stream) {
     if (items <= 0) return hipSuccess;
-    if (n < 3 || n > kMaxNWide || (n % 2) == 0 || p < 0 || p > 2 || n + p > kMaxMWide) return hipErrorInvalidValue;
+    if (n < 3 || n > kMaxNWide || (n % 2) == 0 || p < 0 || p > 3 || n + p > kMaxMWide) return hipErrorInvalidValue;
     hipLaunchKernelGGL(build_wide_kernel, dim3((unsigned)items), dim3(kWaveThreads), build_wide_lds_bytes(n, p),
                        stream, d_probs, nprob, d_w);
     return hipGetLastError();

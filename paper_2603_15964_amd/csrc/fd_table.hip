@@ -51,13 +51,13 @@ __device__ void fornberg_weights(int n, double z, const double* x, double (*c)[M
 // One thread per (stencil size, evaluation node a).
 __global__ void fd_table_kernel(double* __restrict__ tab) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= kNumN * kMaxN) return;
-    const int n = 3 + 2 * (t / kMaxN);
-    const int a = t % kMaxN;
+    if (t >= kNumFd * kFdMaxN) return;
+    const int n = 3 + 2 * (t / kFdMaxN);
+    const int a = t % kFdMaxN;
     if (a >= n) return;
-    double x[kMaxN];
+    double x[kFdMaxN];
     for (int k = 0; k < n; ++k) x[k] = (double)k - 0.5 * (double)(n - 1);
-    double c[kMaxN][4];
+    double c[kFdMaxN][4];
     fornberg_weights<3>(n, x[a], x, c);
     for (int d = 0; d < kFdDerivs; ++d)
         for (int k = 0; k < n; ++k) tab[fd_index(n, d, a, k)] = c[k][d + 1];
@@ -98,7 +98,7 @@ hipError_t fd_table_init(const double** d_table_out) {
     if (!g_ptr[dev]) {
         void* p = nullptr;
         if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_fd_table))) != hipSuccess) return e;
-        hipLaunchKernelGGL(fd_table_kernel, dim3(1), dim3(kNumN * kMaxN), 0, nullptr, (double*)p);
+        hipLaunchKernelGGL(fd_table_kernel, dim3(1), dim3(kNumFd * kFdMaxN), 0, nullptr, (double*)p);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
         g_ptr[dev] = (const double*)p;

@@ -135,7 +135,7 @@ bool finite(double x) { return std::isfinite(x); }
 // Checks of one instance (ERR_ARG for malformed input, ERR_UNSUPPORTED for a
 // well-formed combination the kernels do not implement).
 int check_problem(const lmep_problem& q, int k) {
-    const int nmax = nonuniform(q) ? kMaxNWide : kMaxN;
+    const int nmax = nonuniform(q) ? kMaxNWide : (q.scheme == LMEP_ETDRK4 && !frozen(q) ? kMaxNRk4 : kMaxN);
     if (q.n < 3 || q.n > nmax || (q.n % 2) == 0)
         return fail(LMEP_ERR_ARG, "instance %d: stencil size n=%d must be odd, 3..%d", k, q.n, nmax);
     if (q.N < q.n) return fail(LMEP_ERR_ARG, "instance %d: N=%lld < n=%d", k, (long long)q.N, q.n);
@@ -150,9 +150,11 @@ int check_problem(const lmep_problem& q, int k) {
     if (q.scheme == LMEP_LINEAR && q.nonlin != LMEP_NL_NONE)
         return fail(LMEP_ERR_ARG, "instance %d: LINEAR scheme with a nonlinear term", k);
     if (q.state_off < 0 || q.weight_off < 0) return fail(LMEP_ERR_ARG, "instance %d: negative offset", k);
-    if (q.n + scheme_p(q.scheme) > (nonuniform(q) ? kMaxMWide : kMaxM))
-        return fail(LMEP_ERR_UNSUPPORTED, "instance %d: n + p = %d exceeds %d", k, q.n + scheme_p(q.scheme),
-                    nonuniform(q) ? kMaxMWide : kMaxM);
+    // the order of the augmented matrix: a DPP row (16) on uniform grids, the
+    // LDS build (32) on non-uniform ones and for uniform ETDRK4 tables
+    const int mmax = (nonuniform(q) || q.scheme == LMEP_ETDRK4) ? kMaxMWide : kMaxM;
+    if (q.n + scheme_p(q.scheme) > mmax)
+        return fail(LMEP_ERR_UNSUPPORTED, "instance %d: n + p = %d exceeds %d", k, q.n + scheme_p(q.scheme), mmax);
     if (frozen(q) && q.scheme != LMEP_ETD1)
         return fail(LMEP_ERR_UNSUPPORTED, "instance %d: frozen-velocity Burgers needs ETD1", k);
     if (q.window != LMEP_WIN_CENTRED && q.window != LMEP_WIN_UPWIND)
@@ -293,7 +295,8 @@ struct Group {
     bool taylor = false;     // build by finite Taylor series (items = kTaylorTile-node tiles)
     bool pernode = false;    // weights stored per node (frozen velocity or non-uniform grid)
     bool frozen = false;     // rebuilt every step (frozen velocity)
-    bool nonuniform = false; // non-uniform grid: wide build, per-node stationary weights
+    bool nonuniform = false; // non-uniform grid: per-node stationary weights
+    bool wide = false;       // build groups: the LDS build (non-uniform grids, orders beyond a DPP row)
     bool resident = false;   // non-uniform, several steps per launch, one block per instance
     int64_t max_nodes = 0;
     bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
@@ -325,16 +328,20 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
     struct Part {
         int k, harvest;
     };
-    // (n, p, kind): kind 0 Pade on a uniform grid, 1 non-uniform grid, 2 finite Taylor
+    // (n, p, kind): kind 0 Pade in DPP rows, 1 the LDS build, 2 finite Taylor
     std::map<std::tuple<int, int, int>, std::vector<Part>> by;
+    // the LDS build for non-uniform grids and for orders beyond a DPP row
+    auto kind_of = [&](const lmep_problem& q, int p) {
+        return (nonuniform(q) || q.n + p > kMaxM) ? 1 : (taylor(q, o) ? 2 : 0);
+    };
     for (int k = 0; k < count; ++k) {
         if (!want(prob[k])) continue;
-        const int kind = nonuniform(prob[k]) ? 1 : (taylor(prob[k], o) ? 2 : 0);
         if (prob[k].scheme == LMEP_ETDRK4) {
-            by[{prob[k].n, 3, kind}].push_back({k, HARVEST_RK4_FULL});
-            by[{prob[k].n, 1, kind}].push_back({k, HARVEST_RK4_HALF});
+            by[{prob[k].n, 3, kind_of(prob[k], 3)}].push_back({k, HARVEST_RK4_FULL});
+            by[{prob[k].n, 1, kind_of(prob[k], 1)}].push_back({k, HARVEST_RK4_HALF});
         } else {
-            by[{prob[k].n, scheme_p(prob[k].scheme), kind}].push_back({k, HARVEST_PLAIN});
+            const int p = scheme_p(prob[k].scheme);
+            by[{prob[k].n, p, kind_of(prob[k], p)}].push_back({k, HARVEST_PLAIN});
         }
     }
     std::vector<Group> groups;
@@ -342,7 +349,7 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         Group g;
         g.n = std::get<0>(kv.first);
         g.p = std::get<1>(kv.first);
-        g.nonuniform = std::get<2>(kv.first) == 1;
+        g.wide = std::get<2>(kv.first) == 1;
         g.taylor = std::get<2>(kv.first) == 2;
         for (const Part& part : kv.second) g.nodes += prob[part.k].N;
         if (g.taylor && frozen_kb > 0) {
@@ -433,7 +440,7 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
 std::string bool_s(bool b) { return b ? "true" : "false"; }
 std::string build_kernel_name(const Group& g, bool fused, bool multi, int kb) {
     char b[96];
-    if (g.nonuniform) return "build_wide_kernel";
+    if (g.wide) return "build_wide_kernel";
     if (g.taylor && multi) snprintf(b, sizeof(b), "taylor_stepk_kernel<%d>", g.n);
     else if (g.taylor) snprintf(b, sizeof(b), "build_taylor_kernel<%d,%s>", g.n, bool_s(fused).c_str());
     else snprintf(b, sizeof(b), "build_pade_kernel<%d,%d,%s>", g.n, g.p, bool_s(fused).c_str());
@@ -1202,7 +1209,7 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
     const DevProb* dtab = (const DevProb*)(base + L.build_tab);
     for (auto& g : groups) {
         if (g.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
-        if (g.nonuniform)
+        if (g.wide)
             HIP_TRY(launch_build_wide(g.n, g.p, dtab + g.first, g.count, g.items, d_w, s));
         else if (g.taylor)
             HIP_TRY(launch_build_taylor(g.n, dtab + g.first, g.count, g.items, fd, tay, d_u, d_w, nullptr, s));

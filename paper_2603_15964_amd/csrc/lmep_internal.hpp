@@ -17,6 +17,9 @@ constexpr int kMaxMWide = 32; // non-uniform grids: largest local matrix (LDS bu
 constexpr int kResidentMaxN = 512;  // non-uniform instances a multi-step block holds whole
 constexpr int kResidentMaxSteps = 1 << 16;  // steps of one such launch (longer runs: several)
 constexpr int kFdDerivs = 3;  // first, second and third derivative tables
+constexpr int kMaxNRk4 = 19;  // uniform grids: ETDRK4 stencils up to 19 points (orders n + 3 <= 22, LDS build)
+constexpr int kFdMaxN = 25;   // the finite-difference table covers stencils 3, 5, ..., 25
+constexpr int kNumFd = (kFdMaxN - 1) / 2;
 
 // Device-side record of one instance, filled by the host from lmep_problem.
 // `item_begin` is the prefix sum of work items (matrices or tiles) over the
@@ -47,10 +50,11 @@ enum : int { WIN_CENTRED = 0, WIN_UPWIND = 1 };
 
 // Table of finite-difference weights on the centred integer stencil
 // x_k = k - (n-1)/2: fd[(n-3)/2][d][a][k] is the weight of node k for the
-// (d+1)-th derivative at node a.  Lives in a static device array per device.
-constexpr int kFdTableDoubles = kNumN * kFdDerivs * kMaxN * kMaxN;
+// (d+1)-th derivative at node a, n = 3, 5, ..., kFdMaxN.  Lives in a static
+// device array per device.
+constexpr int kFdTableDoubles = kNumFd * kFdDerivs * kFdMaxN * kFdMaxN;
 __host__ __device__ inline int fd_index(int n, int d, int a, int k) {
-    return ((((n - 3) / 2) * kFdDerivs + d) * kMaxN + a) * kMaxN + k;
+    return ((((n - 3) / 2) * kFdDerivs + d) * kFdMaxN + a) * kFdMaxN + k;
 }
 
 // Table of the finite-Taylor build: taylor[(n-3)/2][a][k][j] = k-th derivative
@@ -101,8 +105,10 @@ hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb
                                const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
                                unsigned long long* stats, hipStream_t stream);
 
-// Stationary per-node weights of non-uniform grids (one node per wavefront,
-// matrices in LDS; p <= 2, n + p <= kMaxMWide).
+// Stationary weights by the LDS build (one matrix per wavefront, orders up to
+// kMaxMWide): per node on non-uniform grids (p <= 2), and per harvested row of
+// a uniform instance whose order n + p exceeds a DPP row (the stationary table
+// [kind][r][k]; ETDRK4 parts as in launch_build).  items = nodes or rows.
 hipError_t launch_build_wide(int n, int p, const DevProb* d_probs, int nprob, int64_t items, double* d_w,
                              hipStream_t stream);
 size_t build_wide_lds_bytes(int n, int p);

@@ -32,7 +32,7 @@ constexpr int NT = 256;
 constexpr int V = 8;               // positions per thread and pass
 constexpr int LR = kStepRegion;    // staged positions per block
 static_assert(LR == NT * V, "one pass per thread covers the region");
-constexpr int MARGIN = 8;          // unused slots before and after the region (>= R)
+constexpr int MARGIN = 16;         // unused slots before and after the region (>= R)
 constexpr int LP = (LR + 2 * MARGIN) + (LR + 2 * MARGIN) / 8;  // padded length of one array
 
 // LDS slot of region position q, -MARGIN <= q < LR + MARGIN.

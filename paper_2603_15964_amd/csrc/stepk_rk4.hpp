@@ -30,7 +30,7 @@ struct ShapeRK4 {
     static constexpr int HALO = stepk_halo(NN, SCH_ETDRK4, NL, KB);
     static constexpr int TILE = stepk_tile(NN, SCH_ETDRK4, NL, KB);
     static constexpr int NBUF = !HAS_N ? 2 : (DERIV ? 6 : 4);
-    static_assert(NN + 3 <= kMaxM, "ETDRK4 needs n + 3 <= 16");
+    static_assert(NN <= kMaxNRk4, "ETDRK4 stencils up to kMaxNRk4 points");
     static_assert(R <= MARGIN && TILE > 0, "shape");
 };
 
@@ -327,7 +327,7 @@ hipError_t go_rk4(const DevProb* p, const int* ti, int64_t tiles, const double* 
 template <int NN, int KB>
 hipError_t dispatch_rk4(int nonlin, const DevProb* p, const int* ti, int64_t tiles, const double* fd, const double* w,
                         const double* ui, double* uo, int ksteps, hipStream_t s) {
-    if constexpr (NN + 3 > kMaxM) {
+    if constexpr (NN > kMaxNRk4) {
         return hipErrorInvalidValue;
     } else {
         switch (nonlin) {
@@ -349,6 +349,9 @@ hipError_t dispatch_n_rk4(int n, int nonlin, const DevProb* p, const int* ti, in
         case 9: return dispatch_rk4<9, KB>(nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
         case 11: return dispatch_rk4<11, KB>(nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
         case 13: return dispatch_rk4<13, KB>(nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 15: return dispatch_rk4<15, KB>(nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 17: return dispatch_rk4<17, KB>(nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 19: return dispatch_rk4<19, KB>(nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
         default: return hipErrorInvalidValue;
     }
 }

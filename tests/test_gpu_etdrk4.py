@@ -1,5 +1,7 @@
 """GPU parity of ETDRK4 (weights from the (n+3)-order augmented matrix at dt
-and the (n+1)-order one at dt/2; four-stage update) with the CPU oracle.
+and the (n+1)-order one at dt/2 -- in 16-lane DPP rows up to order 16, by the
+LDS build beyond, up to the paper's n = 19 -- four-stage update) with the CPU
+oracle.
 
 Weights: 1e-12 relative per harvested row, all six kinds and every stencil
 row.  States: 1e-10 relative after several steps, for every boundary type and
@@ -48,7 +50,7 @@ def _run(problems, states, steps, kb=None):
     return b.unpack(out)
 
 
-@pytest.mark.parametrize("n", [3, 5, 7, 9, 11, 13])
+@pytest.mark.parametrize("n", [3, 5, 7, 9, 11, 13, 15, 17, 19])
 def test_weights_all_rows(n):
     _case("etdrk4 weights", n)
     p = make_problem(N=n, n=n, bc="dirichlet", h=0.3, dt=0.07, c=0.9, nu=0.04, delta=0.001, react=-0.2,
@@ -90,7 +92,12 @@ CASES = [
     ("no nonlinearity dirichlet n13", lambda: (make_problem(N=2200, n=13, bc="dirichlet", h=0.05, dt=0.01, c=0.7,
                                                             nu=0.02, delta=1e-5, scheme="etdrk4", bc_left=0.2),
                                                np.cos(np.linspace(0, 9, 2200)))),
-    ("paper burgers N1024 n13", lambda: workloads.burgers_etdrk4(N=1024)),
+    ("paper burgers N1024 n13", lambda: workloads.burgers_etdrk4(N=1024, n=13)),
+    ("paper burgers N1024 n19", lambda: workloads.burgers_etdrk4(N=1024, n=19)),
+    ("allen-cahn neumann n17", lambda: _ac(3000, 17, "neumann")),
+    ("kdv periodic n19", lambda: _kdv(2048, 19, "periodic")),
+    ("allen-cahn dirichlet n15", lambda: (dict(_ac(2500, 15, "dirichlet", mu=0.1)[0], bc_left=0.05,
+                                               bc_right=-0.05), _ac(2500, 15, "dirichlet", mu=0.1)[1])),
 ]
 
 
@@ -135,7 +142,7 @@ def test_mixed_batch_with_other_schemes():
 
 
 def test_full_size_paper_burgers():
-    """The throughput configuration (N = 2^20, n = 13, 8 steps per launch):
+    """The throughput configuration (N = 2^20, n = 19, 8 steps per launch):
     16 steps equal the one-step path bit for bit and the oracle to 1e-10."""
     _case("etdrk4 full size")
     p, u0 = workloads.burgers_etdrk4()
@@ -143,3 +150,30 @@ def test_full_size_paper_burgers():
     one = _run([p], [u0], steps)[0]
     assert np.array_equal(_run([p], [u0], steps, kb=8)[0], one)
     assert _rel(one, oracle.run(p, u0, steps)) <= 1e-10
+
+
+def test_fourth_order_at_n19():
+    """The paper's stencil on the GPU: periodic diffusion + Allen-Cahn (N = 64,
+    n = 19) against the semi-discrete system integrated to 1e-13; the errors
+    at T = 1 fall by 2^4 per halving of dt."""
+    from scipy.integrate import solve_ivp
+    _case("etdrk4 order at n = 19")
+    N, n, nu, g, T = 64, 19, 0.02, 1.0, 1.0
+    h = 2 * np.pi / N
+    x = np.arange(N) * h
+    u0 = 0.4 * np.sin(x) + 0.1
+    D = oracle.fd_matrices(n, h)
+    R = (n - 1) // 2
+    A = np.zeros((N, N))
+    for i in range(N):
+        for k in range(n):
+            A[i, (i - R + k) % N] += nu * D[1][R][k]
+    ref = solve_ivp(lambda t, u: A @ u + g * (u - u ** 3), (0, T), u0, method="DOP853", rtol=1e-13,
+                    atol=1e-15).y[:, -1]
+    errs = []
+    for m in (8, 16, 32, 64):
+        p = make_problem(N=N, n=n, bc="periodic", h=h, dt=T / m, nu=nu, scheme="etdrk4", nonlin="allen_cahn",
+                         nl_coef=g)
+        errs.append(np.max(np.abs(_run([p], [u0], m, kb=8)[0] - ref)))
+    slopes = [np.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert all(abs(s - 4.0) <= 0.3 for s in slopes), (errs, slopes)

@@ -147,12 +147,12 @@ def burgers_adjoint_batch(batch: int = 64, N: int = 262144, n: int = 9, nu: floa
 
 
 # ------------------------------------------------- ETDRK4 (next row) ------
-def burgers_etdrk4(N: int = 2 ** 20, n: int = 13, nu: float = 0.03, mu: float = 0.5):
+def burgers_etdrk4(N: int = 2 ** 20, n: int = 19, nu: float = 0.03, mu: float = 0.5):
     """The paper's own Burgers run (Sec. 4.3.1) at a throughput size: periodic
     [-pi, pi), nu = 0.03, u0 = exp(-10 sin^2(x/2)), stationary L = nu D2 and
     N = -u u_x in the conservative form -(1/2) d/dx(u^2) (the KdV-form term with
-    coefficient 1), ETDRK4.  n = 13 is the largest stencil with n + 3 <= 16
-    (the paper uses n = 19); dt = mu h^2 / nu.  Deterministic, no seed."""
+    coefficient 1), ETDRK4 with the paper's n = 19; dt = mu h^2 / nu.
+    Deterministic, no seed."""
     h = 2.0 * math.pi / N
     x = -math.pi + h * np.arange(N)
     u0 = np.exp(-10.0 * np.sin(x / 2.0) ** 2)
