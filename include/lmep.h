@@ -58,7 +58,7 @@ enum { LMEP_BC_PERIODIC = 0, LMEP_BC_DIRICHLET = 1, LMEP_BC_NEUMANN = 2 };
 /* Schemes (Sec. 3): LINEAR u+ = W0 u; ETD1 (ETD-s with s = 1); ETD2RK
  * (Cox-Matthews); ETDRK4 (the four-stage scheme of Sec. 3 with
  * alpha, beta, gamma built from phi1..phi3, stationary weights only,
- * n + 3 <= 16).  p = 0, 1, 2, 3 phi-functions. */
+ * n <= 19 on uniform grids).  p = 0, 1, 2, 3 phi-functions. */
 enum { LMEP_LINEAR = 0, LMEP_ETD1 = 1, LMEP_ETD2RK = 2, LMEP_ETDRK4 = 3 };
 
 /* Nonlinear terms N(u), g = nl_coef:
@@ -121,7 +121,7 @@ enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
  * weights d_w[weight_off, weight_off + lmep_weight_count(&prob[k])). */
 typedef struct {
     int64_t N;          /* grid nodes; N >= n; Neumann also needs N >= (n+1)/2       */
-    int32_t n;          /* stencil size: odd, 3..15; n + p <= 16                      */
+    int32_t n;          /* stencil size: odd, 3..15 with n + p <= 16 (ETDRK4: 3..19)  */
     int32_t bc;         /* LMEP_BC_*                                                  */
     double  h;          /* uniform grid spacing, > 0                                  */
     double  dt;         /* time step, > 0                                             */
