@@ -78,17 +78,20 @@ enum { LMEP_NL_NONE = 0, LMEP_NL_BURGERS_FROZEN = 1, LMEP_NL_KDV = 2, LMEP_NL_AL
  * derivative in the remainder N_j uses node j's own side).  Either way a
  * Dirichlet grid moves the window to the n nearest in-domain nodes.  A
  * one-sided pure-advection update is stable for Courant numbers |a| dt / h in
- * [(n-3)/2, (n+1)/2] (and at the integers, where it is an exact shift); in
- * FP64 its edge-row exponentials lose accuracy as n and the Courant number
- * grow.  Stationary tables are balanced (a power-of-two diagonal similarity)
- * before the exponential: their rows agree with the exact ones to ~1e-12 up
- * to n = 9 (Courant <= 3.5 with diffusion), 5e-11 / 1e-9 / 5e-8 at n = 11 /
- * 13 / 15.
- * Frozen-velocity weights (rebuilt every step) are not balanced: ~1e-12 for
- * n = 7 across its band.  UPWIND is supported for LINEAR,
- * ETD1 and ETD2RK with the one-step kernels, and for BURGERS_FROZEN also
- * under LMEP_F_PERSISTENT; ETDRK4, LMEP_F_PERSISTENT with stationary weights
- * and the reverse step return LMEP_ERR_UNSUPPORTED. */
+ * [(n-3)/2, (n+1)/2] (and at the integers, where it is an exact shift).
+ * Its edge-row exponentials cancel heavily, so stationary one-sided tables
+ * (no reaction term) and frozen-velocity one-sided windows of n >= 9 points
+ * are built by the finite Taylor series in double-double: rows exact to
+ * rounding for n up to 15 across that band.  With a reaction term, or under
+ * LMEP_OPT_EXP_METHOD = LMEP_EXP_PADE, tables are balanced (a power-of-two
+ * diagonal similarity) and built in FP64: ~1e-12 up to n = 9, 5e-11 / 1e-9 /
+ * 5e-8 at n = 11 / 13 / 15.  The frozen-velocity remainder differentiates u
+ * on one-sided windows, whose end rows grow like 2^n / n: for n >= 13 it
+ * amplifies grid-scale perturbations unless the velocity varies little.
+ * UPWIND is supported for LINEAR, ETD1 and ETD2RK with the one-step kernels,
+ * and for BURGERS_FROZEN also under LMEP_F_PERSISTENT; ETDRK4,
+ * LMEP_F_PERSISTENT with stationary weights and the reverse step return
+ * LMEP_ERR_UNSUPPORTED. */
 enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
 
 /* lmep_step flags */

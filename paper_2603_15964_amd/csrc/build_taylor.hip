@@ -42,7 +42,12 @@
 // N_j = -g (u_j - u_i) (du/dx)_j over its window (the factor -g rides on W1
 // with dt), and the weights never leave registers.  Without FUSE the weights
 // are written in the per-node layout.
+//
+// One-sided windows of 9 or more points take the same build in double-double
+// (build_taylor_dd_kernel, taylor_stepk_dd_kernel; the weight routine is in
+// taylor_dd.hpp), and so do stationary one-sided tables (build_table_dd_kernel).
 #include "lmep_device.hpp"
+#include "taylor_dd.hpp"
 
 namespace lmep {
 namespace {
@@ -193,14 +198,13 @@ __device__ __forceinline__ void node_weights(bool active, int r, int sh, bool di
     }
 }
 
-template <int NN, bool FUSE>
-__global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb* __restrict__ probs, int nprob,
-                                                                   const double* __restrict__ fd,
-                                                                   const double* __restrict__ taylor,
-                                                                   const double* __restrict__ u,
-                                                                   double* __restrict__ w,
-                                                                   unsigned long long* __restrict__ stats,
-                                                                   double* __restrict__ u_out) {
+// The one-step kernel's body; DD: weights in double-double from the
+// double-double table (`taylor` is then that table).
+template <int NN, bool FUSE, bool DD>
+__device__ __forceinline__ void build_taylor_body(const DevProb* __restrict__ probs, int nprob,
+                                                  const double* __restrict__ fd, const double* __restrict__ taylor,
+                                                  const double* __restrict__ u, double* __restrict__ w,
+                                                  unsigned long long* __restrict__ stats, double* __restrict__ u_out) {
     constexpr int R = (NN - 1) / 2;
     constexpr int H = NN - 1;  // staged halo: a one-sided window reaches n - 1 positions
     constexpr int S = kTaylorTile + 2 * H;
@@ -262,11 +266,16 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
     const int sh = (int)rint(half);
 
     double W0[NN], W1[NN];
-    node_weights<NN>(active, r, sh, disp, a, CoefAtUse{b, e}, taylor, nullptr, W0, W1);
     // fused: W1 carries -g dt, so the window term is (u_j - u_i) d_j
     const double w1s = FUSE ? -g * dt : dt;
+    if constexpr (DD) {
+        double W2[NN];
+        node_weights_dd<NN, 1>(r, sh, a, b, e, w1s, taylor, W0, W1, W2);
+    } else {
+        node_weights<NN>(active, r, sh, disp, a, CoefAtUse{b, e}, taylor, nullptr, W0, W1);
 #pragma unroll
-    for (int j = 0; j < NN; ++j) W1[j] *= w1s;
+        for (int j = 0; j < NN; ++j) W1[j] *= w1s;
+    }
 
     if constexpr (FUSE) {
         const int base = tid + H - r;  // slot of window position 0
@@ -292,6 +301,27 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
     }
 }
 
+template <int NN, bool FUSE>
+__global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb* __restrict__ probs, int nprob,
+                                                                   const double* __restrict__ fd,
+                                                                   const double* __restrict__ taylor,
+                                                                   const double* __restrict__ u,
+                                                                   double* __restrict__ w,
+                                                                   unsigned long long* __restrict__ stats,
+                                                                   double* __restrict__ u_out) {
+    build_taylor_body<NN, FUSE, false>(probs, nprob, fd, taylor, u, w, stats, u_out);
+}
+template <int NN, bool FUSE>
+__global__ __launch_bounds__(kTaylorTile) void build_taylor_dd_kernel(const DevProb* __restrict__ probs, int nprob,
+                                                                      const double* __restrict__ fd,
+                                                                      const double* __restrict__ tdd,
+                                                                      const double* __restrict__ u,
+                                                                      double* __restrict__ w,
+                                                                      unsigned long long* __restrict__ stats,
+                                                                      double* __restrict__ u_out) {
+    build_taylor_body<NN, FUSE, true>(probs, nprob, fd, tdd, u, w, stats, u_out);
+}
+
 // Several frozen-velocity steps per launch (LMEP_F_PERSISTENT; centred or
 // one-sided windows on Dirichlet or periodic grids).  A block stages reg <=
 // kTaylorRegion consecutive positions of its instance in LDS, advances them
@@ -309,19 +339,19 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_kernel(const DevProb
 // read their rows from there at every step instead of from global memory.
 // Elsewhere a wavefront's lanes part only where the shift or the window side
 // changes; those few read the table in global memory, which measured faster.
-template <int NN>
-__global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevProb* __restrict__ probs, int nprob,
-                                                                   int kb, int ksteps, int reg,
-                                                                   const double* __restrict__ fd,
-                                                                   const double* __restrict__ taylor,
-                                                                   const double* __restrict__ u_in,
-                                                                   double* __restrict__ u_out,
-                                                                   unsigned long long* __restrict__ stats) {
+// With DD the weights come from the double-double routine (one-sided windows
+// of 9 or more points) and the table block is not staged.
+template <int NN, bool DD>
+__device__ __forceinline__ void taylor_stepk_body(const DevProb* __restrict__ probs, int nprob, int kb, int ksteps,
+                                                  int reg, const double* __restrict__ fd,
+                                                  const double* __restrict__ taylor,
+                                                  const double* __restrict__ u_in, double* __restrict__ u_out,
+                                                  unsigned long long* __restrict__ stats) {
     constexpr int R = (NN - 1) / 2;
     constexpr int H = NN - 1;
     constexpr int MAXR = kTaylorRegion;
     __shared__ double lds[3 * MAXR];  // current u, next u, derivative: addressed by offsets
-    __shared__ double lt[NN * NN * NN];  // this stencil size's table block
+    __shared__ double lt[DD ? 1 : NN * NN * NN];  // this stencil size's table block
     __shared__ double lfd[NN * NN];      // first-derivative rows of the clamped and one-sided windows
     const int REG = reg;
     const int nt = blockDim.x;  // threads: one staged position each per pass (normally nt = reg)
@@ -357,7 +387,7 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
     const int cd = 2 * MAXR;
     for (int t = tid; t < REG; t += nt)
         lds[cu + t] = (t >= g_lo && t < g_hi) ? us[map_index(v0 + t, N, bc)] : 0.0;
-    if (dir) stage_taylor_block<NN>(taylor, lt, tid, nt);
+    if (dir && !DD) stage_taylor_block<NN>(taylor, lt, tid, nt);
     for (int i = tid; i < NN * NN; i += nt) lfd[i] = fd[fd_index(NN, 0, i / NN, i % NN)] * ih;
     __syncthreads();
     int lo = g_lo, hi = g_hi;  // slots whose current u is valid
@@ -404,14 +434,21 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
             const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
             const int sh = (int)rint(half);
             double W0[NN], W1[NN];
-            if constexpr (HOIST)
-                node_weights<NN>(active, r, sh, disp, a, cf0, taylor, dir ? lt : nullptr, W0, W1);
-            else
-                node_weights<NN>(active, r, sh, disp, a, CoefAtUse{P.nu * ih * ih * dt, -P.delta * ih * ih * ih * dt},
-                                 taylor, dir ? lt : nullptr, W0, W1);
             const double w1s = -g * dt;  // as in the one-step kernel
+            if constexpr (DD) {
+                double W2[NN];
+                node_weights_dd<NN, 1>(r, sh, a, P.nu * ih * ih * dt, -P.delta * ih * ih * ih * dt, w1s, taylor, W0, W1,
+                                       W2);
+            } else {
+                if constexpr (HOIST)
+                    node_weights<NN>(active, r, sh, disp, a, cf0, taylor, dir ? lt : nullptr, W0, W1);
+                else
+                    node_weights<NN>(active, r, sh, disp, a,
+                                     CoefAtUse{P.nu * ih * ih * dt, -P.delta * ih * ih * ih * dt}, taylor,
+                                     dir ? lt : nullptr, W0, W1);
 #pragma unroll
-            for (int j = 0; j < NN; ++j) W1[j] *= w1s;
+                for (int j = 0; j < NN; ++j) W1[j] *= w1s;
+            }
             double acc = 0.0;
 #pragma unroll
             for (int j = 0; j < NN; ++j) {
@@ -440,8 +477,66 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
 }
 
 template <int NN>
-hipError_t go_taylor(const DevProb* d_probs, int nprob, int64_t tiles, const double* fd, const double* taylor,
+__global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevProb* __restrict__ probs, int nprob,
+                                                                   int kb, int ksteps, int reg,
+                                                                   const double* __restrict__ fd,
+                                                                   const double* __restrict__ taylor,
+                                                                   const double* __restrict__ u_in,
+                                                                   double* __restrict__ u_out,
+                                                                   unsigned long long* __restrict__ stats) {
+    taylor_stepk_body<NN, false>(probs, nprob, kb, ksteps, reg, fd, taylor, u_in, u_out, stats);
+}
+// launched with kTaylorDdThreads threads (two or more passes over the region)
+template <int NN>
+__global__ __launch_bounds__(kTaylorDdThreads) void taylor_stepk_dd_kernel(const DevProb* __restrict__ probs,
+                                                                         int nprob, int kb, int ksteps, int reg,
+                                                                         const double* __restrict__ fd,
+                                                                         const double* __restrict__ tdd,
+                                                                         const double* __restrict__ u_in,
+                                                                         double* __restrict__ u_out,
+                                                                         unsigned long long* __restrict__ stats) {
+    taylor_stepk_body<NN, true>(probs, nprob, kb, ksteps, reg, fd, tdd, u_in, u_out, stats);
+}
+
+// Stationary one-sided tables in double-double: one thread per harvested row
+// (items = n per instance, item_begin = the instance's first row), the plain
+// layout [kind][r][k] with W1 = dt phi1 and W2 = dt phi2 rows.
+template <int NN, int PP>
+__global__ __launch_bounds__(64) void build_table_dd_kernel(const DevProb* __restrict__ probs, int nprob,
+                                                            int64_t items, const double* __restrict__ tdd,
+                                                            double* __restrict__ w) {
+    const int64_t item = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (item >= items) return;
+    const DevProb& P = probs[find_instance(probs, nprob, item)];
+    const int r = (int)(item - P.item_begin);
+    const double ih = 1.0 / P.h, dt = P.dt;
+    const double a = -P.c * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
+    const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
+    double W0[NN], W1[NN], W2[NN];
+    node_weights_dd<NN, PP>(r, (int)rint(half), a, b, e, dt, tdd, W0, W1, W2);
+    double* __restrict__ wb = w + P.weight_off;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+        wb[r * NN + k] = W0[k];
+        if constexpr (PP >= 1) wb[(NN + r) * NN + k] = W1[k];
+        if constexpr (PP >= 2) wb[(2 * NN + r) * NN + k] = W2[k];
+    }
+}
+
+template <int NN>
+hipError_t go_taylor(bool dd, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd, const double* taylor,
                      const double* d_u, double* d_w, unsigned long long* stats, double* d_u_out, hipStream_t stream) {
+    if constexpr (NN < kTaylorDdMinN) {
+        if (dd) return hipErrorInvalidValue;
+    } else if (dd) {
+        if (d_u_out)
+            hipLaunchKernelGGL((build_taylor_dd_kernel<NN, true>), dim3((unsigned)tiles), dim3(kTaylorTile), 0,
+                               stream, d_probs, nprob, fd, taylor, d_u, d_w, stats, d_u_out);
+        else
+            hipLaunchKernelGGL((build_taylor_dd_kernel<NN, false>), dim3((unsigned)tiles), dim3(kTaylorTile), 0,
+                               stream, d_probs, nprob, fd, taylor, d_u, d_w, stats, d_u_out);
+        return hipGetLastError();
+    }
     if (d_u_out)
         hipLaunchKernelGGL((build_taylor_kernel<NN, true>), dim3((unsigned)tiles), dim3(kTaylorTile), 0, stream,
                            d_probs, nprob, fd, taylor, d_u, d_w, stats, d_u_out);
@@ -451,41 +546,89 @@ hipError_t go_taylor(const DevProb* d_probs, int nprob, int64_t tiles, const dou
     return hipGetLastError();
 }
 
+template <int NN, int PP>
+hipError_t go_table_dd(const DevProb* d_probs, int nprob, int64_t items, const double* tdd, double* d_w,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL((build_table_dd_kernel<NN, PP>), dim3((unsigned)((items + 63) / 64)), dim3(64), 0, stream,
+                       d_probs, nprob, items, tdd, d_w);
+    return hipGetLastError();
+}
+template <int NN>
+hipError_t go_table_dd_p(int p, const DevProb* d_probs, int nprob, int64_t items, const double* tdd, double* d_w,
+                         hipStream_t stream) {
+    switch (p) {
+        case 0: return go_table_dd<NN, 0>(d_probs, nprob, items, tdd, d_w, stream);
+        case 1: return go_table_dd<NN, 1>(d_probs, nprob, items, tdd, d_w, stream);
+        case 2: return go_table_dd<NN, 2>(d_probs, nprob, items, tdd, d_w, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb* d_probs, int nprob, int64_t tiles,
                                const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
-                               unsigned long long* stats, hipStream_t stream) {
+                               unsigned long long* stats, hipStream_t stream, bool dd) {
     if (tiles <= 0) return hipSuccess;
     if (tiles > 0x7fffffff || kb < 1 || kb > 8 || ksteps < 1 || ksteps > kb || reg < 64 || reg > kTaylorRegion ||
-        reg % 64 != 0 || taylor_stepk_tile(n, kb, reg, false) < 1)
+        reg % 64 != 0 || taylor_stepk_tile(n, kb, reg, false) < 1 || (dd && n < kTaylorDdMinN))
         return hipErrorInvalidValue;
+    const int nt = reg < kTaylorDdThreads ? reg : kTaylorDdThreads;
 #define LMEP_TSK_CASE(NN)                                                                                         \
     case NN:                                                                                                      \
-        hipLaunchKernelGGL((taylor_stepk_kernel<NN>), dim3((unsigned)tiles), dim3(reg), 0, stream, d_probs,         \
+        hipLaunchKernelGGL((taylor_stepk_kernel<NN>), dim3((unsigned)tiles), dim3(reg), 0, stream, d_probs, nprob,  \
+                           kb, ksteps, reg, fd, taylor, d_u_in, d_u_out, stats);                                  \
+        return hipGetLastError();
+#define LMEP_TSK_DD_CASE(NN)                                                                                      \
+    case NN:                                                                                                      \
+        hipLaunchKernelGGL((taylor_stepk_dd_kernel<NN>), dim3((unsigned)tiles), dim3(nt), 0, stream, d_probs,      \
                            nprob, kb, ksteps, reg, fd, taylor, d_u_in, d_u_out, stats);                           \
         return hipGetLastError();
+    if (dd) {
+        static_assert(kTaylorDdMinN == 9, "the double-double cases below start at n = 9");
+        switch (n) {
+            LMEP_TSK_DD_CASE(9) LMEP_TSK_DD_CASE(11) LMEP_TSK_DD_CASE(13) LMEP_TSK_DD_CASE(15)
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (n) {
         LMEP_TSK_CASE(3) LMEP_TSK_CASE(5) LMEP_TSK_CASE(7) LMEP_TSK_CASE(9) LMEP_TSK_CASE(11) LMEP_TSK_CASE(13)
         LMEP_TSK_CASE(15)
         default: return hipErrorInvalidValue;
     }
 #undef LMEP_TSK_CASE
+#undef LMEP_TSK_DD_CASE
+}
+
+hipError_t launch_build_table_dd(int n, int p, const DevProb* d_probs, int nprob, int64_t items, const double* tdd,
+                                 double* d_w, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    if (items > 0x7fffffffLL * 64) return hipErrorInvalidValue;
+    switch (n) {
+        case 3: return go_table_dd_p<3>(p, d_probs, nprob, items, tdd, d_w, stream);
+        case 5: return go_table_dd_p<5>(p, d_probs, nprob, items, tdd, d_w, stream);
+        case 7: return go_table_dd_p<7>(p, d_probs, nprob, items, tdd, d_w, stream);
+        case 9: return go_table_dd_p<9>(p, d_probs, nprob, items, tdd, d_w, stream);
+        case 11: return go_table_dd_p<11>(p, d_probs, nprob, items, tdd, d_w, stream);
+        case 13: return go_table_dd_p<13>(p, d_probs, nprob, items, tdd, d_w, stream);
+        case 15: return go_table_dd_p<15>(p, d_probs, nprob, items, tdd, d_w, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd,
                                const double* taylor, const double* d_u, double* d_w, unsigned long long* stats,
-                               hipStream_t stream, double* d_u_out) {
+                               hipStream_t stream, double* d_u_out, bool dd) {
     if (tiles <= 0) return hipSuccess;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     switch (n) {
-        case 3: return go_taylor<3>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
-        case 5: return go_taylor<5>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
-        case 7: return go_taylor<7>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
-        case 9: return go_taylor<9>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
-        case 11: return go_taylor<11>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
-        case 13: return go_taylor<13>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
-        case 15: return go_taylor<15>(d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 3: return go_taylor<3>(dd, d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 5: return go_taylor<5>(dd, d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 7: return go_taylor<7>(dd, d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 9: return go_taylor<9>(dd, d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 11: return go_taylor<11>(dd, d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 13: return go_taylor<13>(dd, d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
+        case 15: return go_taylor<15>(dd, d_probs, nprob, tiles, fd, taylor, d_u, d_w, stats, d_u_out, stream);
         default: return hipErrorInvalidValue;
     }
 }

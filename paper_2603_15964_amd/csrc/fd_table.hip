@@ -12,6 +12,7 @@
 // rows of D1^k / k! (D1 the unit-spacing first-derivative matrix).
 #include <mutex>
 
+#include "dd.hpp"
 #include "lmep_device.hpp"
 
 namespace lmep {
@@ -19,6 +20,7 @@ namespace {
 
 __device__ double g_fd_table[kFdTableDoubles];
 __device__ double g_taylor_table[kTaylorTableDoubles];
+__device__ double g_taylor_dd_table[2 * kTaylorTableDoubles];  // high parts, then low parts
 
 // Fornberg (1988), "Generation of finite difference formulas on arbitrarily
 // spaced grids": weights c[j][d] of node j for the d-th derivative at z,
@@ -87,7 +89,60 @@ std::mutex g_mu;
 const double* g_ptr[64] = {};
 const double* g_taylor_ptr[64] = {};
 
+// The same table in double-double, exactly rounded: on the integer stencil
+// l_j(x_a + y) = prod_{m != j} (y + a - m) / prod_{m != j} (j - m), whose
+// numerator coefficients and denominator are integers below 2^53 for n <= 15
+// (products of at most 14 factors of size <= 14), so each entry is one
+// double-double quotient of two exact doubles.  One thread per (stencil size,
+// expansion node a, basis polynomial j).
+__global__ void taylor_dd_table_kernel(double* __restrict__ hi, double* __restrict__ lo) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kNumN * kMaxN * kMaxN) return;
+    const int n = 3 + 2 * (t / (kMaxN * kMaxN));
+    const int a = (t / kMaxN) % kMaxN, j = t % kMaxN;
+    if (a >= n || j >= n) return;
+    double c[kMaxN] = {};  // coefficients of the numerator, lowest first
+    c[0] = 1.0;
+    int deg = 0;
+    double den = 1.0;
+    for (int m = 0; m < n; ++m) {
+        if (m == j) continue;
+        const double d = (double)(a - m);
+        for (int k = deg + 1; k >= 1; --k) c[k] = c[k - 1] + d * c[k];
+        c[0] *= d;
+        ++deg;
+        den *= (double)(j - m);
+    }
+    for (int k = 0; k < n; ++k) {
+        const dd q = dd_div_d(dd_of(c[k]), den);
+        hi[taylor_index(n, a, k, j)] = q.hi;
+        lo[taylor_index(n, a, k, j)] = q.lo;
+    }
+}
+
 }  // namespace
+
+hipError_t taylor_dd_table_init(const double** d_table_out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    static const double* ptr[64] = {};
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_taylor_dd_table))) != hipSuccess) return e;
+        double* hi = (double*)p;
+        const int threads = kNumN * kMaxN * kMaxN;
+        hipLaunchKernelGGL(taylor_dd_table_kernel, dim3((threads + 255) / 256), dim3(256), 0, nullptr, hi,
+                           hi + kTaylorTableDoubles);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+        ptr[dev] = hi;
+    }
+    *d_table_out = ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t fd_table_init(const double** d_table_out) {
     int dev = 0;

@@ -124,6 +124,14 @@ bool pernode(const lmep_problem& q) { return frozen(q) || nonuniform(q); }
 bool taylor(const lmep_problem& q, const Opts& o) {
     return frozen(q) && !nonuniform(q) && q.react == 0.0 && o.exp_method == LMEP_EXP_AUTO;
 }
+// One-sided windows whose rows FP64 sums cannot resolve: the finite-Taylor
+// build carried in double-double -- every stationary one-sided table (uniform
+// grid, no reaction term) and frozen-velocity one-sided windows of
+// kTaylorDdMinN or more points -- unless LMEP_OPT_EXP_METHOD asks for Pade.
+bool taylor_dd(const lmep_problem& q, const Opts& o) {
+    if (q.window != LMEP_WIN_UPWIND || nonuniform(q) || q.react != 0.0 || o.exp_method != LMEP_EXP_AUTO) return false;
+    return frozen(q) ? q.n >= kTaylorDdMinN : q.scheme != LMEP_ETDRK4;
+}
 
 int64_t weight_count(const lmep_problem& q) {
     const int64_t kinds = scheme_kinds(q.scheme);
@@ -293,6 +301,8 @@ struct Group {
     int n = 0, p = 0, scheme = 0, nonlin = 0, tile = 0;
     int reg = 0;             // multi-step finite-Taylor groups: staged positions per block
     bool taylor = false;     // build by finite Taylor series (items = kTaylorTile-node tiles)
+    bool dd = false;         // ... carried in double-double (frozen one-sided windows)
+    bool ddtable = false;    // stationary one-sided table in double-double (items = rows)
     bool pernode = false;    // weights stored per node (frozen velocity or non-uniform grid)
     bool frozen = false;     // rebuilt every step (frozen velocity)
     bool nonuniform = false; // non-uniform grid: per-node stationary weights
@@ -328,11 +338,15 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
     struct Part {
         int k, harvest;
     };
-    // (n, p, kind): kind 0 Pade in DPP rows, 1 the LDS build, 2 finite Taylor
+    // (n, p, kind): kind 0 Pade in DPP rows, 1 the LDS build, 2 finite Taylor,
+    // 3 finite Taylor in double-double (frozen velocity), 4 a stationary table
+    // in double-double
     std::map<std::tuple<int, int, int>, std::vector<Part>> by;
     // the LDS build for non-uniform grids and for orders beyond a DPP row
     auto kind_of = [&](const lmep_problem& q, int p) {
-        return (nonuniform(q) || q.n + p > kMaxM) ? 1 : (taylor(q, o) ? 2 : 0);
+        if (nonuniform(q) || q.n + p > kMaxM) return 1;
+        if (taylor_dd(q, o)) return frozen(q) ? 3 : 4;
+        return taylor(q, o) ? 2 : 0;
     };
     for (int k = 0; k < count; ++k) {
         if (!want(prob[k])) continue;
@@ -350,7 +364,9 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         g.n = std::get<0>(kv.first);
         g.p = std::get<1>(kv.first);
         g.wide = std::get<2>(kv.first) == 1;
-        g.taylor = std::get<2>(kv.first) == 2;
+        g.taylor = std::get<2>(kv.first) == 2 || std::get<2>(kv.first) == 3;
+        g.dd = std::get<2>(kv.first) == 3;
+        g.ddtable = std::get<2>(kv.first) == 4;
         for (const Part& part : kv.second) g.nodes += prob[part.k].N;
         if (g.taylor && frozen_kb > 0) {
             // staged positions per block (= threads): about one block per CU for
@@ -441,8 +457,10 @@ std::string bool_s(bool b) { return b ? "true" : "false"; }
 std::string build_kernel_name(const Group& g, bool fused, bool multi, int kb) {
     char b[96];
     if (g.wide) return "build_wide_kernel";
-    if (g.taylor && multi) snprintf(b, sizeof(b), "taylor_stepk_kernel<%d>", g.n);
-    else if (g.taylor) snprintf(b, sizeof(b), "build_taylor_kernel<%d,%s>", g.n, bool_s(fused).c_str());
+    const char* dd = g.dd ? "_dd" : "";
+    if (g.ddtable) snprintf(b, sizeof(b), "build_table_dd_kernel<%d,%d>", g.n, g.p);
+    else if (g.taylor && multi) snprintf(b, sizeof(b), "taylor_stepk%s_kernel<%d>", dd, g.n);
+    else if (g.taylor) snprintf(b, sizeof(b), "build_taylor%s_kernel<%d,%s>", dd, g.n, bool_s(fused).c_str());
     else snprintf(b, sizeof(b), "build_pade_kernel<%d,%d,%s>", g.n, g.p, bool_s(fused).c_str());
     (void)kb;
     return b;
@@ -651,6 +669,7 @@ struct StepPlan {
     bool all_resident = false;    // every group advances all steps in its first launch
     bool apply_launched = false;  // any apply kernel besides the fused ones
     bool need_taylor = false;
+    bool need_dd = false;
     Layout L;
     int64_t ext = 0;
 };
@@ -677,7 +696,8 @@ int make_step_plan(StepPlan& P, const lmep_problem* prob, int32_t count, bool mu
     P.count = count;
     P.bgroups = plan_build(prob, count, [](const lmep_problem& q) { return frozen(q); }, P.btab, o, multi ? P.kb : 0);
     P.agroups = plan_apply(prob, count, P.atab, P.tile_inst, o, multi ? P.kb : 0);
-    for (auto& g : P.bgroups) P.need_taylor |= g.taylor;
+    for (auto& g : P.bgroups) P.need_taylor |= g.taylor && !g.dd;
+    for (auto& g : P.bgroups) P.need_dd |= g.dd;
     P.all_resident = P.bgroups.empty();
     for (auto& g : P.agroups) P.all_resident &= g.resident;
     for (auto& g : P.agroups) P.apply_launched |= !(g.frozen && P.fuse);
@@ -696,7 +716,7 @@ std::vector<Piece> step_pieces(const StepPlan& P) {
 int step_launches(const StepPlan& P, int n_steps) { return P.all_resident ? 1 : (n_steps + P.kb - 1) / P.kb; }
 
 // The launch sequence of n_steps steps (kernels only: capturable).
-int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double* tay, double* d_w,
+int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double* tay, const double* tdd, double* d_w,
                   const double* d_u_in, double* d_u_out, int n_steps, unsigned long long* counters, Timer& timer,
                   hipStream_t s) {
     const DevProb* dbt = (const DevProb*)(base + P.L.build_tab);
@@ -727,12 +747,13 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
                 HIP_TRY(e);
                 if (one_span) span = t;
             }
+            const double* tt = gr.dd ? tdd : tay;
             if (gr.taylor && P.multi)
                 HIP_TRY(launch_taylor_stepk(gr.n, kb, std::min(kb, n_steps - st * kb), gr.reg, dbt + gr.first,
-                                            gr.count, gr.items, fd, tay, src, dst, counters, s));
+                                            gr.count, gr.items, fd, tt, src, dst, counters, s, gr.dd));
             else if (gr.taylor)
-                HIP_TRY(launch_build_taylor(gr.n, dbt + gr.first, gr.count, gr.items, fd, tay, src, d_w, counters, s,
-                                            P.fuse ? dst : nullptr));
+                HIP_TRY(launch_build_taylor(gr.n, dbt + gr.first, gr.count, gr.items, fd, tt, src, d_w, counters, s,
+                                            P.fuse ? dst : nullptr, gr.dd));
             else
                 HIP_TRY(launch_build(gr.n, gr.p, dbt + gr.first, gr.count, gr.items, fd, src, d_w, counters, s,
                                      P.fuse ? dst : nullptr));
@@ -792,13 +813,13 @@ struct GraphCache {
 };
 
 // Capture the step loop on this thread's capture stream and instantiate it.
-int capture_steps(const StepPlan& P, char* base, const double* fd, const double* tay, double* d_w,
+int capture_steps(const StepPlan& P, char* base, const double* fd, const double* tay, const double* tdd, double* d_w,
                   const double* d_u_in, double* d_u_out, int n_steps, hipGraphExec_t* exec) {
     if (!t_capture.s) HIP_TRY(hipStreamCreateWithFlags(&t_capture.s, hipStreamNonBlocking));
     hipStream_t cs = t_capture.s;
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     Timer off;
-    int rc = enqueue_steps(P, base, fd, tay, d_w, d_u_in, d_u_out, n_steps, nullptr, off, cs);
+    int rc = enqueue_steps(P, base, fd, tay, tdd, d_w, d_u_in, d_u_out, n_steps, nullptr, off, cs);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc) {
@@ -819,8 +840,10 @@ int run_step(const StepPlan& P, char* base, double* d_w, const double* d_u_in, d
              uint32_t flags, hipStream_t s, GraphCache* cache) {
     const double* fd = nullptr;
     const double* tay = nullptr;
+    const double* tdd = nullptr;
     HIP_TRY(fd_table_init(&fd));
     if (P.need_taylor) HIP_TRY(taylor_table_init(&tay));
+    if (P.need_dd) HIP_TRY(taylor_dd_table_init(&tdd));
     Timer timer;
     timer.on = (flags & LMEP_F_PROFILE) != 0;
     const size_t per_launch = P.bgroups.size() + P.agroups.size();
@@ -834,7 +857,7 @@ int run_step(const StepPlan& P, char* base, double* d_w, const double* d_u_in, d
             for (auto& en : cache->entries)
                 if (en.w == d_w && en.in == d_u_in && en.out == d_u_out && en.steps == n_steps) exec = en.exec;
         const bool fresh = exec == nullptr;
-        if (fresh && (rc = capture_steps(P, base, fd, tay, d_w, d_u_in, d_u_out, n_steps, &exec))) return rc;
+        if (fresh && (rc = capture_steps(P, base, fd, tay, tdd, d_w, d_u_in, d_u_out, n_steps, &exec))) return rc;
         hipError_t e = hipGraphLaunch(exec, s);
         if (fresh) {
             if (cache) {
@@ -848,7 +871,7 @@ int run_step(const StepPlan& P, char* base, double* d_w, const double* d_u_in, d
             }
         }
         if (e != hipSuccess) return fail(LMEP_ERR_DEVICE, "graph launch: %s", hipGetErrorString(e));
-    } else if ((rc = enqueue_steps(P, base, fd, tay, d_w, d_u_in, d_u_out, n_steps, counters, timer, s))) {
+    } else if ((rc = enqueue_steps(P, base, fd, tay, tdd, d_w, d_u_in, d_u_out, n_steps, counters, timer, s))) {
         return rc;
     }
     if ((rc = timer.collect(s))) return rc;
@@ -1207,12 +1230,17 @@ int lmep_build_weights(const lmep_problem* prob, int32_t count, const double* d_
     char* base = (char*)d_scratch;
     if ((rc = upload_pieces({{L.build_tab, btab.size() * sizeof(DevProb), btab.data()}}, base, s, false))) return rc;
     const DevProb* dtab = (const DevProb*)(base + L.build_tab);
+    const double* tdd = nullptr;
     for (auto& g : groups) {
-        if (g.taylor && !tay) HIP_TRY(taylor_table_init(&tay));
+        if (g.taylor && !g.dd && !tay) HIP_TRY(taylor_table_init(&tay));
+        if ((g.dd || g.ddtable) && !tdd) HIP_TRY(taylor_dd_table_init(&tdd));
         if (g.wide)
             HIP_TRY(launch_build_wide(g.n, g.p, dtab + g.first, g.count, g.items, d_w, s));
+        else if (g.ddtable)
+            HIP_TRY(launch_build_table_dd(g.n, g.p, dtab + g.first, g.count, g.items, tdd, d_w, s));
         else if (g.taylor)
-            HIP_TRY(launch_build_taylor(g.n, dtab + g.first, g.count, g.items, fd, tay, d_u, d_w, nullptr, s));
+            HIP_TRY(launch_build_taylor(g.n, dtab + g.first, g.count, g.items, fd, g.dd ? tdd : tay, d_u, d_w,
+                                        nullptr, s, nullptr, g.dd));
         else
             HIP_TRY(launch_build(g.n, g.p, dtab + g.first, g.count, g.items, fd, d_u, d_w, nullptr, s));
     }

@@ -69,6 +69,9 @@ __host__ __device__ inline int taylor_index(int n, int a, int k, int j) {
 // Fill the per-device stencil tables (blocking; once per device).
 hipError_t fd_table_init(const double** d_table_out);
 hipError_t taylor_table_init(const double** d_table_out);
+// The finite-Taylor table in double-double: high parts at d_table_out[i],
+// low parts at d_table_out[kTaylorTableDoubles + i], same index.
+hipError_t taylor_dd_table_init(const double** d_table_out);
 
 // Build weights for one group of instances sharing (n, p).  items = total
 // matrices of the group.  stats (nullable, profiling): stats[0] += matrices
@@ -83,10 +86,13 @@ hipError_t launch_build(int n, int p, const DevProb* d_probs, int nprob, int64_t
 // (react = 0, uniform grid): one thread per node, blocks of kTaylorTile nodes
 // of one instance; items = tiles, item_begin = the instance's first tile.
 // With d_u_out the step is fused as in launch_build.  stats[0] += nodes built.
+// dd: one-sided windows of n >= kTaylorDdMinN points, weights carried in
+// double-double from the double-double table (`taylor` is then that table).
 constexpr int kTaylorTile = 256;
+constexpr int kTaylorDdMinN = 9;
 hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t tiles, const double* fd,
                                const double* taylor, const double* d_u, double* d_w, unsigned long long* stats,
-                               hipStream_t stream, double* d_u_out = nullptr);
+                               hipStream_t stream, double* d_u_out = nullptr, bool dd = false);
 // The same fused step, ksteps <= kb steps per launch (Dirichlet or periodic):
 // a block stages `reg` positions (kTaylorRegion, or half of it for groups too
 // small to fill the GPU otherwise) and writes taylor_stepk_tile(n, kb, reg,
@@ -101,9 +107,18 @@ __host__ __device__ constexpr int taylor_stepk_tile(int n, int kb, int reg, bool
 }
 static_assert(taylor_stepk_tile(15, 8, kTaylorRegion, false) >= 256, "halo too wide for the staged region");
 static_assert(taylor_stepk_tile(15, 8, kTaylorRegion, true) >= 32, "halo too wide for the staged region");
+// dd as above; the double-double kernel runs kTaylorDdThreads threads per
+// block (at most reg), each taking reg / kTaylorDdThreads positions per pass.
+constexpr int kTaylorDdThreads = 256;
 hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb* d_probs, int nprob, int64_t tiles,
                                const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
-                               unsigned long long* stats, hipStream_t stream);
+                               unsigned long long* stats, hipStream_t stream, bool dd = false);
+// Stationary one-sided tables (uniform grid, react = 0, p <= 2) by the finite
+// Taylor series in double-double: items = n rows per instance (item_begin =
+// the instance's first row); writes the plain table [kind][r][k] with the
+// rows of e^{dt L}, dt phi1 and dt phi2.  tdd: the double-double table.
+hipError_t launch_build_table_dd(int n, int p, const DevProb* d_probs, int nprob, int64_t items, const double* tdd,
+                                 double* d_w, hipStream_t stream);
 
 // Stationary weights by the LDS build (one matrix per wavefront, orders up to
 // kMaxMWide): per node on non-uniform grids (p <= 2), and per harvested row of
