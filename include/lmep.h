@@ -88,9 +88,8 @@ enum { LMEP_NL_NONE = 0, LMEP_NL_BURGERS_FROZEN = 1, LMEP_NL_KDV = 2, LMEP_NL_AL
  * 5e-8 at n = 11 / 13 / 15.  The frozen-velocity remainder differentiates u
  * on one-sided windows, whose end rows grow like 2^n / n: for n >= 13 it
  * amplifies grid-scale perturbations unless the velocity varies little.
- * UPWIND is supported for LINEAR, ETD1 and ETD2RK with the one-step kernels,
- * and for BURGERS_FROZEN also under LMEP_F_PERSISTENT; ETDRK4,
- * LMEP_F_PERSISTENT with stationary weights and the reverse step return
+ * UPWIND is supported for LINEAR, ETD1 and ETD2RK, one step or several
+ * per launch (LMEP_F_PERSISTENT); ETDRK4 and the reverse step return
  * LMEP_ERR_UNSUPPORTED. */
 enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
 
@@ -101,7 +100,7 @@ enum { LMEP_WIN_CENTRED = 0, LMEP_WIN_UPWIND = 1 };
                                   /* LMEP_OPT_STEPS_PER_LAUNCH), so                             */
                                   /* HBM is read and written once per launch instead of once    */
                                   /* per step; same result bit for bit as the one-step path.    */
-                                  /* Stationary weights: centred windows.  BURGERS_FROZEN:      */
+                                  /* Stationary weights: centred or upwind windows.  BURGERS_FROZEN: */
                                   /* the fused finite-Taylor build and step (react = 0,         */
                                   /* LMEP_EXP_AUTO) on Dirichlet or periodic grids, centred or  */
                                   /* upwind windows; other frozen-velocity instances are        */

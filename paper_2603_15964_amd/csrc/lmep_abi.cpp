@@ -310,6 +310,7 @@ struct Group {
     bool resident = false;   // non-uniform, several steps per launch, one block per instance
     int64_t max_nodes = 0;
     bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
+    int side = 0;        // stationary windows: 0 centred, 1 one-sided ending at the node (c > 0), 2 starting at it
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
     int64_t nodes = 0;         // nodes of the group's instances
@@ -403,17 +404,25 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
 
 // Apply groups: keyed by kernel variant; also fills the block -> table-row map.
 // multi_kb > 0: tiles of the multi-step kernel advancing multi_kb steps per launch.
+// Window side of a stationary instance's interior nodes (frozen-velocity and
+// non-uniform instances pick theirs per node: 0).
+int stationary_side(const lmep_problem& q) {
+    if (frozen(q) || nonuniform(q) || q.window != LMEP_WIN_UPWIND || q.c == 0.0) return 0;
+    return q.c > 0.0 ? 1 : 2;
+}
+
 std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab,
                               std::vector<int>& tile_inst, const Opts& o, int multi_kb = 0) {
     // weight kind: 0 stationary table, 1 frozen velocity, 2 non-uniform grid
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> by;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < count; ++k)
-        by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : (nonuniform(prob[k]) ? 2 : 0)}]
+        by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : (nonuniform(prob[k]) ? 2 : 0),
+            stationary_side(prob[k])}]
             .push_back(k);
     std::vector<Group> groups;
     for (auto& kv : by) {
         Group g;
-        std::tie(g.n, g.scheme, g.nonlin, std::ignore) = kv.first;
+        std::tie(g.n, g.scheme, g.nonlin, std::ignore, g.side) = kv.first;
         g.pernode = std::get<3>(kv.first) != 0;
         g.frozen = std::get<3>(kv.first) == 1;
         g.nonuniform = std::get<3>(kv.first) == 2;
@@ -469,6 +478,8 @@ std::string apply_kernel_name(const Group& g, int kb) {
     char b[96];
     const int nl = g.scheme == LMEP_LINEAR ? 0 : g.nonlin;
     if (g.stepk && g.scheme == LMEP_ETDRK4) snprintf(b, sizeof(b), "stepk_rk4_kernel<%d,%d,%d>", g.n, g.nonlin, kb);
+    else if (g.stepk && g.side != 0)
+        snprintf(b, sizeof(b), "stepk_upwind_kernel<%d,%d,%d,%d,%d>", g.n, g.scheme, nl, kb, g.side);
     else if (g.stepk) snprintf(b, sizeof(b), "stepk_kernel<%d,%d,%d,%d>", g.n, g.scheme, nl, kb);
     else if (g.resident)
         snprintf(b, sizeof(b), "resident_kernel<%d,%d,%d,%s>", g.n, g.scheme, nl, bool_s(!g.nonuniform).c_str());
@@ -682,9 +693,6 @@ int make_step_plan(StepPlan& P, const lmep_problem* prob, int32_t count, bool mu
             if (frozen(prob[k]) && (!taylor(prob[k], o) || prob[k].bc == LMEP_BC_NEUMANN))
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with BURGERS_FROZEN (instance %d) needs the "
                             "finite-Taylor build (react = 0, LMEP_EXP_AUTO) on a Dirichlet or periodic grid", k);
-            if (prob[k].window != LMEP_WIN_CENTRED && !frozen(prob[k]))
-                return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT with stationary weights needs centred windows "
-                            "(instance %d)", k);
             if (nonuniform(prob[k]) && prob[k].N > kResidentMaxN)
                 return fail(LMEP_ERR_UNSUPPORTED, "LMEP_F_PERSISTENT on a non-uniform grid needs N <= %d "
                             "(instance %d)", kResidentMaxN, k);
@@ -771,7 +779,7 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
                 }
                 if (gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
-                                         dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
+                                         dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s, gr.side));
                 else if (gr.resident) {
                     // in place after the first chunk: a block reads its whole
                     // instance before it writes any of it

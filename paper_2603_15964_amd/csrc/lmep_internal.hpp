@@ -173,11 +173,18 @@ template <int KB>
 hipError_t launch_stepk_depth(int n, int scheme, int nonlin, int ksteps, const DevProb* d_probs,
                               const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
                               const double* d_u_in, double* d_u_out, hipStream_t stream);
+template <int KB>
+hipError_t launch_stepk_upwind_depth(int side, int n, int scheme, int nonlin, int ksteps, const DevProb* d_probs,
+                                     const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                                     const double* d_u_in, double* d_u_out, hipStream_t stream);
 // Block b of a group writes nodes [b' * tile, (b' + 1) * tile) of its instance,
-// b' = b - item_begin, tile = stepk_tile(n, scheme, nonlin, kb).
+// b' = b - item_begin, tile = stepk_tile(n, scheme, nonlin, kb) -- on
+// Dirichlet and Neumann grids the last block [N - tile, N) when N >= tile.
+// side: 0 centred windows, 1 one-sided windows ending at the node (c > 0),
+// 2 starting at it (c < 0); every instance of a launch has the same side.
 hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const DevProb* d_probs,
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
-                        const double* d_u_in, double* d_u_out, hipStream_t stream);
+                        const double* d_u_in, double* d_u_out, hipStream_t stream, int side = 0);
 
 constexpr int kApplyTileTiny = 64;     // nodes per apply block for small non-uniform instances
 constexpr int kApplyTileSmall = 256;   // nodes per apply block for groups with few nodes

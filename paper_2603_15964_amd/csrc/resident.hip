@@ -39,7 +39,8 @@ __global__ __launch_bounds__(kResidentMaxN) void resident_kernel(const DevProb* 
     double* sNa = sa + N;         // N(a)
 
     const int bc = UNI ? P.bc : BC_DIRICHLET;
-    const int o = node ? (int)window_offset(i, N, NN, bc) : 0;
+    // a uniform grid's window may be one-sided (stationary: the side of c)
+    const int o = node ? (int)window_offset(i, N, NN, bc, UNI ? P.window : WIN_CENTRED, P.c) : 0;
     const bool fixed = bc == BC_DIRICHLET && ((i == 0) || (i == N - 1));
     double W0[NN], W1[NN], W2[NN];
     int slot[NN];  // LDS slot of window position k

@@ -5,9 +5,19 @@ namespace lmep {
 
 hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const DevProb* d_probs,
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
-                        const double* d_u_in, double* d_u_out, hipStream_t stream) {
+                        const double* d_u_in, double* d_u_out, hipStream_t stream, int side) {
     if (tiles <= 0) return hipSuccess;
-    if (ksteps < 1 || ksteps > kb) return hipErrorInvalidValue;
+    if (ksteps < 1 || ksteps > kb || side < 0 || side > 2) return hipErrorInvalidValue;
+    if (side != 0) {
+        if (scheme == SCH_ETDRK4) return hipErrorInvalidValue;
+        switch (kb) {
+            case 1: return launch_stepk_upwind_depth<1>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+            case 2: return launch_stepk_upwind_depth<2>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+            case 4: return launch_stepk_upwind_depth<4>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+            case 8: return launch_stepk_upwind_depth<8>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (kb) {
         case 1: return launch_stepk_depth<1>(n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
         case 2: return launch_stepk_depth<2>(n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);

@@ -16,10 +16,20 @@
 //    the thread's base;
 //  * the pointwise Allen-Cahn term is formed on the fly from the state window;
 //    KdV's derivative term gets a pass of its own;
-//  * centre-row weights live in registers; blocks that reach a Dirichlet end
-//    redo the nodes next to it with their own one-sided row in a short extra
-//    pass, and blocks that reach a Neumann end give halo positions their
-//    mirror node's value.
+//  * the interior row's weights live in registers; blocks that reach a
+//    Dirichlet end redo the nodes next to it with their own clamped row in a
+//    short extra pass, and blocks that reach a Neumann end give halo
+//    positions their mirror node's value;
+//  * on Dirichlet and Neumann grids the last block of an instance is moved
+//    back to end at node N - 1 (it rewrites part of its neighbour's tile with
+//    the same values): the clamped windows next to an end reach n - 1 nodes
+//    inwards, and a tile starting there would not hold what they depend on.
+// One-sided (upwind) windows of a stationary operator are the same kernel
+// with the interior window ending (SIDE 1, c > 0) or starting (SIDE 2, c < 0)
+// at the node: every application then spoils n - 1 positions on the upstream
+// side only, so the whole halo sits upstream of the tile, and the Dirichlet
+// pass covers the n - 1 clamped nodes at the upstream end and the held
+// downstream end.
 // Every value is formed by the same expression, in the same order, as in the
 // one-step apply kernel, so the two give bitwise identical states.
 #pragma once
@@ -63,6 +73,16 @@ __device__ __forceinline__ double pointwise_N(double x, double g) {
     return g * (x - x * x * x);
 }
 
+// Interior window of a SIDE: offset O (stencil i + O .. i + O + n - 1), row
+// RI = -O, and the nodes the Dirichlet pass redoes (EC of them).
+template <int NN, int SIDE>
+struct Win {
+    static constexpr int O = SIDE == 0 ? -((NN - 1) / 2) : (SIDE == 1 ? -(NN - 1) : 0);
+    static constexpr int RI = -O;
+    static constexpr int EC = SIDE == 0 ? NN - 1 : NN;
+    static_assert(-O <= MARGIN && NN - 1 + O <= MARGIN, "window reads must stay inside the margins");
+};
+
 template <int NN, int SCH, int NL, int KB>
 struct Shape {
     static constexpr int R = (NN - 1) / 2;
@@ -81,13 +101,16 @@ struct Shape {
     static_assert(TILE > 0 && HALO % 1 == 0, "tile");
 };
 
-template <int NN, int SCH, int NL, int KB>
-__global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ probs, const int* __restrict__ tile_inst,
-                                                   const double* __restrict__ fd, const double* __restrict__ w,
-                                                   const double* __restrict__ u_in, double* __restrict__ u_out,
-                                                   int ksteps) {
+template <int NN, int SCH, int NL, int KB, int SIDE>
+__device__ __forceinline__ void stepk_body(const DevProb* __restrict__ probs, const int* __restrict__ tile_inst,
+                                           const double* __restrict__ fd, const double* __restrict__ w,
+                                           const double* __restrict__ u_in, double* __restrict__ u_out, int ksteps) {
     using S = Shape<NN, SCH, NL, KB>;
+    using Wn = Win<NN, SIDE>;
     constexpr int R = S::R, PP = S::PP, W = V + NN - 1;
+    constexpr int O = Wn::O, RI = Wn::RI;
+    // halo before the tile: (applications) x (reach of a window to the left)
+    constexpr int LHALO = KB * stepk_apps(SCH, NL) * RI;
     __shared__ double lds[S::NBUF * LP];
     __shared__ double sw[(PP + 1) * NN * NN];
     __shared__ double sD1[S::DERIV ? NN * NN : 1];
@@ -96,8 +119,9 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
     const DevProb& P = probs[tile_inst[blockIdx.x]];
     const int64_t N = P.N;
     const int bc = P.bc;
-    const int64_t t0 = ((int64_t)blockIdx.x - P.item_begin) * S::TILE;
-    const int64_t base = t0 - S::HALO;  // unwrapped position of region index 0
+    const int64_t tb = ((int64_t)blockIdx.x - P.item_begin) * S::TILE;  // the block's own tile
+    const int64_t t0 = (bc != BC_PERIODIC && N >= S::TILE && tb > N - S::TILE) ? N - S::TILE : tb;
+    const int64_t base = t0 - LHALO;  // unwrapped position of region index 0
     const double g = P.nl_coef;
     // does the region reach an end of the grid?  (block-uniform)
     const bool at_end = base < NN || base + LR > N - NN;
@@ -123,25 +147,25 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
     }
     __syncthreads();
 
-    // centre-row weights of each kind, read from global memory at a
+    // interior-row weights of each kind, read from global memory at a
     // block-uniform address, so they live in scalar registers and leave the
     // vector registers to the windows
     double Wc[PP + 1][NN];
 #pragma unroll
     for (int kd = 0; kd <= PP; ++kd)
 #pragma unroll
-        for (int k = 0; k < NN; ++k) Wc[kd][k] = w[P.weight_off + (kd * NN + R) * NN + k];
+        for (int k = 0; k < NN; ++k) Wc[kd][k] = w[P.weight_off + (kd * NN + RI) * NN + k];
     double D1c[S::DERIV ? NN : 1];
     if constexpr (S::DERIV) {
 #pragma unroll
-        for (int k = 0; k < NN; ++k) D1c[k] = sD1[R * NN + k];
+        for (int k = 0; k < NN; ++k) D1c[k] = sD1[RI * NN + k];
     }
 
     const int p0 = tid * V;                   // this thread's first position
     const int wb = phys(p0 - MARGIN);         // slot base of its windows
     const int ob = wb + rel(MARGIN);          // slot base of its own positions
-    // window value j (position p0 - R + j) of array a
-    auto wread = [&](const double* __restrict__ a, int j) { return a[wb + rel(MARGIN - R + j)]; };
+    // window value j (position p0 + O + j) of array a
+    auto wread = [&](const double* __restrict__ a, int j) { return a[wb + rel(MARGIN + O + j)]; };
     auto own = [&](const double* __restrict__ a, int v) { return a[ob + rel(v) - rel(0)]; };
     // one-sided rows: slot of the first node of the window of node i
     auto edge_win = [&](int64_t i, int64_t off) { return clampi((int)(i + off - base), -MARGIN, LR + MARGIN - NN); };
@@ -184,7 +208,7 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             xu[j] = wread(su, j);
-            if constexpr (S::HAS_N) xn[j] = n_at(su, sn, xu[j], wb + rel(MARGIN - R + j));
+            if constexpr (S::HAS_N) xn[j] = n_at(su, sn, xu[j], wb + rel(MARGIN + O + j));
         }
         double o[V];
 #pragma unroll
@@ -206,7 +230,7 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
                        const double* __restrict__ sna, double* __restrict__ dst) {
         double d[W];
 #pragma unroll
-        for (int j = 0; j < W; ++j) d[j] = n_diff(su, snu, sa, sna, wb + rel(MARGIN - R + j));
+        for (int j = 0; j < W; ++j) d[j] = n_diff(su, snu, sa, sna, wb + rel(MARGIN + O + j));
         double o[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -219,23 +243,26 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
         for (int v = 0; v < V; ++v) dst[ob + rel(v) - rel(0)] = o[v];
     };
 
-    // Dirichlet: after a pass has written every position with the centre row,
-    // blocks that reach an end redo the nodes whose window is one-sided with
-    // their own row (and hold the end nodes).  Node e of the 2R such nodes is
-    // e (e < R) or N - 1 - (e - R).
+    // Dirichlet: after a pass has written every position with the interior
+    // row, blocks that reach an end redo the nodes whose window is clamped
+    // with their own row (and hold the end nodes).  Centred: node e of the
+    // 2R such nodes is e (e < R) or N - 1 - (e - R); one-sided: the n - 1
+    // nodes at the upstream end, then the downstream end node.
     auto edge_node = [&](int e, int64_t& i, int& q) -> bool {
-        i = e < R ? (int64_t)e : N - 1 - (e - R);
+        if constexpr (SIDE == 0) i = e < R ? (int64_t)e : N - 1 - (e - R);
+        else if constexpr (SIDE == 1) i = e < NN - 1 ? (int64_t)e : N - 1;
+        else i = e < NN - 1 ? N - 1 - e : 0;
         q = (int)(i - base);
         return i - base >= 0 && i - base < LR;
     };
     auto edge_N = [&](const double* __restrict__ src, double* __restrict__ dst) {
         if (!dir) return;
         __syncthreads();
-        for (int e = tid; e < 2 * R; e += NT) {
+        for (int e = tid; e < Wn::EC; e += NT) {
             int64_t i;
             int q;
             if (!edge_node(e, i, q)) continue;
-            const int64_t off = window_offset(i, N, NN, bc);
+            const int64_t off = window_offset(i, N, NN, bc, P.window, P.c);
             const int rr = (int)(-off);
             const int b0 = edge_win(i, off);
             double acc = 0.0;
@@ -249,7 +276,7 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
     auto edge_a = [&](const double* __restrict__ su, const double* __restrict__ sn, double* __restrict__ dst) {
         if (!dir) return;
         __syncthreads();
-        for (int e = tid; e < 2 * R; e += NT) {
+        for (int e = tid; e < Wn::EC; e += NT) {
             int64_t i;
             int q;
             if (!edge_node(e, i, q)) continue;
@@ -257,7 +284,7 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
                 dst[phys(q)] = (i == 0) ? P.bc_left : P.bc_right;
                 continue;
             }
-            const int64_t off = window_offset(i, N, NN, bc);
+            const int64_t off = window_offset(i, N, NN, bc, P.window, P.c);
             const int rr = (int)(-off);
             const int b0 = edge_win(i, off);
             double acc = 0.0;
@@ -273,13 +300,13 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
                       const double* __restrict__ sna, double* __restrict__ dst) {
         if (!dir) return;
         __syncthreads();
-        for (int e = tid; e < 2 * R; e += NT) {
+        for (int e = tid; e < Wn::EC; e += NT) {
             int64_t i;
             int q;
             if (!edge_node(e, i, q)) continue;
             double acc = sa[phys(q)];
             if (i != 0 && i != N - 1) {  // the first stage holds the end values
-                const int64_t off = window_offset(i, N, NN, bc);
+                const int64_t off = window_offset(i, N, NN, bc, P.window, P.c);
                 const int rr = (int)(-off);
                 const int b0 = edge_win(i, off);
                 for (int k = 0; k < NN; ++k) acc += sw[(PP * NN + rr) * NN + k] * n_diff(su, snu, sa, sna, phys(b0 + k));
@@ -356,49 +383,70 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
     double* __restrict__ out = u_out + P.state_off;
     for (int q = tid; q < S::TILE; q += NT) {
         const int64_t i = t0 + q;
-        if (i < N) out[i] = cur[phys(q + S::HALO)];
+        if (i < N) out[i] = cur[phys(q + LHALO)];
     }
 }
 
 template <int NN, int SCH, int NL, int KB>
+__global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ probs, const int* __restrict__ tile_inst,
+                                                   const double* __restrict__ fd, const double* __restrict__ w,
+                                                   const double* __restrict__ u_in, double* __restrict__ u_out,
+                                                   int ksteps) {
+    stepk_body<NN, SCH, NL, KB, 0>(probs, tile_inst, fd, w, u_in, u_out, ksteps);
+}
+// one-sided windows: SIDE 1 (c > 0, window ends at the node), 2 (c < 0)
+template <int NN, int SCH, int NL, int KB, int SIDE>
+__global__ __launch_bounds__(NT) void stepk_upwind_kernel(const DevProb* __restrict__ probs,
+                                                          const int* __restrict__ tile_inst,
+                                                          const double* __restrict__ fd, const double* __restrict__ w,
+                                                          const double* __restrict__ u_in, double* __restrict__ u_out,
+                                                          int ksteps) {
+    stepk_body<NN, SCH, NL, KB, SIDE>(probs, tile_inst, fd, w, u_in, u_out, ksteps);
+}
+
+template <int NN, int SCH, int NL, int KB, int SIDE>
 hipError_t go(const DevProb* p, const int* ti, int64_t tiles, const double* fd, const double* w, const double* ui,
               double* uo, int ksteps, hipStream_t s) {
-    hipLaunchKernelGGL((stepk_kernel<NN, SCH, NL, KB>), dim3((unsigned)tiles), dim3(NT), 0, s, p, ti, fd, w, ui, uo,
-                       ksteps);
+    if constexpr (SIDE == 0)
+        hipLaunchKernelGGL((stepk_kernel<NN, SCH, NL, KB>), dim3((unsigned)tiles), dim3(NT), 0, s, p, ti, fd, w, ui,
+                           uo, ksteps);
+    else
+        hipLaunchKernelGGL((stepk_upwind_kernel<NN, SCH, NL, KB, SIDE>), dim3((unsigned)tiles), dim3(NT), 0, s, p, ti,
+                           fd, w, ui, uo, ksteps);
     return hipGetLastError();
 }
 
-template <int NN, int KB>
+template <int NN, int KB, int SIDE>
 hipError_t dispatch(int scheme, int nonlin, const DevProb* p, const int* ti, int64_t tiles, const double* fd,
                     const double* w, const double* ui, double* uo, int ksteps, hipStream_t s) {
-    if (scheme == SCH_LINEAR) return go<NN, SCH_LINEAR, NL_NONE, KB>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
+    if (scheme == SCH_LINEAR) return go<NN, SCH_LINEAR, NL_NONE, KB, SIDE>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
     if (scheme != SCH_ETD1 && scheme != SCH_ETD2RK) return hipErrorInvalidValue;
     const bool rk2 = scheme == SCH_ETD2RK;
     switch (nonlin) {
         case NL_NONE:
-            return rk2 ? go<NN, SCH_ETD2RK, NL_NONE, KB>(p, ti, tiles, fd, w, ui, uo, ksteps, s)
-                       : go<NN, SCH_ETD1, NL_NONE, KB>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
+            return rk2 ? go<NN, SCH_ETD2RK, NL_NONE, KB, SIDE>(p, ti, tiles, fd, w, ui, uo, ksteps, s)
+                       : go<NN, SCH_ETD1, NL_NONE, KB, SIDE>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
         case NL_AC:
-            return rk2 ? go<NN, SCH_ETD2RK, NL_AC, KB>(p, ti, tiles, fd, w, ui, uo, ksteps, s)
-                       : go<NN, SCH_ETD1, NL_AC, KB>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
+            return rk2 ? go<NN, SCH_ETD2RK, NL_AC, KB, SIDE>(p, ti, tiles, fd, w, ui, uo, ksteps, s)
+                       : go<NN, SCH_ETD1, NL_AC, KB, SIDE>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
         case NL_KDV:
-            return rk2 ? go<NN, SCH_ETD2RK, NL_KDV, KB>(p, ti, tiles, fd, w, ui, uo, ksteps, s)
-                       : go<NN, SCH_ETD1, NL_KDV, KB>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
+            return rk2 ? go<NN, SCH_ETD2RK, NL_KDV, KB, SIDE>(p, ti, tiles, fd, w, ui, uo, ksteps, s)
+                       : go<NN, SCH_ETD1, NL_KDV, KB, SIDE>(p, ti, tiles, fd, w, ui, uo, ksteps, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int KB>
+template <int KB, int SIDE>
 hipError_t dispatch_n(int n, int scheme, int nonlin, const DevProb* p, const int* ti, int64_t tiles, const double* fd,
                       const double* w, const double* ui, double* uo, int ksteps, hipStream_t s) {
     switch (n) {
-        case 3: return dispatch<3, KB>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
-        case 5: return dispatch<5, KB>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
-        case 7: return dispatch<7, KB>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
-        case 9: return dispatch<9, KB>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
-        case 11: return dispatch<11, KB>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
-        case 13: return dispatch<13, KB>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
-        case 15: return dispatch<15, KB>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 3: return dispatch<3, KB, SIDE>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 5: return dispatch<5, KB, SIDE>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 7: return dispatch<7, KB, SIDE>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 9: return dispatch<9, KB, SIDE>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 11: return dispatch<11, KB, SIDE>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 13: return dispatch<13, KB, SIDE>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case 15: return dispatch<15, KB, SIDE>(scheme, nonlin, p, ti, tiles, fd, w, ui, uo, ksteps, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -9,7 +9,7 @@ hipError_t launch_stepk_depth<4>(int n, int scheme, int nonlin, int ksteps, cons
                                   const double* d_u_in, double* d_u_out, hipStream_t stream) {
     if (scheme == SCH_ETDRK4)
         return dispatch_n_rk4<4>(n, nonlin, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, ksteps, stream);
-    return dispatch_n<4>(n, scheme, nonlin, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, ksteps, stream);
+    return dispatch_n<4, 0>(n, scheme, nonlin, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, ksteps, stream);
 }
 
 }  // namespace lmep

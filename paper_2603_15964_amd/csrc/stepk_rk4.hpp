@@ -13,8 +13,8 @@
 // (n-1)/2 positions of halo per side (twice that with KdV's derivative term,
 // which gets passes of its own).  Allen-Cahn: N is formed on the fly, four
 // arrays (u, a, b, c) and N(a) + N(b) stored over a once c exists.  KdV: six
-// arrays, stages written over dead ones.  Dirichlet end rows and Neumann
-// mirrors as in stepk.hpp.  E2 and P2 stay in registers; E, A, B, C are read
+// arrays, stages written over dead ones.  Dirichlet end rows, Neumann
+// mirrors and the placement of an instance's last block as in stepk.hpp.  E2 and P2 stay in registers; E, A, B, C are read
 // from LDS in the final pass.
 #pragma once
 #include "stepk.hpp"
@@ -50,7 +50,9 @@ __global__ __launch_bounds__(NT) void stepk_rk4_kernel(const DevProb* __restrict
     const DevProb& P = probs[tile_inst[blockIdx.x]];
     const int64_t N = P.N;
     const int bc = P.bc;
-    const int64_t t0 = ((int64_t)blockIdx.x - P.item_begin) * S::TILE;
+    // the last block of a Dirichlet or Neumann instance ends at node N - 1 (see stepk.hpp)
+    const int64_t own = ((int64_t)blockIdx.x - P.item_begin) * S::TILE;
+    const int64_t t0 = (bc != BC_PERIODIC && N >= S::TILE && own > N - S::TILE) ? N - S::TILE : own;
     const int64_t base = t0 - S::HALO;
     const double g = P.nl_coef;
     const bool at_end = base < NN || base + LR > N - NN;

@@ -153,8 +153,8 @@ def test_exp_method_option():
 
 def test_window_field_checks():
     """The window field: unknown values are ARG; upwind windows are refused
-    with ETDRK4, with multi-step launches and by the reverse step before any
-    device work.  The Python mirror has the C layout (window at byte 112)."""
+    with ETDRK4 and by the reverse step before any device work.  The Python
+    mirror has the C layout (window at byte 112)."""
     assert lmep.lmep_problem.window.offset == 112 and lmep.lmep_problem.x.offset == 120
     assert ctypes.sizeof(lmep.lmep_problem) == 128
     lib = lmep.library()
@@ -169,10 +169,6 @@ def test_window_field_checks():
     rc = lib.lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 1, 0,
                        ctypes.c_void_p(256), 1 << 30, None)
     assert rc == lmep.LMEP_ERR_UNSUPPORTED, lmep.lmep_last_error()
-    s = lmep.problem_array([dict(rk4, scheme="etd1")])
-    rc = lib.lmep_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(4096), 4,
-                       lmep.LMEP_F_PERSISTENT, ctypes.c_void_p(256), 1 << 30, None)
-    assert rc == lmep.LMEP_ERR_UNSUPPORTED and "centred" in lmep.lmep_last_error()
     s = _structs(window="upwind")
     rc = lib.lmep_adjoint_step(s, 1, ctypes.c_void_p(8), ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20),
                                ctypes.c_void_p(1 << 24), ctypes.c_void_p(256), 1 << 30, None)
