@@ -21,6 +21,9 @@ Printed, one JSON line:
             with nu * 1.1): forward + checkpointed reverse, beside its own
             plain single-instance forward, with the roofline of the reverse
             kernel;
+  upwind_sweep  linear advection on one-sided stencils of n = 7 .. 15 at
+            Courant number n/2 to a fixed final time (the time taken should
+            not grow with n);
   single_instance  the viscous-Burgers workload (N = 65536, n = 7, weights
             rebuilt every step from the frozen velocity), 1000 steps;
   cpu_baseline  the oracle on a bounded sample of the batch, on the host's
@@ -31,6 +34,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -183,6 +187,10 @@ def make_workload(name: str):
         return ([p] * len(u0s), u0s,
                 "64 Burgers trajectories N=262144 n=9 Dirichlet (the adjoint workload's forward), frozen-velocity "
                 "ETD1, weights rebuilt every step")
+    if name.startswith("upwind_advection"):
+        n = int(name[len("upwind_advection"):] or 15)
+        p, u0 = workloads.upwind_advection(n=n)
+        return [p], [u0], f"linear advection N=1048576 periodic on one-sided stencils, n={n}, Courant {n / 2}"
     if name == "burgers_adjoint":
         p, pt, u0s = workloads.burgers_adjoint_batch()
         return ([p] * len(u0s), u0s,
@@ -552,6 +560,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain single-instance comparison runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance Burgers workload")
+    ap.add_argument("--no-upwind-sweep", action="store_true",
+                    help="skip the one-sided advection runs over stencil sizes")
     ap.add_argument("--adjoint-steps", type=int, default=500)
     ap.add_argument("--adjoint-every", type=int, default=50, help="checkpoint interval of the adjoint run")
     ap.add_argument("--copy-probe", action="store_true",
@@ -639,6 +649,8 @@ def main():
             if not args.no_adjoint:
                 ap_, as_, _ = make_workload("burgers_adjoint")
                 out["adjoint"] = adjoint_line(ap_, as_, args)
+            if not args.no_upwind_sweep:
+                out["upwind_sweep"] = upwind_sweep()
             if not args.no_single:
                 sp, ss, sdesc = make_workload("burgers")
                 sflags, skb = launch_choice(sp, argparse.Namespace(launch="auto", persistent=False,
@@ -655,7 +667,8 @@ def main():
 
 def launch_choice(problems, args):
     """(flags, steps per launch): several steps per launch wherever the
-    multi-step kernels cover every instance (stationary centred windows;
+    multi-step kernels cover every instance (stationary weights, centred or
+    one-sided windows;
     frozen velocity by the finite-Taylor kernel on Dirichlet or periodic grids
     under 2^20 nodes -- larger batches fill the GPU in one step), else one."""
     import paper_2603_15964_amd as lmep
@@ -679,11 +692,44 @@ def launch_choice(problems, args):
         return lmep.LMEP_F_PERSISTENT, kb
     if any(frozen):
         return 0, 1
-    centred = all(p.get("window", "centred") == "centred" for p in problems)
     nonuniform_small = all(p.get("x") is None or p["N"] <= 512 for p in problems)
-    if centred and nonuniform_small:
+    if nonuniform_small:
         return lmep.LMEP_F_PERSISTENT, (args.steps_per_launch or 8)
     return 0, 1
+
+
+def upwind_sweep(stencils=(7, 9, 11, 13, 15), N=2 ** 20, transit=1.0 / 8.0):
+    """Sec. 4.1's efficiency claim for one-sided stencils: advection over a
+    fixed time (the signal crosses `transit` of the periodic domain) at
+    Courant number n/2, 8 steps per launch.  The steps needed fall like 1/n
+    while the work per step grows like n, so the time to the final time
+    should not grow with n.  One warm-up run per n, then one timed run."""
+    import torch
+    import paper_2603_15964_amd as lmep
+    import workloads
+    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, 8)
+    rows = []
+    for n in stencils:
+        p, u0 = workloads.upwind_advection(n=n, N=N)
+        steps = int(math.ceil(transit / p["dt"]))
+        b = lmep.Batch([p], device="cuda:0")
+        w = b.empty_weights()
+        u = b.pack([u0])
+        out = b.empty_state()
+        b.build_weights(w, u)
+        b.step(w, u, steps, lmep.LMEP_F_PERSISTENT, u_out=out)  # warm-up, plans
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(w, u, steps, lmep.LMEP_F_PERSISTENT, u_out=out)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        rows.append({"n": n, "courant": p["dt"] / p["h"], "steps": steps, "ms": secs * 1e3,
+                     "us_per_step": secs * 1e6 / steps, "node_steps_per_s": N * steps / secs})
+    for r in rows:
+        r["time_vs_first"] = r["ms"] / rows[0]["ms"]
+    return {"workload": f"linear advection N={N} periodic, one-sided stencils at Courant n/2, final time "
+                        f"{transit} of a transit, 8 steps per launch",
+            "rows": rows}
 
 
 def adjoint_line(problems, states, args):

@@ -184,6 +184,24 @@ def burgers_upwind(N: int = 65536, n: int = 7, nu: float = 2.5e-3, cfl: float = 
     return p, u0
 
 
+def upwind_advection(n: int = 15, N: int = 2 ** 20, sigma: float = 0.5, modes: int = 8,
+                     seed: int = BASE_SEED + 7):
+    """Linear advection u_t + u_x = 0 on fully one-sided stencils at the
+    Courant numbers of Sec. 4.1's efficiency runs, nu = (n+1)/2 - sigma
+    (sigma = 1/2: departure points half-way between nodes): periodic [0, 1),
+    u0 a sum of 8 sine modes with amplitudes N(0, 1/k^2) and phases U[0, 2pi).
+    dt = nu h grows with n, so a fixed final time takes fewer steps."""
+    h = 1.0 / N
+    x = h * np.arange(N)
+    g = rng(seed)
+    a = g.normal(0.0, 1.0, modes) / np.arange(1, modes + 1)
+    ph = g.uniform(0.0, 2.0 * math.pi, modes)
+    u0 = sum(a[k - 1] * np.sin(2.0 * math.pi * k * x + ph[k - 1]) for k in range(1, modes + 1))
+    cfl = (n + 1) / 2 - sigma
+    p = make_problem(N=N, n=n, bc="periodic", h=h, dt=cfl * h, c=1.0, scheme="linear", window="upwind")
+    return p, u0
+
+
 # ---------------------------------------- Chebyshev grids (next row) -----
 def chebyshev(N: int) -> np.ndarray:
     """Chebyshev points of the second kind on [-1, 1], increasing."""
