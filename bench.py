@@ -3,7 +3,7 @@
 Default workload: the batched path -- 4096 independent Allen-Cahn instances
 (N_k uniform in [512, 65536], stencil n_k in {5, 7, 9, 11}, periodic or Neumann
 ends, ETD1 with phi1 weights of the augmented local matrix built once per
-instance) advanced 8 steps per launch.  A "step" is one time step of the whole
+instance) advanced 16 steps per launch.  A "step" is one time step of the whole
 hot path for every instance: the weights are stationary, so after the first
 build a step is the banded apply.
 
@@ -454,10 +454,15 @@ def kernel_work(name, problems, steps):
     if base == "build_taylor_kernel":
         g = group(lambda p: frozen(p) and p["n"] == v[0])
         return "alu", taylor_flops(v[0], v[1]) * sum(p["N"] for p in g) * steps, "flop"
-    if base in ("stepk_kernel", "stepk_rk4_kernel"):
-        if base == "stepk_kernel":
+    if base in ("stepk_kernel", "stepk_upwind_kernel", "stepk_rk4_kernel"):
+        def side(p):
+            if p.get("window", "centred") != "upwind" or p.get("c", 0.0) == 0.0:
+                return 0
+            return 1 if p["c"] > 0 else 2
+        if base != "stepk_rk4_kernel":
+            want = v[4] if base == "stepk_upwind_kernel" else 0
             g = group(lambda p: p["n"] == v[0] and SCHEME_ID[p["scheme"]] == v[1] and nl_id(p) == v[2]
-                      and not frozen(p) and p.get("x") is None)
+                      and not frozen(p) and p.get("x") is None and side(p) == want)
         else:
             g = group(lambda p: p["n"] == v[0] and p["scheme"] == "etdrk4")
         return "alu", sum(stationary_flops(p) * p["N"] for p in g) * steps, "flop"
@@ -570,7 +575,7 @@ def main():
                     help="auto: several steps per launch wherever the multi-step kernels cover the workload; "
                          "--persistent is the same as --launch persistent")
     ap.add_argument("--persistent", action="store_true", help="advance several steps per launch")
-    ap.add_argument("--steps-per-launch", type=int, default=None, choices=(1, 2, 4, 8))
+    ap.add_argument("--steps-per-launch", type=int, default=None, choices=(1, 2, 4, 8, 16))
     ap.add_argument("--tune", action="store_true",
                     help="let the autotuner pick the launch configuration (cached per GPU and shape)")
     ap.add_argument("--exp-method", choices=("auto", "pade"), default="auto",
@@ -668,7 +673,7 @@ def main():
 def launch_choice(problems, args):
     """(flags, steps per launch): several steps per launch wherever the
     multi-step kernels cover every instance (stationary weights, centred or
-    one-sided windows;
+    one-sided windows, 16 per launch;
     frozen velocity by the finite-Taylor kernel on Dirichlet or periodic grids
     under 2^20 nodes -- larger batches fill the GPU in one step), else one."""
     import paper_2603_15964_amd as lmep
@@ -694,20 +699,24 @@ def launch_choice(problems, args):
         return 0, 1
     nonuniform_small = all(p.get("x") is None or p["N"] <= 512 for p in problems)
     if nonuniform_small:
-        return lmep.LMEP_F_PERSISTENT, (args.steps_per_launch or 8)
+        # 16 steps per launch for stationary weights: the launch's HBM pass costs
+        # about as much as two steps of the n = 11 kernel, and the wider halo
+        # (8 (n - 1) per side for ETD1) is still small beside the 2048-position
+        # region (ETDRK4 groups take 8)
+        return lmep.LMEP_F_PERSISTENT, (args.steps_per_launch or 16)
     return 0, 1
 
 
-def upwind_sweep(stencils=(7, 9, 11, 13, 15), N=2 ** 20, transit=1.0 / 8.0):
+def upwind_sweep(stencils=(7, 9, 11, 13, 15), N=2 ** 20, transit=1.0 / 8.0, kb=16):
     """Sec. 4.1's efficiency claim for one-sided stencils: advection over a
     fixed time (the signal crosses `transit` of the periodic domain) at
-    Courant number n/2, 8 steps per launch.  The steps needed fall like 1/n
+    Courant number n/2, kb steps per launch.  The steps needed fall like 1/n
     while the work per step grows like n, so the time to the final time
     should not grow with n.  One warm-up run per n, then one timed run."""
     import torch
     import paper_2603_15964_amd as lmep
     import workloads
-    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, 8)
+    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
     rows = []
     for n in stencils:
         p, u0 = workloads.upwind_advection(n=n, N=N)
@@ -727,8 +736,9 @@ def upwind_sweep(stencils=(7, 9, 11, 13, 15), N=2 ** 20, transit=1.0 / 8.0):
                      "us_per_step": secs * 1e6 / steps, "node_steps_per_s": N * steps / secs})
     for r in rows:
         r["time_vs_first"] = r["ms"] / rows[0]["ms"]
+    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, 8)
     return {"workload": f"linear advection N={N} periodic, one-sided stencils at Courant n/2, final time "
-                        f"{transit} of a transit, 8 steps per launch",
+                        f"{transit} of a transit, {kb} steps per launch",
             "rows": rows}
 
 

@@ -293,9 +293,11 @@ const char* lmep_last_error(void);
 
 /* Process-wide tuning options (read at each lmep_step call).
  *  LMEP_OPT_STEPS_PER_LAUNCH  steps advanced per launch under
- *                             LMEP_F_PERSISTENT: 1, 2, 4 or 8 (default 8).  More
- *                             steps mean less HBM traffic but a wider halo
- *                             recomputed by every block.
+ *                             LMEP_F_PERSISTENT: 1, 2, 4, 8 or 16 (default 8).
+ *                             More steps mean less HBM traffic but a wider halo
+ *                             recomputed by every block.  Frozen-velocity and
+ *                             ETDRK4 groups take at most 8 (each kernel group
+ *                             of a batch advances its own number per launch).
  *  LMEP_OPT_PROFILE_ADJOINT   1: every lmep_adjoint_step records HIP events
  *                             around its Frechet-derivative kernel(s) and
  *                             around the whole step on its stream, then
@@ -334,6 +336,14 @@ const char* lmep_last_error(void);
  *                             the Pade path's.  Other instances: Pade.
  *                             LMEP_EXP_PADE: Pade scaling-and-squaring for
  *                             every instance.  The two agree to rounding.
+ *  LMEP_OPT_TAYLOR_REGION     positions staged per block (= threads) by the
+ *                             frozen-velocity multi-step kernel: 0 (default)
+ *                             sizes it from the group (about one block per CU
+ *                             for small groups, 512 for large ones); a
+ *                             multiple of 64 in [128, 512] forces it, raised
+ *                             where the halo would leave fewer than 64
+ *                             written nodes per block.  Results do not
+ *                             depend on it.
  * lmep_set_option returns LMEP_OK or LMEP_ERR_ARG (unknown option or value);
  * lmep_get_option returns the value or LMEP_ERR_ARG. */
 #define LMEP_OPT_STEPS_PER_LAUNCH 1
@@ -341,6 +351,7 @@ const char* lmep_last_error(void);
 #define LMEP_OPT_FUSE_FROZEN 3
 #define LMEP_OPT_APPLY_TILE 4
 #define LMEP_OPT_EXP_METHOD 5
+#define LMEP_OPT_TAYLOR_REGION 6
 #define LMEP_EXP_AUTO 0
 #define LMEP_EXP_PADE 1
 int lmep_set_option(int32_t option, int32_t value);

@@ -54,9 +54,10 @@ struct Opts {
     int fuse_frozen = 1;        // LMEP_OPT_FUSE_FROZEN
     int apply_tile = 0;         // LMEP_OPT_APPLY_TILE (0 = by size)
     int exp_method = LMEP_EXP_AUTO;  // LMEP_OPT_EXP_METHOD
+    int taylor_region = 0;      // LMEP_OPT_TAYLOR_REGION (0 = by size)
 };
 std::atomic<int> g_steps_per_launch{8}, g_profile_adjoint{0}, g_fuse_frozen{1}, g_apply_tile{0},
-    g_exp_method{LMEP_EXP_AUTO};
+    g_exp_method{LMEP_EXP_AUTO}, g_taylor_region{0};
 
 Opts process_opts() {
     Opts o;
@@ -65,6 +66,7 @@ Opts process_opts() {
     o.fuse_frozen = g_fuse_frozen.load();
     o.apply_tile = g_apply_tile.load();
     o.exp_method = g_exp_method.load();
+    o.taylor_region = g_taylor_region.load();
     return o;
 }
 
@@ -86,8 +88,8 @@ int fail(int code, const char* fmt, ...) {
 int set_opt(Opts& o, int32_t option, int32_t value) {
     switch (option) {
         case LMEP_OPT_STEPS_PER_LAUNCH:
-            if (value != 1 && value != 2 && value != 4 && value != 8)
-                return fail(LMEP_ERR_ARG, "steps per launch must be 1, 2, 4 or 8, got %d", value);
+            if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+                return fail(LMEP_ERR_ARG, "steps per launch must be 1, 2, 4, 8 or 16, got %d", value);
             o.steps_per_launch = value;
             return LMEP_OK;
         case LMEP_OPT_PROFILE_ADJOINT:
@@ -106,6 +108,12 @@ int set_opt(Opts& o, int32_t option, int32_t value) {
                 return fail(LMEP_ERR_ARG, "apply tile must be 0, 64, %d or %d, got %d", kApplyTileSmall, kApplyTile,
                             value);
             o.apply_tile = value;
+            return LMEP_OK;
+        case LMEP_OPT_TAYLOR_REGION:
+            if (value != 0 && (value < 128 || value > kTaylorRegion || value % 64 != 0))
+                return fail(LMEP_ERR_ARG, "finite-Taylor region must be 0 or a multiple of 64 in [128, %d], got %d",
+                            kTaylorRegion, value);
+            o.taylor_region = value;
             return LMEP_OK;
         default: return fail(LMEP_ERR_ARG, "unknown option %d", option);
     }
@@ -300,6 +308,7 @@ DevProb to_dev(const lmep_problem& q, int index) {
 struct Group {
     int n = 0, p = 0, scheme = 0, nonlin = 0, tile = 0;
     int reg = 0;             // multi-step finite-Taylor groups: staged positions per block
+    int kb = 1;              // steps per launch of the group's multi-step kernel
     bool taylor = false;     // build by finite Taylor series (items = kTaylorTile-node tiles)
     bool dd = false;         // ... carried in double-double (frozen one-sided windows)
     bool ddtable = false;    // stationary one-sided table in double-double (items = rows)
@@ -369,6 +378,7 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         g.dd = std::get<2>(kv.first) == 3;
         g.ddtable = std::get<2>(kv.first) == 4;
         for (const Part& part : kv.second) g.nodes += prob[part.k].N;
+        if (g.taylor && frozen_kb > 0) g.kb = std::min(frozen_kb, kTaylorMaxKb);
         if (g.taylor && frozen_kb > 0) {
             // staged positions per block (= threads): about one block per CU for
             // groups too small to fill the GPU -- a step then costs the latency of
@@ -376,9 +386,13 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             // CUs -- and the full region for larger ones
             bool upwind = false;
             for (const Part& part : kv.second) upwind |= prob[part.k].window == LMEP_WIN_UPWIND;
-            const int64_t halo = (int64_t)frozen_kb * taylor_stepk_reach(g.n, upwind);
+            const int64_t halo = (int64_t)g.kb * taylor_stepk_reach(g.n, upwind);
             const int64_t want_tile = std::max<int64_t>((g.nodes + cu_count() - 1) / cu_count(), 64);
             g.reg = (int)std::min<int64_t>((want_tile + 2 * halo + 63) / 64 * 64, kTaylorRegion);
+            // a forced region, raised where it would write fewer than 64 nodes per block
+            if (o.taylor_region > 0)
+                g.reg = (int)std::min<int64_t>(std::max<int64_t>(o.taylor_region, (64 + 2 * halo + 63) / 64 * 64),
+                                               kTaylorRegion);
         }
         g.first = (int)tab.size();
         int64_t items = 0;
@@ -388,7 +402,7 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             d.harvest = part.harvest;
             if (part.harvest == HARVEST_RK4_HALF) d.dt = 0.5 * prob[part.k].dt;
             d.item_begin = items;
-            const int64_t tt = frozen_kb > 0 ? taylor_stepk_tile(g.n, frozen_kb, g.reg,
+            const int64_t tt = frozen_kb > 0 ? taylor_stepk_tile(g.n, g.kb, g.reg,
                                                                  prob[part.k].window == LMEP_WIN_UPWIND)
                                              : kTaylorTile;
             items += g.taylor ? (prob[part.k].N + tt - 1) / tt
@@ -436,9 +450,10 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
                                    (g.nonlin == LMEP_NL_NONE || g.nonlin == LMEP_NL_ALLEN_CAHN);
         g.resident = multi_kb > 0 && (g.nonuniform || small_uniform);
         g.stepk = !g.resident && !g.nonuniform && (multi_kb > 0 || g.scheme == LMEP_ETDRK4);
+        if (g.stepk && multi_kb > 0) g.kb = g.scheme == LMEP_ETDRK4 ? std::min(multi_kb, kStepRk4MaxKb) : multi_kb;
         const int64_t avg = g.nodes / (int64_t)kv.second.size();
         const int forced = o.apply_tile;  // 0, 64 (non-uniform groups only), 256 or 1024
-        g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, multi_kb > 0 ? multi_kb : 1)
+        g.tile = g.stepk ? stepk_tile(g.n, g.scheme, g.nonlin, g.kb)
                  : (forced != 0 && (forced != kApplyTileTiny || g.nonuniform))
                      ? forced
                      : (g.nonuniform && avg <= kApplyTileTiny)
@@ -463,7 +478,7 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
 // Names of the kernels a group launches, as a kernel trace shows them
 // (namespace and argument list left out).
 std::string bool_s(bool b) { return b ? "true" : "false"; }
-std::string build_kernel_name(const Group& g, bool fused, bool multi, int kb) {
+std::string build_kernel_name(const Group& g, bool fused, bool multi) {
     char b[96];
     if (g.wide) return "build_wide_kernel";
     const char* dd = g.dd ? "_dd" : "";
@@ -471,10 +486,10 @@ std::string build_kernel_name(const Group& g, bool fused, bool multi, int kb) {
     else if (g.taylor && multi) snprintf(b, sizeof(b), "taylor_stepk%s_kernel<%d>", dd, g.n);
     else if (g.taylor) snprintf(b, sizeof(b), "build_taylor%s_kernel<%d,%s>", dd, g.n, bool_s(fused).c_str());
     else snprintf(b, sizeof(b), "build_pade_kernel<%d,%d,%s>", g.n, g.p, bool_s(fused).c_str());
-    (void)kb;
     return b;
 }
-std::string apply_kernel_name(const Group& g, int kb) {
+std::string apply_kernel_name(const Group& g) {
+    const int kb = g.kb;
     char b[96];
     const int nl = g.scheme == LMEP_LINEAR ? 0 : g.nonlin;
     if (g.stepk && g.scheme == LMEP_ETDRK4) snprintf(b, sizeof(b), "stepk_rk4_kernel<%d,%d,%d>", g.n, g.nonlin, kb);
@@ -720,8 +735,16 @@ std::vector<Piece> step_pieces(const StepPlan& P) {
             {P.L.tile_inst, P.tile_inst.size() * sizeof(int), P.tile_inst.data()}};
 }
 
-// Apply-kernel launches per group for n_steps steps.
-int step_launches(const StepPlan& P, int n_steps) { return P.all_resident ? 1 : (n_steps + P.kb - 1) / P.kb; }
+// Launches of a group for n_steps steps: one per kb steps (the resident
+// kernel: one, which runs them all), and the most of any group.
+int group_launches(const Group& g, int n_steps) { return g.resident ? 1 : (n_steps + g.kb - 1) / g.kb; }
+int step_launches(const StepPlan& P, int n_steps) {
+    int l = 1;
+    for (auto& g : P.bgroups) l = std::max(l, group_launches(g, n_steps));
+    for (auto& g : P.agroups)
+        if (!(g.frozen && P.fuse)) l = std::max(l, group_launches(g, n_steps));
+    return l;
+}
 
 // The launch sequence of n_steps steps (kernels only: capturable).
 int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double* tay, const double* tdd, double* d_w,
@@ -732,7 +755,6 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
     const int* dti = (const int*)(base + P.L.tile_inst);
     double* bufA = (double*)(base + P.L.state);
     const int launches = step_launches(P, n_steps);
-    const int kb = P.kb;
     hipError_t e = hipSuccess;
     // When a step runs a single kernel, its launches follow each other with
     // nothing between them: one pair of events spans them all (events around
@@ -741,17 +763,25 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
     for (auto& gr : P.agroups) per_round += !(gr.frozen && P.fuse);
     const bool one_span = per_round == 1;
     int span = -1;
-    // destinations alternate between the scratch state and d_u_out so that
-    // the last step lands in d_u_out and no step works in place
+    // Round st launches every group that still has steps to go.  Each
+    // group's destinations alternate between the scratch state and d_u_out
+    // so that its last launch lands in d_u_out and none works in place
+    // (groups own disjoint parts of both).
+    auto src_of = [&](int st, int lg) -> const double* {
+        return (st == 0) ? d_u_in : (((lg - st) % 2 == 0) ? d_u_out : bufA);
+    };
+    auto dst_of = [&](int st, int lg) -> double* { return ((lg - 1 - st) % 2 == 0) ? d_u_out : bufA; };
     for (int st = 0; st < launches; ++st) {
-        const double* src = (st == 0) ? d_u_in : (((launches - st) % 2 == 0) ? d_u_out : bufA);
-        double* dst = ((launches - 1 - st) % 2 == 0) ? d_u_out : bufA;
         // frozen-velocity groups: weights rebuilt, and with fusion applied in
         // the same kernel (their apply groups are then skipped)
         for (auto& gr : P.bgroups) {
+            const int lg = group_launches(gr, n_steps), kb = gr.kb;
+            if (st >= lg) continue;
+            const double* src = src_of(st, lg);
+            double* dst = dst_of(st, lg);
             int t = -1;
             if (timer.on && (!one_span || st == 0)) {
-                t = timer.begin(build_kernel_name(gr, P.fuse, P.multi, kb), true, s, e);
+                t = timer.begin(build_kernel_name(gr, P.fuse, P.multi), true, s, e);
                 HIP_TRY(e);
                 if (one_span) span = t;
             }
@@ -770,10 +800,13 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
         int64_t tile0 = 0;
         for (auto& gr : P.agroups) {
             const bool fused = gr.frozen && P.fuse;  // already advanced by its build kernel
-            if (!fused) {
+            const int lg = group_launches(gr, n_steps), kb = gr.kb;
+            if (!fused && st < lg) {
+                const double* src = src_of(st, lg);
+                double* dst = dst_of(st, lg);
                 int t = -1;
                 if (timer.on && (!one_span || st == 0)) {
-                    t = timer.begin(apply_kernel_name(gr, kb), false, s, e);
+                    t = timer.begin(apply_kernel_name(gr), false, s, e);
                     HIP_TRY(e);
                     if (one_span) span = t;
                 }
@@ -1183,6 +1216,7 @@ int lmep_set_option(int32_t option, int32_t value) {
     g_fuse_frozen.store(o.fuse_frozen);
     g_apply_tile.store(o.apply_tile);
     g_exp_method.store(o.exp_method);
+    g_taylor_region.store(o.taylor_region);
     return LMEP_OK;
 }
 
@@ -1194,6 +1228,7 @@ int32_t lmep_get_option(int32_t option) {
         case LMEP_OPT_FUSE_FROZEN: return o.fuse_frozen;
         case LMEP_OPT_APPLY_TILE: return o.apply_tile;
         case LMEP_OPT_EXP_METHOD: return o.exp_method;
+        case LMEP_OPT_TAYLOR_REGION: return o.taylor_region;
         default: return fail(LMEP_ERR_ARG, "unknown option %d", option);
     }
 }

@@ -101,6 +101,7 @@ hipError_t launch_build_taylor(int n, const DevProb* d_probs, int nprob, int64_t
 // one-sided ones (the window and the derivative at its positions each reach
 // that far to one side).
 constexpr int kTaylorRegion = 512;
+constexpr int kTaylorMaxKb = 8;  // steps per launch of the frozen-velocity multi-step kernel, at most
 __host__ __device__ constexpr int taylor_stepk_reach(int n, bool upwind) { return upwind ? 2 * (n - 1) : n - 1; }
 __host__ __device__ constexpr int taylor_stepk_tile(int n, int kb, int reg, bool upwind) {
     return reg - 2 * kb * taylor_stepk_reach(n, upwind);
@@ -154,8 +155,10 @@ hipError_t launch_apply_nonuniform(int n, int tile, int scheme, int nonlin, cons
 // kStepRegion consecutive positions of its instance, advances them `ksteps`
 // <= kb steps in LDS (kb = 1, 2, 4 or 8) and writes the middle
 // stepk_tile(...) of them; the rest is the halo the steps consume (each
-// stencil application spoils (n-1)/2 positions at each open end).
+// stencil application spoils (n-1)/2 positions at each open end); kb = 16
+// for the ETD schemes.
 constexpr int kStepRegion = 2048;
+constexpr int kStepRk4MaxKb = 8;  // ETDRK4 multi-step launches: at most 8 steps (the stationary ETD kernels 16)
 __host__ __device__ constexpr int stepk_apps(int scheme, int nonlin) {
     // stencil applications per step: one per stage, one more per KdV N pass
     return (scheme == SCH_ETDRK4 && nonlin != NL_NONE ? 4 : (scheme == SCH_ETD2RK && nonlin != NL_NONE ? 2 : 1)) *
@@ -167,7 +170,7 @@ __host__ __device__ constexpr int stepk_halo(int n, int scheme, int nonlin, int 
 __host__ __device__ constexpr int stepk_tile(int n, int scheme, int nonlin, int kb) {
     return kStepRegion - 2 * stepk_halo(n, scheme, nonlin, kb);
 }
-static_assert(stepk_tile(15, SCH_ETD2RK, NL_KDV, 8) >= 1024, "halo too wide for the staged region");
+static_assert(stepk_tile(15, SCH_ETD2RK, NL_KDV, 16) >= 1024, "halo too wide for the staged region");
 static_assert(stepk_tile(13, SCH_ETDRK4, NL_KDV, 8) >= 1024, "halo too wide for the staged region");
 template <int KB>
 hipError_t launch_stepk_depth(int n, int scheme, int nonlin, int ksteps, const DevProb* d_probs,

@@ -15,6 +15,7 @@ hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const
             case 2: return launch_stepk_upwind_depth<2>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
             case 4: return launch_stepk_upwind_depth<4>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
             case 8: return launch_stepk_upwind_depth<8>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+            case 16: return launch_stepk_upwind_depth<16>(side, n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
             default: return hipErrorInvalidValue;
         }
     }
@@ -23,6 +24,7 @@ hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const
         case 2: return launch_stepk_depth<2>(n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
         case 4: return launch_stepk_depth<4>(n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
         case 8: return launch_stepk_depth<8>(n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 16: return launch_stepk_depth<16>(n, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
         default: return hipErrorInvalidValue;
     }
 }

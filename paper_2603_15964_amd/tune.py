@@ -6,12 +6,19 @@ keeps the fastest one whose result agrees with the default path:
 * frozen-velocity instances: the fused build-and-apply kernel or the
   build-then-apply pair (LMEP_OPT_FUSE_FROZEN), each with the finite-Taylor
   or the Pade exponential (LMEP_OPT_EXP_METHOD);
-* one step per launch, or LMEP_F_PERSISTENT with 1, 2, 4 or 8 steps per
+* one step per launch, or LMEP_F_PERSISTENT with 1, 2, 4, 8 or 16 steps per
   launch (LMEP_OPT_STEPS_PER_LAUNCH; non-uniform instances held whole by a
   block run every step in one launch; frozen-velocity instances through the
-  finite-Taylor multi-step kernel);
+  finite-Taylor multi-step kernel, at most 8 steps per launch, whose region
+  size -- the positions a block stages, LMEP_OPT_TAYLOR_REGION -- is sized
+  from the group or forced to 256 or 512);
 * one-step launches: the apply tile, chosen by size or forced to 256 / 1024
   nodes (LMEP_OPT_APPLY_TILE).
+
+Not offered: merging kernel groups of different stencil sizes into one
+launch (each kernel is specialised on n; the groups of a batch are launched
+back to back on one stream) and several lanes per node in the frozen-velocity
+kernel (measured slower).
 
 Choices are cached in a JSON file keyed by the GPU architecture and a
 signature of the batch (per kernel group: stencil size, scheme, nonlinearity,
@@ -28,10 +35,12 @@ import os
 from dataclasses import dataclass, field
 
 from ._native import (LMEP_EXP_AUTO, LMEP_EXP_PADE, LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE, LMEP_OPT_EXP_METHOD,
-                      LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, lmep_get_option, lmep_set_option)
+                      LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_TAYLOR_REGION, lmep_get_option,
+                      lmep_set_option)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2603_15964_amd", "tune.json")
-_OPTIONS = (LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_APPLY_TILE, LMEP_OPT_EXP_METHOD)
+_OPTIONS = (LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_APPLY_TILE, LMEP_OPT_EXP_METHOD,
+            LMEP_OPT_TAYLOR_REGION)
 
 
 @dataclass(frozen=True)
@@ -49,7 +58,8 @@ class Choice:
 
     def describe(self):
         names = {LMEP_OPT_FUSE_FROZEN: "fuse_frozen", LMEP_OPT_STEPS_PER_LAUNCH: "steps_per_launch",
-                 LMEP_OPT_APPLY_TILE: "apply_tile", LMEP_OPT_EXP_METHOD: "exp_method"}
+                 LMEP_OPT_APPLY_TILE: "apply_tile", LMEP_OPT_EXP_METHOD: "exp_method",
+                 LMEP_OPT_TAYLOR_REGION: "taylor_region"}
         d = {names[a]: b for a, b in self.options}
         d["persistent"] = bool(self.flags & LMEP_F_PERSISTENT)
         return d
@@ -85,12 +95,13 @@ def signature(problems) -> str:
 def candidates(problems):
     """Every configuration the library accepts for this batch."""
     frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
-    # several steps per launch: stationary weights on centred windows (non-uniform
-    # instances held whole by a block); frozen velocity through the finite-Taylor
-    # multi-step kernel (no reaction term, Dirichlet or periodic, either window)
+    # several steps per launch: stationary weights (non-uniform instances held
+    # whole by a block); frozen velocity through the finite-Taylor multi-step
+    # kernel (no reaction term, Dirichlet or periodic, either window)
     persistent_ok = all(p.get("x") is None or int(p["N"]) <= 512 for p in problems) and \
-        all((p["bc"] != "neumann" and p.get("react", 0.0) == 0.0) if p.get("nonlin") == "burgers_frozen"
-            else p.get("window", "centred") == "centred" for p in problems)
+        all(p["bc"] != "neumann" and p.get("react", 0.0) == 0.0 for p in problems
+            if p.get("nonlin") == "burgers_frozen")
+    stationary = any(p.get("nonlin") != "burgers_frozen" for p in problems)
     nonuniform = any(p.get("x") is not None for p in problems)
     tiles = (0, 256, 1024) + ((64,) if nonuniform else ())
     out = []
@@ -102,10 +113,14 @@ def candidates(problems):
                 out.append(Choice(0, ((LMEP_OPT_FUSE_FROZEN, fuse), (LMEP_OPT_STEPS_PER_LAUNCH, 8),
                                       (LMEP_OPT_APPLY_TILE, tile), (LMEP_OPT_EXP_METHOD, method))))
     if persistent_ok:
-        kbs = (8,) if (nonuniform and all(p.get("x") is not None for p in problems)) else (1, 2, 4, 8)
+        kbs = (8,) if (nonuniform and all(p.get("x") is not None for p in problems)) else \
+            ((1, 2, 4, 8, 16) if stationary else (1, 2, 4, 8))
+        regions = (0, 256, 512) if frozen else (0,)
         for kb in kbs:
-            out.append(Choice(LMEP_F_PERSISTENT, ((LMEP_OPT_FUSE_FROZEN, 1), (LMEP_OPT_STEPS_PER_LAUNCH, kb),
-                                                  (LMEP_OPT_APPLY_TILE, 0), (LMEP_OPT_EXP_METHOD, LMEP_EXP_AUTO))))
+            for reg in regions:
+                opts = ((LMEP_OPT_FUSE_FROZEN, 1), (LMEP_OPT_STEPS_PER_LAUNCH, kb), (LMEP_OPT_APPLY_TILE, 0),
+                        (LMEP_OPT_EXP_METHOD, LMEP_EXP_AUTO))
+                out.append(Choice(LMEP_F_PERSISTENT, opts + (((LMEP_OPT_TAYLOR_REGION, reg),) if frozen else ())))
     return out
 
 

@@ -106,7 +106,7 @@ def test_multistep_flag_and_option():
     """LMEP_F_PERSISTENT is refused before any device work for frozen-velocity
     instances the multi-step finite-Taylor kernel does not cover (Neumann
     grids, a reaction term, the Pade method); the steps-per-launch option
-    accepts 1, 2, 4 and 8 only."""
+    accepts 1, 2, 4, 8 and 16 only."""
     lib = lmep.library()
     for over in (dict(bc="neumann"), dict(react=0.5)):
         s = _structs(**over)  # frozen-velocity Burgers
@@ -122,7 +122,7 @@ def test_multistep_flag_and_option():
         lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD, lmep.LMEP_EXP_AUTO)
     opt = lmep.LMEP_OPT_STEPS_PER_LAUNCH
     assert lmep.lmep_get_option(opt) == 8
-    for bad in (0, 3, 5, 16, -8):
+    for bad in (0, 3, 5, 32, -8):
         with pytest.raises(lmep.LmepError):
             lmep.lmep_set_option(opt, bad)
     with pytest.raises(lmep.LmepError):
@@ -134,6 +134,21 @@ def test_multistep_flag_and_option():
         assert lmep.lmep_get_option(opt) == 4
     finally:
         lmep.lmep_set_option(opt, 8)
+
+
+def test_taylor_region_option():
+    """LMEP_OPT_TAYLOR_REGION takes 0 or a multiple of 64 in [128, 512]."""
+    opt = lmep.LMEP_OPT_TAYLOR_REGION
+    assert lmep.lmep_get_option(opt) == 0
+    for bad in (-64, 64, 100, 576, 1024):
+        with pytest.raises(lmep.LmepError):
+            lmep.lmep_set_option(opt, bad)
+    try:
+        for good in (128, 320, 512):
+            lmep.lmep_set_option(opt, good)
+            assert lmep.lmep_get_option(opt) == good
+    finally:
+        lmep.lmep_set_option(opt, 0)
 
 
 def test_exp_method_option():

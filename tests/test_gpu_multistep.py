@@ -1,6 +1,6 @@
 """Multi-step launches (LMEP_F_PERSISTENT) against the one-step path and the oracle.
 
-Each block of the multi-step kernel advances its tile of nodes up to 1, 2, 4 or 8
+Each block of the multi-step kernel advances its tile of nodes up to 1, 2, 4, 8 or 16
 steps in LDS, recomputing a halo instead of exchanging it.  It forms every
 value with the same expression as the one-step kernel, so the two paths must
 agree bit for bit; both are also checked against the CPU oracle (1e-10
@@ -99,7 +99,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("kb", [1, 2, 4, 8])
+@pytest.mark.parametrize("kb", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_multistep_matches_one_step_and_oracle(name, make, kb):
     _print_case("multistep", name, "kb", kb)

@@ -1,6 +1,6 @@
 """Several steps per launch (LMEP_F_PERSISTENT) with stationary weights on
 one-sided (upwind) windows (Sec. 4.1): the multi-step kernel keeps its whole
-halo upstream of the tile.  Bit for bit the one-step path at 1, 2, 4 and 8
+halo upstream of the tile.  Bit for bit the one-step path at 1, 2, 4, 8 and 16
 steps per launch, for both flow directions, every boundary type, the
 pointwise and derivative nonlinearities, ragged last tiles and the last tile
 of a Dirichlet or Neumann instance that would start next to the end (it is
@@ -86,7 +86,7 @@ for n, scheme, nonlin in [(9, "linear", "none"), (5, "etd1", "allen_cahn"), (15,
 @pytest.mark.parametrize("n,scheme,nonlin,bc,sgn", CASES)
 def test_upwind_multistep_equals_one_step(n, scheme, nonlin, bc, sgn):
     """Instances whose last tile is ragged (N = 2 tiles + 1000) or starts
-    next to the end (N = tile + 2) at 8 steps per launch: 1, 2, 4 and 8 steps
+    next to the end (N = tile + 2) at 8 steps per launch: 1, 2, 4, 8 and 16 steps
     per launch equal one step per launch bit for bit over 11 steps."""
     cfl = _courant(n, bc, sgn)
     _case("upwind multistep", n, scheme, nonlin, bc, sgn)
@@ -95,7 +95,7 @@ def test_upwind_multistep_equals_one_step(n, scheme, nonlin, bc, sgn):
     want = _run(list(probs), list(states), 11, 0)
     for k, wv in enumerate(want):
         assert np.all(np.isfinite(wv)), k
-    for kb in (1, 2, 4, 8):
+    for kb in (1, 2, 4, 8, 16):
         got = _run(list(probs), list(states), 11, lmep.LMEP_F_PERSISTENT, kb)
         for k, (g, wv) in enumerate(zip(got, want)):
             assert np.array_equal(g, wv), (kb, k)

@@ -10,7 +10,8 @@ import numpy as np
 import workloads
 from paper_2603_15964_amd import tune
 from paper_2603_15964_amd._native import (LMEP_EXP_AUTO, LMEP_EXP_PADE, LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE,
-                                          LMEP_OPT_EXP_METHOD, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH)
+                                          LMEP_OPT_EXP_METHOD, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH,
+                                          LMEP_OPT_TAYLOR_REGION)
 
 
 def _opts(c):
@@ -35,20 +36,23 @@ def test_candidates_follow_what_the_library_accepts():
     assert {_opts(x)[LMEP_OPT_FUSE_FROZEN] for x in c} == {0, 1}
     assert {_opts(x)[LMEP_OPT_EXP_METHOD] for x in c} == {LMEP_EXP_AUTO, LMEP_EXP_PADE}
     assert _opts(c[0])[LMEP_OPT_EXP_METHOD] == LMEP_EXP_AUTO  # the default comes first (reference result)
-    # frozen velocity several steps per launch: the finite-Taylor multi-step kernel only
+    # frozen velocity several steps per launch: the finite-Taylor multi-step
+    # kernel only, at most 8 steps, with its region sized or forced
     pers = [x for x in c if x.flags & LMEP_F_PERSISTENT]
     assert {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in pers} == {1, 2, 4, 8}
+    assert {_opts(x)[LMEP_OPT_TAYLOR_REGION] for x in pers} == {0, 256, 512}
     assert all(_opts(x)[LMEP_OPT_EXP_METHOD] == LMEP_EXP_AUTO for x in pers)
     neumann = [dict(frozen[0], bc="neumann")]
     assert not any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(neumann))
     stat = [workloads.kdv(N=4096)[0]]
     assert {_opts(x)[LMEP_OPT_EXP_METHOD] for x in tune.candidates(stat)} == {LMEP_EXP_AUTO}
     kbs = {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in tune.candidates(stat) if x.flags & LMEP_F_PERSISTENT}
-    assert kbs == {1, 2, 4, 8}
+    assert kbs == {1, 2, 4, 8, 16}
+    assert all(LMEP_OPT_TAYLOR_REGION not in _opts(x) for x in tune.candidates(stat))
     upwind = [workloads.burgers_upwind(N=1000)[0]]  # frozen velocity: the multi-step Taylor kernel takes it
     assert any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(upwind))
-    ac_upwind = [dict(workloads.allen_cahn_batch(count=1)[0][0], window="upwind")]
-    assert not any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(ac_upwind))
+    ac_upwind = [dict(workloads.allen_cahn_batch(count=1)[0][0], window="upwind")]  # one-sided stationary
+    assert any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(ac_upwind))
     cheb = [workloads.allen_cahn_chebyshev()[0]]
     cc = tune.candidates(cheb)
     assert sum(1 for x in cc if x.flags & LMEP_F_PERSISTENT) == 1
