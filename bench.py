@@ -673,7 +673,7 @@ def main():
 def launch_choice(problems, args):
     """(flags, steps per launch): several steps per launch wherever the
     multi-step kernels cover every instance (stationary weights, centred or
-    one-sided windows, 16 per launch;
+    one-sided windows, 16 or 8 per launch;
     frozen velocity by the finite-Taylor kernel on Dirichlet or periodic grids
     under 2^20 nodes -- larger batches fill the GPU in one step), else one."""
     import paper_2603_15964_amd as lmep
@@ -699,11 +699,19 @@ def launch_choice(problems, args):
         return 0, 1
     nonuniform_small = all(p.get("x") is None or p["N"] <= 512 for p in problems)
     if nonuniform_small:
-        # 16 steps per launch for stationary weights: the launch's HBM pass costs
-        # about as much as two steps of the n = 11 kernel, and the wider halo
-        # (8 (n - 1) per side for ETD1) is still small beside the 2048-position
-        # region (ETDRK4 groups take 8)
-        return lmep.LMEP_F_PERSISTENT, (args.steps_per_launch or 16)
+        # the deepest launch whose recomputed halo stays within 1/8 of the
+        # 2048-position region: 16 steps for ETD1 Allen-Cahn up to n = 15 (the
+        # launch's HBM pass costs about two steps of the n = 11 kernel), 8 for
+        # KdV's two stencil passes per stage (ETDRK4 groups take at most 8)
+        def halo(p, kb):
+            nl = p.get("nonlin", "none")
+            apps = (4 if p["scheme"] == "etdrk4" else 2) if (p["scheme"] in ("etd2rk", "etdrk4") and nl != "none") \
+                else 1
+            apps *= 2 if (p["scheme"] != "linear" and nl == "kdv") else 1
+            return kb * apps * ((int(p["n"]) - 1) // 2)
+        kb = args.steps_per_launch or next(k for k in (16, 8) if k == 8 or
+                                           all(2 * halo(p, k) <= 2048 // 8 for p in problems if p.get("x") is None))
+        return lmep.LMEP_F_PERSISTENT, kb
     return 0, 1
 
 
