@@ -1,4 +1,5 @@
-"""CPU models of the multi-step kernels' index arithmetic (no GPU).
+"""CPU models of the multi-step kernels' and the fused reverse step's index
+arithmetic (no GPU).
 
 The stationary multi-step kernel (stepk.hpp) stages a region of 2048
 positions, advances it up to 16 steps in LDS and writes its tile; the halo it
@@ -185,3 +186,166 @@ def test_model_finds_the_last_tile_error():
     assert bad
     bad, covered = check_instance(tile4 + 3, 9, "neumann", 2, "linear", "none", 4, 4)
     assert not bad and covered
+
+
+# --------------------------------------------------------------------------
+# The fused reverse step (adjoint_taylor.hip): one block of 256 weight
+# positions per tile of 256 - 4 (n - 1) nodes.  The model replays the
+# kernel's index arithmetic thread by thread: every LDS index in bounds, and
+# every value read is one that was staged or computed (a staged position the
+# load covered, a weight slot whose node was active, a ghat slot in the range
+# step 3 fills), for every stencil size, boundary type and tile position.
+
+ADJ_T = 256
+
+
+def _map_index(j, N, bc):
+    if bc == "periodic":
+        return j % N
+    if bc == "neumann":
+        j = -j if j < 0 else j
+        return 2 * (N - 1) - j if j > N - 1 else j
+    return j
+
+
+def _window_offset_c(i, N, n, bc):
+    o = -((n - 1) // 2)
+    if bc == "dirichlet":
+        o = max(o, -i)
+        o = min(o, N - n - i)
+    return o
+
+
+def _stencils_containing(j, N, n, bc):
+    R = (n - 1) // 2
+    ps = [j]
+    if bc == "neumann":
+        if 0 < j <= 2 * R:
+            ps.append(-j)
+        if N - 1 > j >= N - 1 - 2 * R:
+            ps.append(2 * (N - 1) - j)
+    out = []
+    for p in ps:
+        for d in range(-(n - 1), n):
+            x = p + d
+            i = x
+            if bc == "periodic":
+                i = _map_index(x, N, bc)
+            elif i < 0 or i > N - 1:
+                continue
+            if bc == "dirichlet" and i in (0, N - 1):
+                continue
+            k = -d - _window_offset_c(i, N, n, bc)
+            if 0 <= k < n:
+                out.append((x if bc == "periodic" else i, k))
+    return out
+
+
+def adj_tile_problems(N, n, bc, tile):
+    """Problems found in tile `tile` of an instance (empty: none)."""
+    T = ADJ_T
+    R = (n - 1) // 2
+    H = n - 1
+    HW = 2 * H
+    TO = T - 2 * HW
+    SU = T + 2 * H
+    t0 = tile * TO
+    base = t0 - HW
+    per, dr = bc == "periodic", bc == "dirichlet"
+    holds = lambda x: per or 0 <= x < N
+    errs = []
+    staged = []
+    for q in range(SU):
+        x = base - H + q
+        staged.append(per or ((0 <= x < N) if dr else (-(N - 1) <= x <= 2 * (N - 1))))
+    computed = [False] * T
+    for tid in range(T):  # step 2
+        x = base + tid
+        active = holds(x)
+        i = _map_index(x, N, bc) if active else (t0 if t0 < N else N - 1)
+        xs = x if active else i
+        us0 = xs - (base - H)
+        o = _window_offset_c(i, N, n, bc)
+        for j in [0] + [o + k for k in range(n)]:
+            if not 0 <= us0 + j < SU:
+                errs.append(("step2 bounds", tid))
+            elif active and not staged[us0 + j]:
+                errs.append(("step2 unstaged", tid))
+        computed[tid] = active
+
+    def weight_slot_ok(q):
+        return 0 <= q < T and computed[q] and 0 <= q + H < SU and staged[q + H]
+
+    ghat = [False] * T
+    for tid in range(H, T - H):  # step 3 (frozen-velocity ghat)
+        m = base + tid
+        if not holds(m):
+            ghat[tid] = True  # written as 0 and read only as such
+            continue
+        mi = _map_index(m, N, bc)
+        if mi >= 2 * (n - 1) and mi <= N - 1 - 2 * (n - 1):
+            terms = [(m + d, R - d) for d in range(-R, R + 1)]
+        else:
+            terms = _stencils_containing(m if per else mi, N, n, bc)
+        ok = True
+        for x, k in terms:
+            if not weight_slot_ok(x - base):
+                errs.append(("step3", tid, x))
+                ok = False
+        ghat[tid] = ok
+    for tid in range(TO):  # step 4
+        j = t0 + tid
+        if j >= N:
+            continue
+        qj = HW + tid
+        inner = j >= 2 * (n - 1) and j <= N - 1 - 2 * (n - 1)
+        terms = [(j + d, R - d) for d in range(-R, R + 1)] if inner else _stencils_containing(j, N, n, bc)
+        for x, k in terms:
+            if not weight_slot_ok(x - base):
+                errs.append(("step4 gather", tid, x))
+        if not (dr and j in (0, N - 1)):
+            o = _window_offset_c(j, N, n, bc)
+            for k in range(n):
+                s = qj + H + o + k
+                if not (0 <= s < SU and staged[s]):
+                    errs.append(("step4 own window", tid))
+        if inner:
+            slots = [qj + d for d in range(-R, R + 1)]
+        else:
+            ps = [j]
+            if bc == "neumann":
+                if 0 < j <= 2 * R:
+                    ps.append(-j)
+                if N - 1 > j >= N - 1 - 2 * R:
+                    ps.append(2 * (N - 1) - j)
+            slots = []
+            for p in ps:
+                for d in range(-(n - 1), n):
+                    x = p + d
+                    m = x
+                    if per:
+                        m = _map_index(x, N, bc)
+                    elif m < 0 or m > N - 1:
+                        continue
+                    l = -d - _window_offset_c(m, N, n, bc)
+                    if 0 <= l < n:
+                        slots.append((x if per else m) - base)
+        for s in slots:
+            if not (H <= s < T - H and ghat[s]):
+                errs.append(("step4 ghat", tid, s))
+    return errs
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet", "neumann"])
+def test_fused_reverse_step_indexing(bc):
+    failures = []
+    for n in (3, 5, 9, 15):
+        TO = ADJ_T - 4 * (n - 1)
+        for N in sorted({n, n + 1, 2 * n + 1, 4 * n, TO - 1, TO, TO + 1, TO + n, 2 * TO + 3}):
+            if N < n:
+                continue
+            for tile in range(-(-N // TO)):
+                e = adj_tile_problems(N, n, bc, tile)
+                if e:
+                    failures.append((n, N, tile, e[:3]))
+    assert not failures, failures[:3]
