@@ -92,6 +92,29 @@ def taylor_flops(n: int, fused: bool) -> float:
     return f
 
 
+def taylor_dd_flops(n: int, fused: bool) -> float:
+    """Algorithmic flops of one node of the double-double finite-Taylor build
+    (one-sided windows), each double-double operation counted by the FP64
+    flops it takes (fma = 2; two-sum 6, add 20, multiply 10, multiply by a
+    double 8, division by a double about 28 with the division counted as
+    one, fma 30): per order K = 1 .. n-1 the K + 1 moments (four products and
+    three adds each, the dispersion term carried too), their exponential and
+    phi1 sums, and the contraction of both rows with the table; then the
+    scaling and rounding of the rows, and with fusion the FP64 derivative and
+    stencil sum."""
+    add, mul, mul_d, div_d, fma = 20, 10, 8, 28, 30
+    f = 0.0
+    for K in range(1, n):
+        moments = K + 1
+        f += moments * (mul + (mul_d + add) + 2 * (mul + add))  # the recursion's terms
+        f += moments * (add + div_d + add)                       # E and F sums
+        f += 2 * n * fma                                         # W0, W1 contraction
+    f += 2 * n * (mul_d + 1)                                     # scaling and rounding
+    if fused:
+        f += 3.0 * n + 6.0 * n
+    return f
+
+
 def stationary_flops(p: dict) -> float:
     """Algorithmic flops of one node-step of the banded apply with stationary
     weights (multiply-add = 2): W0.u (+ W1.N) over the n-window, N itself
@@ -172,6 +195,10 @@ def make_workload(name: str):
         p, u0 = workloads.burgers_upwind()
         return [p], [u0], ("viscous Burgers N=65536 n=7 periodic on fully one-sided (upwind) stencils at "
                            "CFL 3.5, frozen-velocity ETD1, weights rebuilt every step")
+    if name == "burgers_upwind15":
+        p, u0 = workloads.burgers_upwind(n=15, cfl=7.5, amp=1e-4)
+        return [p], [u0], ("viscous Burgers N=65536 n=15 periodic on one-sided stencils at CFL 7.5 (velocity 1 +- 1e-4), "
+                           "frozen-velocity ETD1 with the weights in double-double, rebuilt every step")
     if name == "allen_cahn_chebyshev_batch":
         ps, us = workloads.allen_cahn_chebyshev_batch()
         return ps, us, ("8192 Allen-Cahn instances on the paper's Chebyshev grid (N=64, n=21), nu ~ U[0.005,0.01], "
@@ -451,6 +478,9 @@ def kernel_work(name, problems, steps):
     if base == "taylor_stepk_kernel":
         g = group(lambda p: frozen(p) and p["n"] == v[0])
         return "alu", taylor_flops(v[0], True) * sum(p["N"] for p in g) * steps, "flop"
+    if base == "build_taylor_dd_kernel":
+        g = group(lambda p: frozen(p) and p["n"] == v[0])
+        return "alu", taylor_dd_flops(v[0], v[1]) * sum(p["N"] for p in g) * steps, "flop"
     if base == "build_taylor_kernel":
         g = group(lambda p: frozen(p) and p["n"] == v[0])
         return "alu", taylor_flops(v[0], v[1]) * sum(p["N"] for p in g) * steps, "flop"

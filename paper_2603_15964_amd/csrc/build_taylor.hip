@@ -44,7 +44,7 @@
 // are written in the per-node layout.
 //
 // One-sided windows of 9 or more points take the same build in double-double
-// (build_taylor_dd_kernel, taylor_stepk_dd_kernel; the weight routine is in
+// (build_taylor_dd_kernel, one step per launch; the weight routine is in
 // taylor_dd.hpp), and so do stationary one-sided tables (build_table_dd_kernel).
 #include "lmep_device.hpp"
 #include "taylor_dd.hpp"
@@ -339,9 +339,7 @@ __global__ __launch_bounds__(kTaylorTile) void build_taylor_dd_kernel(const DevP
 // read their rows from there at every step instead of from global memory.
 // Elsewhere a wavefront's lanes part only where the shift or the window side
 // changes; those few read the table in global memory, which measured faster.
-// With DD the weights come from the double-double routine (one-sided windows
-// of 9 or more points) and the table block is not staged.
-template <int NN, bool DD>
+template <int NN>
 __device__ __forceinline__ void taylor_stepk_body(const DevProb* __restrict__ probs, int nprob, int kb, int ksteps,
                                                   int reg, const double* __restrict__ fd,
                                                   const double* __restrict__ taylor,
@@ -351,7 +349,7 @@ __device__ __forceinline__ void taylor_stepk_body(const DevProb* __restrict__ pr
     constexpr int H = NN - 1;
     constexpr int MAXR = kTaylorRegion;
     __shared__ double lds[3 * MAXR];  // current u, next u, derivative: addressed by offsets
-    __shared__ double lt[DD ? 1 : NN * NN * NN];  // this stencil size's table block
+    __shared__ double lt[NN * NN * NN];  // this stencil size's table block
     __shared__ double lfd[NN * NN];      // first-derivative rows of the clamped and one-sided windows
     const int REG = reg;
     const int nt = blockDim.x;  // threads: one staged position each per pass (normally nt = reg)
@@ -387,7 +385,7 @@ __device__ __forceinline__ void taylor_stepk_body(const DevProb* __restrict__ pr
     const int cd = 2 * MAXR;
     for (int t = tid; t < REG; t += nt)
         lds[cu + t] = (t >= g_lo && t < g_hi) ? us[map_index(v0 + t, N, bc)] : 0.0;
-    if (dir && !DD) stage_taylor_block<NN>(taylor, lt, tid, nt);
+    if (dir) stage_taylor_block<NN>(taylor, lt, tid, nt);
     for (int i = tid; i < NN * NN; i += nt) lfd[i] = fd[fd_index(NN, 0, i / NN, i % NN)] * ih;
     __syncthreads();
     int lo = g_lo, hi = g_hi;  // slots whose current u is valid
@@ -434,21 +432,14 @@ __device__ __forceinline__ void taylor_stepk_body(const DevProb* __restrict__ pr
             const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
             const int sh = (int)rint(half);
             double W0[NN], W1[NN];
+            if constexpr (HOIST)
+                node_weights<NN>(active, r, sh, disp, a, cf0, taylor, dir ? lt : nullptr, W0, W1);
+            else
+                node_weights<NN>(active, r, sh, disp, a, CoefAtUse{P.nu * ih * ih * dt, -P.delta * ih * ih * ih * dt},
+                                 taylor, dir ? lt : nullptr, W0, W1);
             const double w1s = -g * dt;  // as in the one-step kernel
-            if constexpr (DD) {
-                double W2[NN];
-                node_weights_dd<NN, 1>(r, sh, a, P.nu * ih * ih * dt, -P.delta * ih * ih * ih * dt, w1s, taylor, W0, W1,
-                                       W2);
-            } else {
-                if constexpr (HOIST)
-                    node_weights<NN>(active, r, sh, disp, a, cf0, taylor, dir ? lt : nullptr, W0, W1);
-                else
-                    node_weights<NN>(active, r, sh, disp, a,
-                                     CoefAtUse{P.nu * ih * ih * dt, -P.delta * ih * ih * ih * dt}, taylor,
-                                     dir ? lt : nullptr, W0, W1);
 #pragma unroll
-                for (int j = 0; j < NN; ++j) W1[j] *= w1s;
-            }
+            for (int j = 0; j < NN; ++j) W1[j] *= w1s;
             double acc = 0.0;
 #pragma unroll
             for (int j = 0; j < NN; ++j) {
@@ -484,20 +475,8 @@ __global__ __launch_bounds__(kTaylorRegion) void taylor_stepk_kernel(const DevPr
                                                                    const double* __restrict__ u_in,
                                                                    double* __restrict__ u_out,
                                                                    unsigned long long* __restrict__ stats) {
-    taylor_stepk_body<NN, false>(probs, nprob, kb, ksteps, reg, fd, taylor, u_in, u_out, stats);
+    taylor_stepk_body<NN>(probs, nprob, kb, ksteps, reg, fd, taylor, u_in, u_out, stats);
 }
-// launched with kTaylorDdThreads threads (two or more passes over the region)
-template <int NN>
-__global__ __launch_bounds__(kTaylorDdThreads) void taylor_stepk_dd_kernel(const DevProb* __restrict__ probs,
-                                                                         int nprob, int kb, int ksteps, int reg,
-                                                                         const double* __restrict__ fd,
-                                                                         const double* __restrict__ tdd,
-                                                                         const double* __restrict__ u_in,
-                                                                         double* __restrict__ u_out,
-                                                                         unsigned long long* __restrict__ stats) {
-    taylor_stepk_body<NN, true>(probs, nprob, kb, ksteps, reg, fd, tdd, u_in, u_out, stats);
-}
-
 // Stationary one-sided tables in double-double: one thread per harvested row
 // (items = n per instance, item_begin = the instance's first row), the plain
 // layout [kind][r][k] with W1 = dt phi1 and W2 = dt phi2 rows.
@@ -568,36 +547,22 @@ hipError_t go_table_dd_p(int p, const DevProb* d_probs, int nprob, int64_t items
 
 hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb* d_probs, int nprob, int64_t tiles,
                                const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
-                               unsigned long long* stats, hipStream_t stream, bool dd) {
+                               unsigned long long* stats, hipStream_t stream) {
     if (tiles <= 0) return hipSuccess;
     if (tiles > 0x7fffffff || kb < 1 || kb > 8 || ksteps < 1 || ksteps > kb || reg < 64 || reg > kTaylorRegion ||
-        reg % 64 != 0 || taylor_stepk_tile(n, kb, reg, false) < 1 || (dd && n < kTaylorDdMinN))
+        reg % 64 != 0 || taylor_stepk_tile(n, kb, reg, false) < 1)
         return hipErrorInvalidValue;
-    const int nt = reg < kTaylorDdThreads ? reg : kTaylorDdThreads;
 #define LMEP_TSK_CASE(NN)                                                                                         \
     case NN:                                                                                                      \
         hipLaunchKernelGGL((taylor_stepk_kernel<NN>), dim3((unsigned)tiles), dim3(reg), 0, stream, d_probs, nprob,  \
                            kb, ksteps, reg, fd, taylor, d_u_in, d_u_out, stats);                                  \
         return hipGetLastError();
-#define LMEP_TSK_DD_CASE(NN)                                                                                      \
-    case NN:                                                                                                      \
-        hipLaunchKernelGGL((taylor_stepk_dd_kernel<NN>), dim3((unsigned)tiles), dim3(nt), 0, stream, d_probs,      \
-                           nprob, kb, ksteps, reg, fd, taylor, d_u_in, d_u_out, stats);                           \
-        return hipGetLastError();
-    if (dd) {
-        static_assert(kTaylorDdMinN == 9, "the double-double cases below start at n = 9");
-        switch (n) {
-            LMEP_TSK_DD_CASE(9) LMEP_TSK_DD_CASE(11) LMEP_TSK_DD_CASE(13) LMEP_TSK_DD_CASE(15)
-            default: return hipErrorInvalidValue;
-        }
-    }
     switch (n) {
         LMEP_TSK_CASE(3) LMEP_TSK_CASE(5) LMEP_TSK_CASE(7) LMEP_TSK_CASE(9) LMEP_TSK_CASE(11) LMEP_TSK_CASE(13)
         LMEP_TSK_CASE(15)
         default: return hipErrorInvalidValue;
     }
 #undef LMEP_TSK_CASE
-#undef LMEP_TSK_DD_CASE
 }
 
 hipError_t launch_build_table_dd(int n, int p, const DevProb* d_probs, int nprob, int64_t items, const double* tdd,

@@ -378,8 +378,11 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         g.dd = std::get<2>(kv.first) == 3;
         g.ddtable = std::get<2>(kv.first) == 4;
         for (const Part& part : kv.second) g.nodes += prob[part.k].N;
-        if (g.taylor && frozen_kb > 0) g.kb = std::min(frozen_kb, kTaylorMaxKb);
-        if (g.taylor && frozen_kb > 0) {
+        // double-double groups advance one step per launch (their fused one-step
+        // kernel), the others up to kTaylorMaxKb in the multi-step kernel
+        const bool multi_taylor = g.taylor && frozen_kb > 0 && !g.dd;
+        if (multi_taylor) g.kb = std::min(frozen_kb, kTaylorMaxKb);
+        if (multi_taylor) {
             // staged positions per block (= threads): about one block per CU for
             // groups too small to fill the GPU -- a step then costs the latency of
             // one block, not of the two or three an uneven spread puts on some
@@ -402,9 +405,9 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
             d.harvest = part.harvest;
             if (part.harvest == HARVEST_RK4_HALF) d.dt = 0.5 * prob[part.k].dt;
             d.item_begin = items;
-            const int64_t tt = frozen_kb > 0 ? taylor_stepk_tile(g.n, g.kb, g.reg,
-                                                                 prob[part.k].window == LMEP_WIN_UPWIND)
-                                             : kTaylorTile;
+            const int64_t tt = multi_taylor ? taylor_stepk_tile(g.n, g.kb, g.reg,
+                                                                prob[part.k].window == LMEP_WIN_UPWIND)
+                                            : kTaylorTile;
             items += g.taylor ? (prob[part.k].N + tt - 1) / tt
                               : (pernode(prob[part.k]) ? prob[part.k].N : prob[part.k].n);
             tab.push_back(d);
@@ -483,7 +486,7 @@ std::string build_kernel_name(const Group& g, bool fused, bool multi) {
     if (g.wide) return "build_wide_kernel";
     const char* dd = g.dd ? "_dd" : "";
     if (g.ddtable) snprintf(b, sizeof(b), "build_table_dd_kernel<%d,%d>", g.n, g.p);
-    else if (g.taylor && multi) snprintf(b, sizeof(b), "taylor_stepk%s_kernel<%d>", dd, g.n);
+    else if (g.taylor && multi && !g.dd) snprintf(b, sizeof(b), "taylor_stepk_kernel<%d>", g.n);
     else if (g.taylor) snprintf(b, sizeof(b), "build_taylor%s_kernel<%d,%s>", dd, g.n, bool_s(fused).c_str());
     else snprintf(b, sizeof(b), "build_pade_kernel<%d,%d,%s>", g.n, g.p, bool_s(fused).c_str());
     return b;
@@ -786,9 +789,9 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
                 if (one_span) span = t;
             }
             const double* tt = gr.dd ? tdd : tay;
-            if (gr.taylor && P.multi)
+            if (gr.taylor && P.multi && !gr.dd)
                 HIP_TRY(launch_taylor_stepk(gr.n, kb, std::min(kb, n_steps - st * kb), gr.reg, dbt + gr.first,
-                                            gr.count, gr.items, fd, tt, src, dst, counters, s, gr.dd));
+                                            gr.count, gr.items, fd, tt, src, dst, counters, s));
             else if (gr.taylor)
                 HIP_TRY(launch_build_taylor(gr.n, dbt + gr.first, gr.count, gr.items, fd, tt, src, d_w, counters, s,
                                             P.fuse ? dst : nullptr, gr.dd));

@@ -108,12 +108,11 @@ __host__ __device__ constexpr int taylor_stepk_tile(int n, int kb, int reg, bool
 }
 static_assert(taylor_stepk_tile(15, 8, kTaylorRegion, false) >= 256, "halo too wide for the staged region");
 static_assert(taylor_stepk_tile(15, 8, kTaylorRegion, true) >= 32, "halo too wide for the staged region");
-// dd as above; the double-double kernel runs kTaylorDdThreads threads per
-// block (at most reg), each taking reg / kTaylorDdThreads positions per pass.
-constexpr int kTaylorDdThreads = 256;
+// (Double-double groups take the one-step kernel at every step instead: at a
+// few steps per launch its halo recomputation cost more than the launches.)
 hipError_t launch_taylor_stepk(int n, int kb, int ksteps, int reg, const DevProb* d_probs, int nprob, int64_t tiles,
                                const double* fd, const double* taylor, const double* d_u_in, double* d_u_out,
-                               unsigned long long* stats, hipStream_t stream, bool dd = false);
+                               unsigned long long* stats, hipStream_t stream);
 // Stationary one-sided tables (uniform grid, react = 0, p <= 2) by the finite
 // Taylor series in double-double: items = n rows per instance (item_begin =
 // the instance's first row); writes the plain table [kind][r][k] with the

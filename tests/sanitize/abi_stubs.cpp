@@ -28,7 +28,7 @@ hipError_t launch_build_taylor(int, const DevProb*, int, int64_t, const double*,
                                unsigned long long*, hipStream_t, double*, bool) { return hipErrorInvalidValue; }
 hipError_t launch_check_finite(const double*, int64_t, int*, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t launch_taylor_stepk(int, int, int, int, const DevProb*, int, int64_t, const double*, const double*,
-                               const double*, double*, unsigned long long*, hipStream_t, bool) {
+                               const double*, double*, unsigned long long*, hipStream_t) {
     return hipErrorInvalidValue;
 }
 hipError_t launch_build_table_dd(int, int, const DevProb*, int, int64_t, const double*, double*, hipStream_t) {

@@ -163,14 +163,16 @@ def burgers_etdrk4(N: int = 2 ** 20, n: int = 19, nu: float = 0.03, mu: float = 
 
 # --------------------------------------------- upwind windows (next row) --
 def burgers_upwind(N: int = 65536, n: int = 7, nu: float = 2.5e-3, cfl: float = 3.5, modes: int = 8,
-                   seed: int = BASE_SEED + 5):
+                   seed: int = BASE_SEED + 5, amp: float = 0.1):
     """Viscous Burgers at high Courant number on fully one-sided stencils
     (Sec. 4.1 runs them at CFL (n+1)/2 - sigma): periodic, h = 16 nu (cell
     Peclet number 16, so the diffusion number cfl/16 stays inside the
     one-sided rows' stable range), u0 = 1 + 0.1 p(x) / max|p| with p a sum of 8
     sine modes, amplitudes N(0, 1/k^2), phases U[0, 2pi); dt = cfl h / mean(u0),
-    so every node's Courant number lies in [0.9, 1.1] * cfl, inside the stable
-    band [(n-3)/2, (n+1)/2].  Frozen-velocity ETD1 with window="upwind"."""
+    so every node's Courant number lies in [0.9, 1.1] * cfl (amp = 0.1), inside
+    the stable band [(n-3)/2, (n+1)/2].  Frozen-velocity ETD1 with
+    window="upwind".  (For n >= 13 the explicit frozen-velocity term amplifies
+    grid-scale perturbations unless amp is small.)"""
     h = 16.0 * nu
     length = N * h
     x = h * np.arange(N)
@@ -178,7 +180,7 @@ def burgers_upwind(N: int = 65536, n: int = 7, nu: float = 2.5e-3, cfl: float = 
     a = g.normal(0.0, 1.0, modes) / np.arange(1, modes + 1)
     ph = g.uniform(0.0, 2.0 * math.pi, modes)
     pert = sum(a[k - 1] * np.sin(2.0 * math.pi * k * x / length + ph[k - 1]) for k in range(1, modes + 1))
-    u0 = 1.0 + 0.1 * pert / float(np.max(np.abs(pert)))
+    u0 = 1.0 + amp * pert / float(np.max(np.abs(pert)))
     p = make_problem(N=N, n=n, bc="periodic", h=h, dt=cfl * h / float(np.mean(u0)), nu=nu, scheme="etd1",
                      nonlin="burgers_frozen", nl_coef=1.0, window="upwind")
     return p, u0
