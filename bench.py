@@ -3,7 +3,7 @@
 Default workload: the batched path -- 4096 independent Allen-Cahn instances
 (N_k uniform in [512, 65536], stencil n_k in {5, 7, 9, 11}, periodic or Neumann
 ends, ETD1 with phi1 weights of the augmented local matrix built once per
-instance) advanced 16 steps per launch.  A "step" is one time step of the whole
+instance) advanced 16 steps per launch, every stencil size in one launch.  A "step" is one time step of the whole
 hot path for every instance: the weights are stationary, so after the first
 build a step is the banded apply.
 
@@ -484,6 +484,10 @@ def kernel_work(name, problems, steps):
     if base == "build_taylor_kernel":
         g = group(lambda p: frozen(p) and p["n"] == v[0])
         return "alu", taylor_flops(v[0], v[1]) * sum(p["N"] for p in g) * steps, "flop"
+    if base == "stepk_mixed_kernel":  # every size of one scheme and nonlinearity, more than 512 nodes
+        g = group(lambda p: SCHEME_ID[p["scheme"]] == v[0] and nl_id(p) == v[1] and not frozen(p)
+                  and p.get("x") is None and p.get("window", "centred") == "centred" and p["N"] > 512)
+        return "alu", sum(stationary_flops(p) * p["N"] for p in g) * steps, "flop"
     if base in ("stepk_kernel", "stepk_upwind_kernel", "stepk_rk4_kernel"):
         def side(p):
             if p.get("window", "centred") != "upwind" or p.get("c", 0.0) == 0.0:
@@ -595,6 +599,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain single-instance comparison runs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--no-single", action="store_true", help="skip the single-instance Burgers workload")
+    ap.add_argument("--separate-groups", action="store_true",
+                    help="one multi-step launch per stencil size instead of one over every size "
+                         "(LMEP_OPT_MERGE_GROUPS = 0)")
     ap.add_argument("--no-upwind-sweep", action="store_true",
                     help="skip the one-sided advection runs over stencil sizes")
     ap.add_argument("--adjoint-steps", type=int, default=500)
@@ -630,6 +637,8 @@ def main():
 
     lmep.lmep_set_option(lmep.LMEP_OPT_EXP_METHOD,
                          lmep.LMEP_EXP_PADE if args.exp_method == "pade" else lmep.LMEP_EXP_AUTO)
+    # the batch's stencil sizes share one multi-step launch (largest n first)
+    lmep.lmep_set_option(lmep.LMEP_OPT_MERGE_GROUPS, 0 if args.separate_groups else 1)
     if args.workload == "burgers_adjoint":
         args.no_adjoint = False
     problems, states, desc = make_workload(args.workload)

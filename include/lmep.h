@@ -344,6 +344,14 @@ const char* lmep_last_error(void);
  *                             where the halo would leave fewer than 64
  *                             written nodes per block.  Results do not
  *                             depend on it.
+ *  LMEP_OPT_MERGE_GROUPS      1: under LMEP_F_PERSISTENT at 8 or 16 steps per
+ *                             launch, uniform stationary instances on centred
+ *                             windows (ETD schemes, more than 512 nodes) of
+ *                             every stencil size share one launch per scheme
+ *                             and nonlinearity, their blocks ordered by n
+ *                             descending (a group of one size keeps its own
+ *                             kernel); 0 (default): one launch per stencil
+ *                             size.  Results do not depend on it.
  * lmep_set_option returns LMEP_OK or LMEP_ERR_ARG (unknown option or value);
  * lmep_get_option returns the value or LMEP_ERR_ARG. */
 #define LMEP_OPT_STEPS_PER_LAUNCH 1
@@ -352,6 +360,7 @@ const char* lmep_last_error(void);
 #define LMEP_OPT_APPLY_TILE 4
 #define LMEP_OPT_EXP_METHOD 5
 #define LMEP_OPT_TAYLOR_REGION 6
+#define LMEP_OPT_MERGE_GROUPS 7
 #define LMEP_EXP_AUTO 0
 #define LMEP_EXP_PADE 1
 int lmep_set_option(int32_t option, int32_t value);

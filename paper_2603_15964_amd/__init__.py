@@ -28,14 +28,14 @@ from ._native import (  # noqa: F401  (re-exported names of the C ABI)
     LMEP_EXP_PADE, LMEP_F_CHECK_FINITE, LMEP_F_COUNT, LMEP_F_GRAPH, LMEP_F_PERSISTENT, LMEP_F_PROFILE, LMEP_LINEAR,
     LMEP_NL_ALLEN_CAHN, LMEP_NL_BURGERS_FROZEN, LMEP_NL_KDV, LMEP_NL_NONE, LMEP_OK, LMEP_OPT_APPLY_TILE,
     LMEP_OPT_EXP_METHOD, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_PROFILE_ADJOINT, LMEP_OPT_STEPS_PER_LAUNCH,
-    LMEP_OPT_TAYLOR_REGION, LMEP_WIN_CENTRED,
+    LMEP_OPT_TAYLOR_REGION, LMEP_OPT_MERGE_GROUPS, LMEP_WIN_CENTRED,
     LMEP_WIN_UPWIND, OP_ADJOINT, OP_BUILD, OP_STEP, LmepError, library, lmep_adjoint_step, lmep_build_weights,
     lmep_get_option, lmep_last_error, lmep_problem, lmep_profile_last, lmep_scratch_bytes, lmep_set_option, lmep_step,
     lmep_step_noalloc, lmep_weight_count, problem_array, to_struct, LMEP_NOALLOC_SCRATCH_BYTES, lmep_plan_create,
     lmep_plan_step, lmep_plan_adjoint_step, lmep_plan_destroy, lmep_profile_kernels, option_generation)
 
 _OPTIONS = (LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_PROFILE_ADJOINT, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_APPLY_TILE,
-            LMEP_OPT_EXP_METHOD, LMEP_OPT_TAYLOR_REGION)
+            LMEP_OPT_EXP_METHOD, LMEP_OPT_TAYLOR_REGION, LMEP_OPT_MERGE_GROUPS)
 
 _KINDS = {"linear": 1, "etd1": 2, "etd2rk": 3, "etdrk4": 6}
 

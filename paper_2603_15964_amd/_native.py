@@ -96,6 +96,7 @@ LMEP_OPT_FUSE_FROZEN = 3
 LMEP_OPT_APPLY_TILE = 4
 LMEP_OPT_EXP_METHOD = 5
 LMEP_OPT_TAYLOR_REGION = 6
+LMEP_OPT_MERGE_GROUPS = 7
 LMEP_EXP_AUTO = 0
 LMEP_EXP_PADE = 1
 

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "liblmep.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["stepk_kb16.hip", "stepk_up_kb16.hip", "stepk_kb8.hip", "stepk_kb4.hip", "stepk_kb2.hip", "stepk_kb1.hip", "stepk_up_kb8.hip", "stepk_up_kb4.hip",
+SOURCES = ["stepk_kb16.hip", "stepk_up_kb16.hip", "stepk_mix_kb16.hip", "stepk_mix_kb8.hip", "stepk_kb8.hip", "stepk_kb4.hip", "stepk_kb2.hip", "stepk_kb1.hip", "stepk_up_kb8.hip", "stepk_up_kb4.hip",
            "stepk_up_kb2.hip", "stepk_up_kb1.hip", "stepk.hip", "fd_table.hip", "build_pade.hip", "build_taylor.hip", "adjoint_taylor.hip", "apply.hip", "apply_wide.hip", "build_wide.hip", "resident.hip", "adjoint.hip", "static_scratch.hip", "lmep_abi.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

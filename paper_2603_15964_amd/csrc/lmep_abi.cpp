@@ -55,9 +55,10 @@ struct Opts {
     int apply_tile = 0;         // LMEP_OPT_APPLY_TILE (0 = by size)
     int exp_method = LMEP_EXP_AUTO;  // LMEP_OPT_EXP_METHOD
     int taylor_region = 0;      // LMEP_OPT_TAYLOR_REGION (0 = by size)
+    int merge_groups = 0;       // LMEP_OPT_MERGE_GROUPS
 };
 std::atomic<int> g_steps_per_launch{8}, g_profile_adjoint{0}, g_fuse_frozen{1}, g_apply_tile{0},
-    g_exp_method{LMEP_EXP_AUTO}, g_taylor_region{0};
+    g_exp_method{LMEP_EXP_AUTO}, g_taylor_region{0}, g_merge_groups{0};
 
 Opts process_opts() {
     Opts o;
@@ -67,6 +68,7 @@ Opts process_opts() {
     o.apply_tile = g_apply_tile.load();
     o.exp_method = g_exp_method.load();
     o.taylor_region = g_taylor_region.load();
+    o.merge_groups = g_merge_groups.load();
     return o;
 }
 
@@ -114,6 +116,10 @@ int set_opt(Opts& o, int32_t option, int32_t value) {
                 return fail(LMEP_ERR_ARG, "finite-Taylor region must be 0 or a multiple of 64 in [128, %d], got %d",
                             kTaylorRegion, value);
             o.taylor_region = value;
+            return LMEP_OK;
+        case LMEP_OPT_MERGE_GROUPS:
+            if (value != 0 && value != 1) return fail(LMEP_ERR_ARG, "option %d takes 0 or 1, got %d", option, value);
+            o.merge_groups = value;
             return LMEP_OK;
         default: return fail(LMEP_ERR_ARG, "unknown option %d", option);
     }
@@ -320,6 +326,7 @@ struct Group {
     int64_t max_nodes = 0;
     bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
     int side = 0;        // stationary windows: 0 centred, 1 one-sided ending at the node (c > 0), 2 starting at it
+    bool mixed = false;  // one multi-step launch over several stencil sizes (n = the largest)
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
     int64_t nodes = 0;         // nodes of the group's instances
@@ -430,16 +437,30 @@ int stationary_side(const lmep_problem& q) {
 
 std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vector<DevProb>& tab,
                               std::vector<int>& tile_inst, const Opts& o, int multi_kb = 0) {
-    // weight kind: 0 stationary table, 1 frozen velocity, 2 non-uniform grid
+    // weight kind: 0 stationary table, 1 frozen velocity, 2 non-uniform grid.
+    // With LMEP_OPT_MERGE_GROUPS the instances of a multi-step launch at 8 or
+    // 16 steps (uniform, stationary, centred, not ETDRK4, more than
+    // kResidentMaxN nodes) form one group per scheme and nonlinearity whatever
+    // their n (key n = 0), ordered by n descending.
+    auto mergeable = [&](const lmep_problem& q) {
+        return o.merge_groups != 0 && (multi_kb == 8 || multi_kb == 16) && !frozen(q) && !nonuniform(q) &&
+               stationary_side(q) == 0 && q.scheme != LMEP_ETDRK4 && q.N > kResidentMaxN;
+    };
     std::map<std::tuple<int, int, int, int, int>, std::vector<int>> by;
     for (int k = 0; k < count; ++k)
-        by[{prob[k].n, prob[k].scheme, prob[k].nonlin, frozen(prob[k]) ? 1 : (nonuniform(prob[k]) ? 2 : 0),
-            stationary_side(prob[k])}]
+        by[{mergeable(prob[k]) ? 0 : prob[k].n, prob[k].scheme, prob[k].nonlin,
+            frozen(prob[k]) ? 1 : (nonuniform(prob[k]) ? 2 : 0), stationary_side(prob[k])}]
             .push_back(k);
     std::vector<Group> groups;
     for (auto& kv : by) {
         Group g;
         std::tie(g.n, g.scheme, g.nonlin, std::ignore, g.side) = kv.first;
+        if (g.n == 0) {  // several stencil sizes: the largest first (the launch ends on the shortest blocks)
+            std::stable_sort(kv.second.begin(), kv.second.end(),
+                             [&](int a, int b) { return prob[a].n > prob[b].n; });
+            g.n = prob[kv.second.front()].n;
+            g.mixed = prob[kv.second.back()].n != g.n;  // one size only: the per-size kernel
+        }
         g.pernode = std::get<3>(kv.first) != 0;
         g.frozen = std::get<3>(kv.first) == 1;
         g.nonuniform = std::get<3>(kv.first) == 2;
@@ -451,7 +472,7 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         // nonlinearity and at most kResidentMaxN nodes), else the tiled kernel
         const bool small_uniform = !g.pernode && g.max_nodes <= kResidentMaxN && g.scheme != LMEP_ETDRK4 &&
                                    (g.nonlin == LMEP_NL_NONE || g.nonlin == LMEP_NL_ALLEN_CAHN);
-        g.resident = multi_kb > 0 && (g.nonuniform || small_uniform);
+        g.resident = multi_kb > 0 && !g.mixed && (g.nonuniform || small_uniform);
         g.stepk = !g.resident && !g.nonuniform && (multi_kb > 0 || g.scheme == LMEP_ETDRK4);
         if (g.stepk && multi_kb > 0) g.kb = g.scheme == LMEP_ETDRK4 ? std::min(multi_kb, kStepRk4MaxKb) : multi_kb;
         const int64_t avg = g.nodes / (int64_t)kv.second.size();
@@ -466,7 +487,8 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         for (int k : kv.second) {
             DevProb d = to_dev(prob[k], k);
             d.item_begin = tiles;
-            const int64_t nt = (prob[k].N + g.tile - 1) / g.tile;
+            const int64_t tk = g.mixed ? stepk_tile(prob[k].n, g.scheme, g.nonlin, g.kb) : g.tile;
+            const int64_t nt = (prob[k].N + tk - 1) / tk;
             for (int64_t t = 0; t < nt; ++t) tile_inst.push_back((int)(tab.size() - g.first));
             tiles += nt;
             tab.push_back(d);
@@ -496,6 +518,7 @@ std::string apply_kernel_name(const Group& g) {
     char b[96];
     const int nl = g.scheme == LMEP_LINEAR ? 0 : g.nonlin;
     if (g.stepk && g.scheme == LMEP_ETDRK4) snprintf(b, sizeof(b), "stepk_rk4_kernel<%d,%d,%d>", g.n, g.nonlin, kb);
+    else if (g.stepk && g.mixed) snprintf(b, sizeof(b), "stepk_mixed_kernel<%d,%d,%d>", g.scheme, nl, kb);
     else if (g.stepk && g.side != 0)
         snprintf(b, sizeof(b), "stepk_upwind_kernel<%d,%d,%d,%d,%d>", g.n, g.scheme, nl, kb, g.side);
     else if (g.stepk) snprintf(b, sizeof(b), "stepk_kernel<%d,%d,%d,%d>", g.n, g.scheme, nl, kb);
@@ -813,7 +836,10 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
                     HIP_TRY(e);
                     if (one_span) span = t;
                 }
-                if (gr.stepk)
+                if (gr.stepk && gr.mixed)
+                    HIP_TRY(launch_stepk_mixed(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
+                                               dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
+                else if (gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
                                          dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s, gr.side));
                 else if (gr.resident) {
@@ -1220,6 +1246,7 @@ int lmep_set_option(int32_t option, int32_t value) {
     g_apply_tile.store(o.apply_tile);
     g_exp_method.store(o.exp_method);
     g_taylor_region.store(o.taylor_region);
+    g_merge_groups.store(o.merge_groups);
     return LMEP_OK;
 }
 
@@ -1232,6 +1259,7 @@ int32_t lmep_get_option(int32_t option) {
         case LMEP_OPT_APPLY_TILE: return o.apply_tile;
         case LMEP_OPT_EXP_METHOD: return o.exp_method;
         case LMEP_OPT_TAYLOR_REGION: return o.taylor_region;
+        case LMEP_OPT_MERGE_GROUPS: return o.merge_groups;
         default: return fail(LMEP_ERR_ARG, "unknown option %d", option);
     }
 }

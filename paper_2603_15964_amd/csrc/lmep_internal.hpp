@@ -187,6 +187,17 @@ hipError_t launch_stepk_upwind_depth(int side, int n, int scheme, int nonlin, in
 hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const DevProb* d_probs,
                         const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
                         const double* d_u_in, double* d_u_out, hipStream_t stream, int side = 0);
+// One launch over instances of several stencil sizes (centred windows, ETD
+// schemes, kb = 8 or 16): instance k's blocks write tiles of
+// stepk_tile(n_k, ...) nodes; nmax = the largest n (sizes the weight rows'
+// dynamic LDS).  Results equal the per-size kernels' bit for bit.
+template <int KB>
+hipError_t launch_stepk_mixed_depth(int nmax, int scheme, int nonlin, int ksteps, const DevProb* d_probs,
+                                    const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                                    const double* d_u_in, double* d_u_out, hipStream_t stream);
+hipError_t launch_stepk_mixed(int nmax, int scheme, int nonlin, int kb, int ksteps, const DevProb* d_probs,
+                              const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                              const double* d_u_in, double* d_u_out, hipStream_t stream);
 
 constexpr int kApplyTileTiny = 64;     // nodes per apply block for small non-uniform instances
 constexpr int kApplyTileSmall = 256;   // nodes per apply block for groups with few nodes

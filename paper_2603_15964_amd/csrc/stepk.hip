@@ -29,4 +29,16 @@ hipError_t launch_stepk(int n, int scheme, int nonlin, int kb, int ksteps, const
     }
 }
 
+hipError_t launch_stepk_mixed(int nmax, int scheme, int nonlin, int kb, int ksteps, const DevProb* d_probs,
+                              const int* d_tile_inst, int64_t tiles, const double* fd, const double* d_w,
+                              const double* d_u_in, double* d_u_out, hipStream_t stream) {
+    if (tiles <= 0) return hipSuccess;
+    if (ksteps < 1 || ksteps > kb) return hipErrorInvalidValue;
+    switch (kb) {
+        case 8: return launch_stepk_mixed_depth<8>(nmax, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        case 16: return launch_stepk_mixed_depth<16>(nmax, scheme, nonlin, ksteps, d_probs, d_tile_inst, tiles, fd, d_w, d_u_in, d_u_out, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace lmep

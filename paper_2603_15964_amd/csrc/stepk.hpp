@@ -101,22 +101,20 @@ struct Shape {
     static_assert(TILE > 0 && HALO % 1 == 0, "tile");
 };
 
+// The kernel body.  lds: S::NBUF * LP doubles; sw: (PP + 1) n^2; sD1: n^2 when
+// the nonlinearity differentiates (the caller's shared arrays).
 template <int NN, int SCH, int NL, int KB, int SIDE>
-__device__ __forceinline__ void stepk_body(const DevProb* __restrict__ probs, const int* __restrict__ tile_inst,
-                                           const double* __restrict__ fd, const double* __restrict__ w,
-                                           const double* __restrict__ u_in, double* __restrict__ u_out, int ksteps) {
+__device__ __forceinline__ void stepk_body(const DevProb& P, const double* __restrict__ fd,
+                                           const double* __restrict__ w, const double* __restrict__ u_in,
+                                           double* __restrict__ u_out, int ksteps, double* lds, double* sw,
+                                           double* sD1) {
     using S = Shape<NN, SCH, NL, KB>;
     using Wn = Win<NN, SIDE>;
     constexpr int R = S::R, PP = S::PP, W = V + NN - 1;
     constexpr int O = Wn::O, RI = Wn::RI;
     // halo before the tile: (applications) x (reach of a window to the left)
     constexpr int LHALO = KB * stepk_apps(SCH, NL) * RI;
-    __shared__ double lds[S::NBUF * LP];
-    __shared__ double sw[(PP + 1) * NN * NN];
-    __shared__ double sD1[S::DERIV ? NN * NN : 1];
-
     const int tid = threadIdx.x;
-    const DevProb& P = probs[tile_inst[blockIdx.x]];
     const int64_t N = P.N;
     const int bc = P.bc;
     const int64_t tb = ((int64_t)blockIdx.x - P.item_begin) * S::TILE;  // the block's own tile
@@ -392,7 +390,11 @@ __global__ __launch_bounds__(NT) void stepk_kernel(const DevProb* __restrict__ p
                                                    const double* __restrict__ fd, const double* __restrict__ w,
                                                    const double* __restrict__ u_in, double* __restrict__ u_out,
                                                    int ksteps) {
-    stepk_body<NN, SCH, NL, KB, 0>(probs, tile_inst, fd, w, u_in, u_out, ksteps);
+    using S = Shape<NN, SCH, NL, KB>;
+    __shared__ double lds[S::NBUF * LP];
+    __shared__ double sw[(S::PP + 1) * NN * NN];
+    __shared__ double sD1[S::DERIV ? NN * NN : 1];
+    stepk_body<NN, SCH, NL, KB, 0>(probs[tile_inst[blockIdx.x]], fd, w, u_in, u_out, ksteps, lds, sw, sD1);
 }
 // one-sided windows: SIDE 1 (c > 0, window ends at the node), 2 (c < 0)
 template <int NN, int SCH, int NL, int KB, int SIDE>
@@ -401,7 +403,71 @@ __global__ __launch_bounds__(NT) void stepk_upwind_kernel(const DevProb* __restr
                                                           const double* __restrict__ fd, const double* __restrict__ w,
                                                           const double* __restrict__ u_in, double* __restrict__ u_out,
                                                           int ksteps) {
-    stepk_body<NN, SCH, NL, KB, SIDE>(probs, tile_inst, fd, w, u_in, u_out, ksteps);
+    using S = Shape<NN, SCH, NL, KB>;
+    __shared__ double lds[S::NBUF * LP];
+    __shared__ double sw[(S::PP + 1) * NN * NN];
+    __shared__ double sD1[S::DERIV ? NN * NN : 1];
+    stepk_body<NN, SCH, NL, KB, SIDE>(probs[tile_inst[blockIdx.x]], fd, w, u_in, u_out, ksteps, lds, sw, sD1);
+}
+
+// Several stencil sizes in one launch (centred windows): each block runs the
+// body of its instance's n, the blocks of larger stencils first (the host
+// orders the instances so), so that the launch ends on the shortest blocks.
+// The weight and derivative rows sit in dynamic LDS sized for the launch's
+// largest n; the staged state is the same size for every n.
+template <int SCH, int NL, int KB>
+__global__ __launch_bounds__(NT) void stepk_mixed_kernel(const DevProb* __restrict__ probs,
+                                                         const int* __restrict__ tile_inst,
+                                                         const double* __restrict__ fd, const double* __restrict__ w,
+                                                         const double* __restrict__ u_in, double* __restrict__ u_out,
+                                                         int ksteps, int nmax) {
+    using S = Shape<3, SCH, NL, KB>;  // NBUF does not depend on n
+    __shared__ double lds[S::NBUF * LP];
+    extern __shared__ double dyn[];
+    const DevProb& P = probs[tile_inst[blockIdx.x]];
+    double* sw = dyn;
+    double* sD1 = dyn + (S::PP + 1) * nmax * nmax;
+    switch (P.n) {
+        case 3: stepk_body<3, SCH, NL, KB, 0>(P, fd, w, u_in, u_out, ksteps, lds, sw, sD1); break;
+        case 5: stepk_body<5, SCH, NL, KB, 0>(P, fd, w, u_in, u_out, ksteps, lds, sw, sD1); break;
+        case 7: stepk_body<7, SCH, NL, KB, 0>(P, fd, w, u_in, u_out, ksteps, lds, sw, sD1); break;
+        case 9: stepk_body<9, SCH, NL, KB, 0>(P, fd, w, u_in, u_out, ksteps, lds, sw, sD1); break;
+        case 11: stepk_body<11, SCH, NL, KB, 0>(P, fd, w, u_in, u_out, ksteps, lds, sw, sD1); break;
+        case 13: stepk_body<13, SCH, NL, KB, 0>(P, fd, w, u_in, u_out, ksteps, lds, sw, sD1); break;
+        case 15: stepk_body<15, SCH, NL, KB, 0>(P, fd, w, u_in, u_out, ksteps, lds, sw, sD1); break;
+        default: break;
+    }
+}
+
+template <int SCH, int NL, int KB>
+hipError_t go_mixed(int nmax, const DevProb* p, const int* ti, int64_t tiles, const double* fd, const double* w,
+                    const double* ui, double* uo, int ksteps, hipStream_t s) {
+    using S = Shape<3, SCH, NL, KB>;
+    const size_t dyn = sizeof(double) * ((S::PP + 1) * nmax * nmax + (S::DERIV ? nmax * nmax : 0));
+    hipLaunchKernelGGL((stepk_mixed_kernel<SCH, NL, KB>), dim3((unsigned)tiles), dim3(NT), dyn, s, p, ti, fd, w, ui,
+                       uo, ksteps, nmax);
+    return hipGetLastError();
+}
+
+template <int KB>
+hipError_t dispatch_mixed(int nmax, int scheme, int nonlin, const DevProb* p, const int* ti, int64_t tiles,
+                          const double* fd, const double* w, const double* ui, double* uo, int ksteps, hipStream_t s) {
+    if (nmax < 3 || nmax > kMaxN || nmax % 2 == 0) return hipErrorInvalidValue;
+    if (scheme == SCH_LINEAR) return go_mixed<SCH_LINEAR, NL_NONE, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+    if (scheme != SCH_ETD1 && scheme != SCH_ETD2RK) return hipErrorInvalidValue;
+    const bool rk2 = scheme == SCH_ETD2RK;
+    switch (nonlin) {
+        case NL_NONE:
+            return rk2 ? go_mixed<SCH_ETD2RK, NL_NONE, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s)
+                       : go_mixed<SCH_ETD1, NL_NONE, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case NL_AC:
+            return rk2 ? go_mixed<SCH_ETD2RK, NL_AC, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s)
+                       : go_mixed<SCH_ETD1, NL_AC, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case NL_KDV:
+            return rk2 ? go_mixed<SCH_ETD2RK, NL_KDV, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s)
+                       : go_mixed<SCH_ETD1, NL_KDV, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int NN, int SCH, int NL, int KB, int SIDE>

@@ -15,10 +15,11 @@ keeps the fastest one whose result agrees with the default path:
 * one-step launches: the apply tile, chosen by size or forced to 256 / 1024
   nodes (LMEP_OPT_APPLY_TILE).
 
-Not offered: merging kernel groups of different stencil sizes into one
-launch (each kernel is specialised on n; the groups of a batch are launched
-back to back on one stream) and several lanes per node in the frozen-velocity
-kernel (measured slower).
+* several steps per launch with stationary weights of several stencil
+  sizes: one launch per size, or one over every size (LMEP_OPT_MERGE_GROUPS).
+
+Not offered: several lanes per node in the frozen-velocity kernel (measured
+slower).
 
 Choices are cached in a JSON file keyed by the GPU architecture and a
 signature of the batch (per kernel group: stencil size, scheme, nonlinearity,
@@ -35,12 +36,12 @@ import os
 from dataclasses import dataclass, field
 
 from ._native import (LMEP_EXP_AUTO, LMEP_EXP_PADE, LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE, LMEP_OPT_EXP_METHOD,
-                      LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_TAYLOR_REGION, lmep_get_option,
-                      lmep_set_option)
+                      LMEP_OPT_FUSE_FROZEN, LMEP_OPT_MERGE_GROUPS, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_TAYLOR_REGION,
+                      lmep_get_option, lmep_set_option)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2603_15964_amd", "tune.json")
 _OPTIONS = (LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH, LMEP_OPT_APPLY_TILE, LMEP_OPT_EXP_METHOD,
-            LMEP_OPT_TAYLOR_REGION)
+            LMEP_OPT_TAYLOR_REGION, LMEP_OPT_MERGE_GROUPS)
 
 
 @dataclass(frozen=True)
@@ -59,7 +60,7 @@ class Choice:
     def describe(self):
         names = {LMEP_OPT_FUSE_FROZEN: "fuse_frozen", LMEP_OPT_STEPS_PER_LAUNCH: "steps_per_launch",
                  LMEP_OPT_APPLY_TILE: "apply_tile", LMEP_OPT_EXP_METHOD: "exp_method",
-                 LMEP_OPT_TAYLOR_REGION: "taylor_region"}
+                 LMEP_OPT_TAYLOR_REGION: "taylor_region", LMEP_OPT_MERGE_GROUPS: "merge_groups"}
         d = {names[a]: b for a, b in self.options}
         d["persistent"] = bool(self.flags & LMEP_F_PERSISTENT)
         return d
@@ -102,6 +103,14 @@ def candidates(problems):
         all(p["bc"] != "neumann" and p.get("react", 0.0) == 0.0 for p in problems
             if p.get("nonlin") == "burgers_frozen")
     stationary = any(p.get("nonlin") != "burgers_frozen" for p in problems)
+    # stationary uniform centred instances of several stencil sizes (of one
+    # scheme and nonlinearity) can share a launch
+    sizes = {}
+    for p in problems:
+        if p.get("nonlin") != "burgers_frozen" and p.get("x") is None and p.get("window", "centred") == "centred" \
+                and p["scheme"] != "etdrk4" and int(p["N"]) > 512:
+            sizes.setdefault((p["scheme"], p.get("nonlin", "none")), set()).add(int(p["n"]))
+    mergeable = any(len(v) > 1 for v in sizes.values())
     nonuniform = any(p.get("x") is not None for p in problems)
     tiles = (0, 256, 1024) + ((64,) if nonuniform else ())
     out = []
@@ -117,10 +126,14 @@ def candidates(problems):
             ((1, 2, 4, 8, 16) if stationary else (1, 2, 4, 8))
         regions = (0, 256, 512) if frozen else (0,)
         for kb in kbs:
+            merges = (0, 1) if (mergeable and kb in (8, 16)) else (None,)
             for reg in regions:
-                opts = ((LMEP_OPT_FUSE_FROZEN, 1), (LMEP_OPT_STEPS_PER_LAUNCH, kb), (LMEP_OPT_APPLY_TILE, 0),
-                        (LMEP_OPT_EXP_METHOD, LMEP_EXP_AUTO))
-                out.append(Choice(LMEP_F_PERSISTENT, opts + (((LMEP_OPT_TAYLOR_REGION, reg),) if frozen else ())))
+                for merge in merges:
+                    opts = ((LMEP_OPT_FUSE_FROZEN, 1), (LMEP_OPT_STEPS_PER_LAUNCH, kb), (LMEP_OPT_APPLY_TILE, 0),
+                            (LMEP_OPT_EXP_METHOD, LMEP_EXP_AUTO))
+                    opts += ((LMEP_OPT_TAYLOR_REGION, reg),) if frozen else ()
+                    opts += ((LMEP_OPT_MERGE_GROUPS, merge),) if merge is not None else ()
+                    out.append(Choice(LMEP_F_PERSISTENT, opts))
     return out
 
 

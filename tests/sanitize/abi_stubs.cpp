@@ -13,6 +13,8 @@ hipError_t launch_build(int, int, const DevProb*, int, int64_t, const double*, c
                         unsigned long long*, hipStream_t, double*) { return hipErrorInvalidValue; }
 hipError_t launch_stepk(int, int, int, int, int, const DevProb*, const int*, int64_t, const double*, const double*,
                         const double*, double*, hipStream_t, int) { return hipErrorInvalidValue; }
+hipError_t launch_stepk_mixed(int, int, int, int, int, const DevProb*, const int*, int64_t, const double*,
+                              const double*, const double*, double*, hipStream_t) { return hipErrorInvalidValue; }
 hipError_t fd_table_init(const double**) { return hipErrorInvalidValue; }
 hipError_t taylor_table_init(const double**) { return hipErrorInvalidValue; }
 hipError_t taylor_dd_table_init(const double**) { return hipErrorInvalidValue; }

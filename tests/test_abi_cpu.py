@@ -151,6 +151,20 @@ def test_taylor_region_option():
         lmep.lmep_set_option(opt, 0)
 
 
+def test_merge_groups_option():
+    """LMEP_OPT_MERGE_GROUPS takes 0 (default) or 1."""
+    opt = lmep.LMEP_OPT_MERGE_GROUPS
+    assert lmep.lmep_get_option(opt) == 0
+    for bad in (-1, 2):
+        with pytest.raises(lmep.LmepError):
+            lmep.lmep_set_option(opt, bad)
+    try:
+        lmep.lmep_set_option(opt, 1)
+        assert lmep.lmep_get_option(opt) == 1
+    finally:
+        lmep.lmep_set_option(opt, 0)
+
+
 def test_exp_method_option():
     """LMEP_OPT_EXP_METHOD takes LMEP_EXP_AUTO (default) or LMEP_EXP_PADE."""
     opt = lmep.LMEP_OPT_EXP_METHOD

@@ -206,3 +206,51 @@ def test_full_size_kdv_multistep():
     ref, got = run_both([p], [u0], steps, 8)
     assert np.array_equal(ref[0], got[0])
     assert state_rel_err(got[0], oracle.run(p, u0, steps)) <= 1e-10
+
+
+@pytest.mark.parametrize("kb", [8, 16])
+@pytest.mark.parametrize("kind", ["allen_cahn_etd1", "kdv_etd2rk", "linear_dirichlet"])
+def test_merged_stencil_sizes_equal_separate_launches(kind, kb):
+    """LMEP_OPT_MERGE_GROUPS: instances of several stencil sizes in one
+    launch (largest n first) give the separate launches' result bit for bit,
+    and that launch is the one that runs."""
+    _print_case("merged sizes", kind, kb)
+    probs, states = [], []
+    for k, (n, N) in enumerate([(5, 3000), (11, 2600), (7, 4100), (9, 2049), (11, 700), (3, 1500), (15, 2100)]):
+        if kind == "allen_cahn_etd1":
+            p, u = _ac(N, n, "periodic" if k % 2 else "neumann", "etd1")
+        elif kind == "kdv_etd2rk":
+            if n > 13:
+                continue
+            p, u = _kdv(N, "periodic", n=n)
+        else:
+            h = 1.0 / N
+            p = make_problem(N=N, n=n, bc="dirichlet", h=h, dt=0.2 * h * h / 1e-3, nu=1e-3, c=0.3 * 1e-3 / h,
+                             scheme="linear", bc_left=0.2, bc_right=-0.1)
+            u = np.cos(np.linspace(0.0, 3.0, N))
+            u[0], u[-1] = 0.2, -0.1
+        probs.append(p)
+        states.append(u)
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, kb)
+    try:
+        outs = []
+        for merge in (0, 1):
+            lmep.lmep_set_option(lmep.LMEP_OPT_MERGE_GROUPS, merge)
+            b = lmep.Batch(probs, device=DEV)
+            w = b.empty_weights()
+            u0 = b.pack(states)
+            b.build_weights(w, u0)
+            outs.append(b.step(w, u0, 2 * kb + 3, lmep.LMEP_F_PERSISTENT | lmep.LMEP_F_PROFILE))
+            names = [k[0] for k in lmep.lmep_profile_kernels()]
+            torch.cuda.synchronize()
+            if merge:
+                assert any(x.startswith("stepk_mixed_kernel<") for x in names), names
+                assert not any(x.startswith("stepk_kernel<") for x in names), names
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_MERGE_GROUPS, 0)
+        lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, saved)
+    assert torch.equal(outs[0], outs[1])
+    got = lmep.Batch(probs, device=DEV).unpack(outs[1])
+    for k, (p, u) in enumerate(zip(probs, states)):
+        assert state_rel_err(got[k], oracle.run(p, u, 2 * kb + 3)) <= 1e-10, k

@@ -11,7 +11,7 @@ import workloads
 from paper_2603_15964_amd import tune
 from paper_2603_15964_amd._native import (LMEP_EXP_AUTO, LMEP_EXP_PADE, LMEP_F_PERSISTENT, LMEP_OPT_APPLY_TILE,
                                           LMEP_OPT_EXP_METHOD, LMEP_OPT_FUSE_FROZEN, LMEP_OPT_STEPS_PER_LAUNCH,
-                                          LMEP_OPT_TAYLOR_REGION)
+                                          LMEP_OPT_MERGE_GROUPS, LMEP_OPT_TAYLOR_REGION)
 
 
 def _opts(c):
@@ -49,6 +49,11 @@ def test_candidates_follow_what_the_library_accepts():
     kbs = {_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH] for x in tune.candidates(stat) if x.flags & LMEP_F_PERSISTENT}
     assert kbs == {1, 2, 4, 8, 16}
     assert all(LMEP_OPT_TAYLOR_REGION not in _opts(x) for x in tune.candidates(stat))
+    assert all(LMEP_OPT_MERGE_GROUPS not in _opts(x) for x in tune.candidates(stat))  # one stencil size
+    acb = workloads.allen_cahn_batch(count=12, n_min=600, n_max=3000)[0]
+    merges = {(_opts(x)[LMEP_OPT_STEPS_PER_LAUNCH], _opts(x).get(LMEP_OPT_MERGE_GROUPS))
+              for x in tune.candidates(acb) if x.flags & LMEP_F_PERSISTENT}
+    assert (16, 0) in merges and (16, 1) in merges and (8, 1) in merges and (4, None) in merges
     upwind = [workloads.burgers_upwind(N=1000)[0]]  # frozen velocity: the multi-step Taylor kernel takes it
     assert any(x.flags & LMEP_F_PERSISTENT for x in tune.candidates(upwind))
     ac_upwind = [dict(workloads.allen_cahn_batch(count=1)[0][0], window="upwind")]  # one-sided stationary
