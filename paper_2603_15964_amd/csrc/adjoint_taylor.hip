@@ -31,13 +31,19 @@ namespace {
 
 constexpr int T = kAdjTile;
 
-template <int NN, int PP, bool SHIFT, bool DISP = true>
-__device__ __forceinline__ void adj_taylor_node(double a, double b, double e, double s, double dt,
-                                                const double* __restrict__ Tr, const double (&U)[NN],
-                                                const double (&V)[NN], double (&W0)[NN], double (&W1)[NN],
-                                                double& Ga, double& Gb, double& Ge) {
+// One side of a node's work.  ROLE 0 forms W0 and the terms of the
+// derivatives that go through it (M_{K-1}(1) tau_K and its b, e analogues);
+// ROLE 1 forms W1 and the terms through it (dt I_1(K-1) nu_K ...).  Each side
+// runs the moment recursion itself and keeps only the per-order sums it
+// uses, so a thread holds one window vector (X = U or V) and one weight row:
+// the two sides of a node run in different wavefronts of the block, and the
+// parameter terms are the sum of the two sides' parts.
+template <int NN, int ROLE, bool SHIFT, bool DISP = true>
+__device__ __forceinline__ void adj_taylor_side(double a, double b, double e, double s, double dt,
+                                                const double* __restrict__ Tr, const double (&X)[NN],
+                                                double (&W)[NN], double& Ga, double& Gb, double& Ge) {
     double m2[NN], m1[NN], m0[NN];  // mu[k-2][.], mu[k-1][.], mu[k][.] (M_k = sum_m mu[k][m] theta^m)
-    double Eh[NN], Ih[NN];          // M_j(1) and I_1(j) of the orders done so far
+    double Hh[NN];                  // M_j(1) (ROLE 0) or I_1(j) (ROLE 1) of the orders done so far
 #pragma unroll
     for (int m = 0; m < NN; ++m) {
         m2[m] = 0.0;
@@ -45,17 +51,12 @@ __device__ __forceinline__ void adj_taylor_node(double a, double b, double e, do
         m0[m] = 0.0;
     }
     m0[0] = 1.0;
-    Eh[0] = 1.0;
-    Ih[0] = 0.5;
+    Hh[0] = ROLE == 0 ? 1.0 : 0.5;
     Ga = 0.0;
     Gb = 0.0;
     Ge = 0.0;
 #pragma unroll
-    for (int j = 0; j < NN; ++j) {  // order 0
-        const double t = Tr[j];
-        W0[j] = t;
-        W1[j] = t;
-    }
+    for (int j = 0; j < NN; ++j) W[j] = Tr[j];  // order 0
     // Without a shift mu[k][m] can be non-zero only for lo(k) <= m <= k (the
     // forward series states why); terms on the exact zeros outside that range,
     // and the cubic term when e = 0 (DISP false), are skipped: each remaining
@@ -78,46 +79,37 @@ __device__ __forceinline__ void adj_taylor_node(double a, double b, double e, do
             }
             nx[m] = v;
         }
-        double E = -0.0, F = -0.0, I1 = -0.0;
+        // ROLE 0: C = E = M_K(1); ROLE 1: C = F = int_0^1 M_K, I1 = I_1(K)
+        double C = -0.0, I1 = -0.0;
 #pragma unroll
         for (int m = 0; m < NN; ++m) {
             m2[m] = m1[m];
             m1[m] = m0[m];
             m0[m] = nx[m];
             if (m <= K && m >= lo(K) && (SHIFT || m >= 1)) {
-                E += nx[m];
-                F = fma(nx[m], 1.0 / (double)(m + 1), F);
-                I1 = fma(nx[m], 1.0 / (double)(m + 2), I1);
+                if constexpr (ROLE == 0) {
+                    C += nx[m];
+                } else {
+                    C = fma(nx[m], 1.0 / (double)(m + 1), C);
+                    I1 = fma(nx[m], 1.0 / (double)(m + 2), I1);
+                }
             }
         }
-        Eh[K] = E;
-        Ih[K] = I1;
+        Hh[K] = ROLE == 0 ? C : I1;
         const double* __restrict__ Tk = Tr + K * kMaxN;
-        double tau = -0.0, nuk = -0.0;
+        double dot = -0.0;  // tau_K (ROLE 0) or nu_K (ROLE 1)
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
             const double t = Tk[j];
-            W0[j] = fma(E, t, W0[j]);
-            tau = fma(t, U[j], tau);
-            if constexpr (PP >= 1) {
-                W1[j] = fma(F, t, W1[j]);
-                nuk = fma(t, V[j], nuk);
-            }
+            W[j] = fma(C, t, W[j]);
+            dot = fma(t, X[j], dot);
         }
         // derivative terms of order K: K M_{K-1}, K (K-1) M_{K-2}, K (K-1) (K-2) M_{K-3}
-        double da = (double)K * Eh[K - 1] * tau;
-        if constexpr (PP >= 1) da = fma((double)K * dt * Ih[K - 1], nuk, da);
-        Ga += da;
-        if (K >= 2) {
-            double db = (double)(K * (K - 1)) * Eh[K - 2] * tau;
-            if constexpr (PP >= 1) db = fma((double)(K * (K - 1)) * dt * Ih[K - 2], nuk, db);
-            Gb += db;
-        }
-        if (K >= 3) {
-            double de = (double)(K * (K - 1) * (K - 2)) * Eh[K - 3] * tau;
-            if constexpr (PP >= 1) de = fma((double)(K * (K - 1) * (K - 2)) * dt * Ih[K - 3], nuk, de);
-            Ge += de;
-        }
+        // (through W1: the same with dt I_1 in place of M(1))
+        const double f = ROLE == 0 ? 1.0 : dt;
+        Ga = fma((double)K * f * Hh[K - 1], dot, Ga);
+        if (K >= 2) Gb = fma((double)(K * (K - 1)) * f * Hh[K - 2], dot, Gb);
+        if (K >= 3) Ge = fma((double)(K * (K - 1) * (K - 2)) * f * Hh[K - 3], dot, Ge);
     }
 }
 
@@ -154,20 +146,24 @@ __device__ __forceinline__ void stencils_containing(int64_t j, int64_t N, int n,
     }
 }
 
-// The whole reverse step of a tile of T - 4 (n - 1) nodes in one block:
-//   1. stage u, du/dx and lambda over the block's 256 weight positions (the
-//      tile and 2 (n - 1) on each side) plus the windows' reach;
-//   2. each thread forms the weights and parameter terms of one position
-//      (adj_taylor_node) into LDS -- positions next to the tile are
+// The whole reverse step of a tile of T - 4 (n - 1) nodes in one block of
+// 2 T threads:
+//   1. stage u, du/dx and lambda over the block's T = 256 weight positions
+//      (the tile and 2 (n - 1) on each side) plus the windows' reach;
+//   2. each position's weights and parameter terms (adj_taylor_side): threads
+//      [0, T) take the W0 side, threads [T, 2T) the W1 side; the weights go
+//      to LDS times lambda of their node -- positions next to the tile are
 //      recomputed by the neighbouring blocks instead of being exchanged;
 //   3. ghat at the positions within n - 1 of the tile (gather over LDS);
 //   4. lambda_k of the tile's nodes (gather over LDS), written to HBM;
 //   5. the tile's parameter terms summed in a fixed order into part[].
-// The per-node weights never reach HBM.  Each term is formed and summed in
-// the same order as in the three-kernel path, so lambda_k agrees with it bit
-// for bit (the parameter sums are split into tiles differently).
-template <int NN, int PP>
-__global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict__ probs, int nprob,
+// The per-node weights never reach HBM.  Every sum runs in a fixed order, so
+// the results do not depend on the launch or on how instances are batched.
+// DISP false: no instance of the launch has a dispersion term, and the cubic
+// term of the moment recursion (exact zeros then) is left out; the kernel
+// then fits in 128 registers, four wavefronts per SIMD.
+template <int NN, int PP, bool DISP>
+__global__ __launch_bounds__(2 * T) void adj_fused_kernel(const DevProb* __restrict__ probs, int nprob,
                                                       const double* __restrict__ fd,
                                                       const double* __restrict__ taylor,
                                                       const double* __restrict__ u_all,
@@ -200,23 +196,27 @@ __global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict_
     // 1. staging.  Positions outside a Dirichlet grid, or more than one
     // reflection away from a Neumann grid, are never read (a node's window
     // reaches at most (n-1)/2 beyond an end).
-    for (int q = tid; q < SU; q += T) {
+    for (int q = tid; q < SU; q += 2 * T) {
         const int64_t x = base - H + q;
         const bool ok = per || (dir ? (x >= 0 && x < N) : (x >= -(N - 1) && x <= 2 * (N - 1)));
         const int64_t xi = ok ? map_index(x, N, bc) : 0;
         su[q] = ok ? u[xi] : 0.0;
         sg[q] = ok ? gg[xi] : 0.0;
     }
-    {
+    if (tid < T) {
         const int64_t x = base + tid;
         sl[tid] = holds(x) ? lam_all[P.state_off + map_index(x, N, bc)] : 0.0;
     }
     __syncthreads();
 
-    // 2. weights and parameter terms of weight slot tid
+    // 2. weights and parameter terms of weight slot pos: threads [0, T) take
+    // the W0 side of slot tid, threads [T, 2T) the W1 side of slot tid - T
+    // (whole wavefronts per side)
     double d0 = 0.0, d1 = 0.0, d2 = 0.0;
     {
-        const int64_t x = base + tid;
+        const int role = tid >= T ? 1 : 0;
+        const int pos = tid - role * T;
+        const int64_t x = base + pos;
         const bool active = holds(x);
         // idle lanes take a node of the tile (results dropped)
         const int64_t i = active ? map_index(x, N, bc) : (t0 < N ? t0 : N - 1);
@@ -227,51 +227,83 @@ __global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict_
         const int o = (int)window_offset(i, N, NN, bc);
         const int r = -o;
         const double a = -ceff * ih * dt, b = P.nu * ih * ih * dt, e = -P.delta * ih * ih * ih * dt;
-        double U[NN], V[NN];
-#pragma unroll
-        for (int j = 0; j < NN; ++j) {
-            U[j] = su[us0 + o + j];
-            double v = 0.0;
-            if constexpr (PP >= 1) {
-                if (burgers) v = -g * (U[j] - ui) * sg[us0 + o + j];
-                else if (P.nonlin == NL_AC) v = g * (U[j] - U[j] * U[j] * U[j]);
-            }
-            V[j] = v;
-        }
         const double half = fmin(fmax(0.5 * a, -(double)NN), (double)NN);
         const int sh = (int)rint(half);
         const double* __restrict__ tb = taylor + taylor_index(NN, 0, 0, 0);
-        double W0[NN], W1[NN], Ga, Gb, Ge;
         int rp = r + sh;
         rp = rp < 0 ? 0 : (rp > NN - 1 ? NN - 1 : rp);
         const int r0 = __builtin_amdgcn_readfirstlane(r), rp0 = __builtin_amdgcn_readfirstlane(rp);
-        if (__ballot(active && (r != r0 || rp != rp0)) == 0) {
-            const double* __restrict__ Tr = tb + rp0 * (kMaxN * kMaxN);
-            if (rp0 == r0) {
-                if (P.delta != 0.0)
-                    adj_taylor_node<NN, PP, false, true>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
-                else
-                    adj_taylor_node<NN, PP, false, false>(a, b, e, 0.0, dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
-            } else
-                adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp0 - r0), dt, Tr, U, V, W0, W1, Ga, Gb, Ge);
-        } else {
-            adj_taylor_node<NN, PP, true>(a, b, e, (double)(rp - r), dt, tb + rp * (kMaxN * kMaxN), U, V, W0, W1,
-                                          Ga, Gb, Ge);
-        }
+        const bool uniform = __ballot(active && (r != r0 || rp != rp0)) == 0;
+        double Ga = 0.0, Gb = 0.0, Ge = 0.0;
+        // one side of slot pos: the window's U or V, the weights to LDS, the
+        // parameter terms to (Ga, Gb, Ge)
+        const double lq = sl[pos];  // the weights are stored times lambda of their node
+        auto side = [&](auto role_c) {
+            constexpr int RL = decltype(role_c)::value;
+            double X[NN], W[NN];
 #pragma unroll
-        for (int j = 0; j < NN; ++j) {
-            sW[j * T + tid] = W0[j];
-            if constexpr (PP >= 1) sW[(NN + j) * T + tid] = dt * W1[j];
+            for (int j = 0; j < NN; ++j) {
+                const double uj = su[us0 + o + j];
+                double v = uj;
+                if constexpr (RL == 1) {
+                    v = 0.0;
+                    if (burgers) v = -g * (uj - ui) * sg[us0 + o + j];
+                    else if (P.nonlin == NL_AC) v = g * (uj - uj * uj * uj);
+                }
+                X[j] = v;
+            }
+            if (uniform) {
+                const double* __restrict__ Tr = tb + rp0 * (kMaxN * kMaxN);
+                if (rp0 == r0)
+                    adj_taylor_side<NN, RL, false, DISP>(a, b, e, 0.0, dt, Tr, X, W, Ga, Gb, Ge);
+                else
+                    adj_taylor_side<NN, RL, true, DISP>(a, b, e, (double)(rp0 - r0), dt, Tr, X, W, Ga, Gb, Ge);
+#pragma unroll
+                for (int j = 0; j < NN; ++j) sW[(RL * NN + j) * T + pos] = lq * (RL == 0 ? W[j] : dt * W[j]);
+            } else {
+                // lanes of several window or table rows (next to an end, or
+                // shifts that differ): one pass per distinct (r, r'), each with
+                // wave-uniform table rows
+                for (;;) {
+                    // the lowest lane still here picks the rows of this pass;
+                    // it matches itself, so every pass retires at least one lane
+                    const int rf = __builtin_amdgcn_readfirstlane(r);
+                    const int rpf = __builtin_amdgcn_readfirstlane(rp);
+                    if (r == rf && rp == rpf) {
+                        adj_taylor_side<NN, RL, true, DISP>(a, b, e, (double)(rpf - rf), dt, tb + rpf * (kMaxN * kMaxN),
+                                                            X, W, Ga, Gb, Ge);
+#pragma unroll
+                        for (int j = 0; j < NN; ++j) sW[(RL * NN + j) * T + pos] = lq * (RL == 0 ? W[j] : dt * W[j]);
+                        break;
+                    }
+                }
+            }
+        };
+        if (role == 0) {
+            side(std::integral_constant<int, 0>{});
+        } else if constexpr (PP >= 1) {
+            side(std::integral_constant<int, 1>{});
+            red[0][pos] = Ga;  // the W1 side's parts, added by the W0 side below
+            red[1][pos] = Gb;
+            red[2][pos] = Ge;
         }
-        const bool fixed = dir && (i == 0 || i == N - 1);
-        const double lam = (active && !fixed) ? sl[tid] : 0.0;
-        const bool mine = active && tid >= HW && tid < HW + TO && x < N;  // a node of the tile
-        if (mine) {
-            d0 = lam * (dt * ih * ih) * Gb;
-            d1 = lam * (-dt * ih) * Ga;
-            d2 = lam * (-dt * ih * ih * ih) * Ge;
+        __syncthreads();
+        if (role == 0) {
+            if constexpr (PP >= 1) {
+                Ga += red[0][pos];
+                Gb += red[1][pos];
+                Ge += red[2][pos];
+            }
+            const bool fixed = dir && (i == 0 || i == N - 1);
+            const double lam = (active && !fixed) ? sl[pos] : 0.0;
+            const bool mine = active && pos >= HW && pos < HW + TO && x < N;  // a node of the tile
+            if (mine) {
+                d0 = lam * (dt * ih * ih) * Gb;
+                d1 = lam * (-dt * ih) * Ga;
+                d2 = lam * (-dt * ih * ih * ih) * Ge;
+            }
+            sdc[pos] = d1;
         }
-        sdc[tid] = d1;
     }
     __syncthreads();
 
@@ -284,7 +316,7 @@ __global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict_
             const double um = su[tid + H];
             auto term = [&](int64_t x, int k) {
                 const int q = (int)(x - base);
-                acc += sl[q] * sW[(NN + k) * T + q] * (-g) * (um - su[q + H]);
+                acc += sW[(NN + k) * T + q] * (-g) * (um - su[q + H]);
             };
             if (gather_interior(mi, N, NN)) {
 #pragma unroll
@@ -309,9 +341,8 @@ __global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict_
         double acc = 0.0;
         auto term = [&](int64_t x, int k) {
             const int q = (int)(x - base);
-            double w = sW[k * T + q];
-            if (etd) w += dNj * sW[(NN + k) * T + q];
-            acc += sl[q] * w;
+            const double w0 = sW[k * T + q];
+            acc += etd ? fma(dNj, sW[(NN + k) * T + q], w0) : w0;
         };
         const bool inner = gather_interior(j, N, NN);
         if (inner) {
@@ -326,7 +357,7 @@ __global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict_
             double sacc = 0.0;
 #pragma unroll
             for (int k = 0; k < NN; ++k) sacc += sW[(NN + k) * T + qj] * sg[qj + H + o + k];
-            acc += sl[qj] * g * sacc + g * sdc[qj];
+            acc += g * sacc + g * sdc[qj];
         }
         if (burgers) {
             if (inner) {
@@ -357,29 +388,36 @@ __global__ __launch_bounds__(T) void adj_fused_kernel(const DevProb* __restrict_
         lam_out_all[P.state_off + j] = acc;
     }
 
-    // 5. the tile's parameter terms, fixed-order tree sum
-    red[0][tid] = d0;
-    red[1][tid] = d1 * (tid >= HW && tid < HW + TO ? 1.0 : 0.0);
-    red[2][tid] = d2;
-    __syncthreads();
-    for (int w = T / 2; w > 0; w >>= 1) {
-        if (tid < w)
-            for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + w];
-        __syncthreads();
+    // 5. the tile's parameter terms, in a fixed order: each wavefront of the
+    // W0 side sums its lanes (shuffles), then thread 0 the four wavefront sums
+    if (tid < T) {
+        double v[3] = {d0, d1 * (tid >= HW && tid < HW + TO ? 1.0 : 0.0), d2};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_down(v[c], off, 64);
+            if ((tid & 63) == 0) red[c][tid >> 6] = v[c];
+        }
     }
+    __syncthreads();
     if (tid == 0)
-        for (int c = 0; c < 3; ++c) part[3 * tile + c] = red[c][0];
+        for (int c = 0; c < 3; ++c) part[3 * tile + c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+}
+
+template <int NN, int PP>
+hipError_t go_adj_fused_p(const AdjointLaunch& a, hipStream_t s) {
+    if (a.disp)
+        hipLaunchKernelGGL((adj_fused_kernel<NN, PP, true>), dim3((unsigned)a.fused_tiles), dim3(2 * T), 0, s,
+                           a.fused_probs, a.nprob, a.fd, a.taylor, a.u, a.lam, a.g, a.lam_out, a.part);
+    else
+        hipLaunchKernelGGL((adj_fused_kernel<NN, PP, false>), dim3((unsigned)a.fused_tiles), dim3(2 * T), 0, s,
+                           a.fused_probs, a.nprob, a.fd, a.taylor, a.u, a.lam, a.g, a.lam_out, a.part);
+    return hipGetLastError();
 }
 
 template <int NN>
 hipError_t go_adj_fused(const AdjointLaunch& a, hipStream_t s) {
-    if (a.p == 0)
-        hipLaunchKernelGGL((adj_fused_kernel<NN, 0>), dim3((unsigned)a.fused_tiles), dim3(T), 0, s, a.fused_probs,
-                           a.nprob, a.fd, a.taylor, a.u, a.lam, a.g, a.lam_out, a.part);
-    else
-        hipLaunchKernelGGL((adj_fused_kernel<NN, 1>), dim3((unsigned)a.fused_tiles), dim3(T), 0, s, a.fused_probs,
-                           a.nprob, a.fd, a.taylor, a.u, a.lam, a.g, a.lam_out, a.part);
-    return hipGetLastError();
+    return a.p == 0 ? go_adj_fused_p<NN, 0>(a, s) : go_adj_fused_p<NN, 1>(a, s);
 }
 
 }  // namespace

@@ -1012,6 +1012,7 @@ struct AdjGroup {
     int64_t nodes = 0, tiles = 0;
     bool taylor = false;
     bool fused = false;  // whole step in one kernel (finite Taylor, tiles of adj_fused_tile(n) nodes)
+    bool disp = false;   // some instance has a dispersion term
     int64_t ftiles = 0;
 };
 struct AdjPlan {
@@ -1064,6 +1065,7 @@ int make_adj_plan(AdjPlan& P, const lmep_problem* prob, int32_t count, const Opt
             d.item_begin = g.ftiles;
             ftab.push_back(d);
             g.nodes += prob[k].N;
+            g.disp |= prob[k].delta != 0.0;
             g.tiles += (prob[k].N + kAdjTile - 1) / kAdjTile;
             g.ftiles += (prob[k].N + adj_fused_tile(g.n) - 1) / adj_fused_tile(g.n);
         }
@@ -1152,6 +1154,7 @@ int run_adjoint(const AdjPlan& P, char* base, const double* d_u_k, const double*
         if (g.fused) {
             a.fused_probs = df + g.first;
             a.fused_tiles = g.ftiles;
+            a.disp = g.disp;
         }
         if (prof) {
             a.frechet_begin = per[gi].first;
@@ -1170,8 +1173,11 @@ int run_adjoint(const AdjPlan& P, char* base, const double* d_u_k, const double*
             HIP_TRY(hipEventElapsedTime(&ms, per[gi].first, per[gi].second));
             fms += ms;
             char nm[64];
-            snprintf(nm, sizeof(nm), "%s<%d,%d>", P.groups[gi].fused ? "adj_fused_kernel" : "adj_frechet_kernel",
-                     P.groups[gi].n, P.groups[gi].p);
+            if (P.groups[gi].fused)
+                snprintf(nm, sizeof(nm), "adj_fused_kernel<%d,%d,%s>", P.groups[gi].n, P.groups[gi].p,
+                         P.groups[gi].disp ? "true" : "false");
+            else
+                snprintf(nm, sizeof(nm), "adj_frechet_kernel<%d,%d>", P.groups[gi].n, P.groups[gi].p);
             bool found = false;
             for (auto& k : kt)
                 if (k.name == nm) {

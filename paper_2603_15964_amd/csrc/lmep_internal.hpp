@@ -231,6 +231,7 @@ struct AdjointLaunch {
     const double* taylor = nullptr;
     const DevProb* fused_probs = nullptr;
     int64_t fused_tiles = 0;
+    bool disp = true;  // some instance of the group has a dispersion term (delta != 0)
     hipEvent_t frechet_begin = nullptr, frechet_end = nullptr;  // recorded around the Frechet kernel if set
 };
 hipError_t launch_adjoint(const AdjointLaunch& a, hipStream_t stream);

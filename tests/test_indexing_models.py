@@ -189,9 +189,10 @@ def test_model_finds_the_last_tile_error():
 
 
 # --------------------------------------------------------------------------
-# The fused reverse step (adjoint_taylor.hip): one block of 256 weight
-# positions per tile of 256 - 4 (n - 1) nodes.  The model replays the
-# kernel's index arithmetic thread by thread: every LDS index in bounds, and
+# The fused reverse step (adjoint_taylor.hip): one block of 2 x 256 threads
+# per tile of 256 - 4 (n - 1) nodes, 256 weight positions, each worked on by
+# two threads (its W0 and W1 sides) with the same index arithmetic; the model
+# replays that arithmetic position by position: every LDS index in bounds, and
 # every value read is one that was staged or computed (a staged position the
 # load covered, a weight slot whose node was active, a ghat slot in the range
 # step 3 fills), for every stencil size, boundary type and tile position.
@@ -259,7 +260,12 @@ def adj_tile_problems(N, n, bc, tile):
         x = base - H + q
         staged.append(per or ((0 <= x < N) if dr else (-(N - 1) <= x <= 2 * (N - 1))))
     computed = [False] * T
-    for tid in range(T):  # step 2
+    for thread in range(2 * T):  # step 2: both sides of every position
+        side = 1 if thread >= T else 0
+        tid = thread - side * T
+        if not 0 <= tid < T:
+            errs.append(("step2 slot", thread))
+            continue
         x = base + tid
         active = holds(x)
         i = _map_index(x, N, bc) if active else (t0 if t0 < N else N - 1)
