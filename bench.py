@@ -485,7 +485,9 @@ def kernel_work(name, problems, steps):
         g = group(lambda p: frozen(p) and p["n"] == v[0])
         return "alu", taylor_flops(v[0], v[1]) * sum(p["N"] for p in g) * steps, "flop"
     if base == "stepk_mixed_kernel":  # every size of one scheme and nonlinearity, more than 512 nodes
-        g = group(lambda p: SCHEME_ID[p["scheme"]] == v[0] and nl_id(p) == v[1] and not frozen(p)
+        # nonlinearity code 4: Allen-Cahn with coefficient 1 in every instance
+        want = NONLIN_ID["allen_cahn"] if v[1] == 4 else v[1]
+        g = group(lambda p: SCHEME_ID[p["scheme"]] == v[0] and nl_id(p) == want and not frozen(p)
                   and p.get("x") is None and p.get("window", "centred") == "centred" and p["N"] > 512)
         return "alu", sum(stationary_flops(p) * p["N"] for p in g) * steps, "flop"
     if base in ("stepk_kernel", "stepk_upwind_kernel", "stepk_rk4_kernel"):

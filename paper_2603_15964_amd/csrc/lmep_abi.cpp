@@ -327,6 +327,7 @@ struct Group {
     bool stepk = false;  // stationary multi-step kernel (always for ETDRK4)
     int side = 0;        // stationary windows: 0 centred, 1 one-sided ending at the node (c > 0), 2 starting at it
     bool mixed = false;  // one multi-step launch over several stencil sizes (n = the largest)
+    bool unit_g = false;  // merged Allen-Cahn launch whose every instance has g = 1
     int first = 0, count = 0;  // slice of the table
     int64_t items = 0;         // matrices (build) or tiles (apply)
     int64_t nodes = 0;         // nodes of the group's instances
@@ -467,6 +468,8 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         g.first = (int)tab.size();
         for (int k : kv.second) g.nodes += prob[k].N;
         for (int k : kv.second) g.max_nodes = std::max(g.max_nodes, prob[k].N);
+        g.unit_g = g.mixed && g.nonlin == LMEP_NL_ALLEN_CAHN && g.scheme != LMEP_LINEAR;
+        for (int k : kv.second) g.unit_g = g.unit_g && prob[k].nl_coef == 1.0;
         // several steps per launch: whole small instances per block (non-uniform
         // grids always; uniform ones with a stationary table, a pointwise or no
         // nonlinearity and at most kResidentMaxN nodes), else the tiled kernel
@@ -513,12 +516,16 @@ std::string build_kernel_name(const Group& g, bool fused, bool multi) {
     else snprintf(b, sizeof(b), "build_pade_kernel<%d,%d,%s>", g.n, g.p, bool_s(fused).c_str());
     return b;
 }
+// nonlinearity code of a merged multi-step launch
+int mixed_nonlin(const Group& g) { return g.unit_g ? kNlAcUnit : g.nonlin; }
 std::string apply_kernel_name(const Group& g) {
     const int kb = g.kb;
     char b[96];
     const int nl = g.scheme == LMEP_LINEAR ? 0 : g.nonlin;
     if (g.stepk && g.scheme == LMEP_ETDRK4) snprintf(b, sizeof(b), "stepk_rk4_kernel<%d,%d,%d>", g.n, g.nonlin, kb);
-    else if (g.stepk && g.mixed) snprintf(b, sizeof(b), "stepk_mixed_kernel<%d,%d,%d>", g.scheme, nl, kb);
+    else if (g.stepk && g.mixed)
+        snprintf(b, sizeof(b), "stepk_mixed_kernel<%d,%d,%d>", g.scheme, g.scheme == LMEP_LINEAR ? 0 : mixed_nonlin(g),
+                 kb);
     else if (g.stepk && g.side != 0)
         snprintf(b, sizeof(b), "stepk_upwind_kernel<%d,%d,%d,%d,%d>", g.n, g.scheme, nl, kb, g.side);
     else if (g.stepk) snprintf(b, sizeof(b), "stepk_kernel<%d,%d,%d,%d>", g.n, g.scheme, nl, kb);
@@ -837,7 +844,7 @@ int enqueue_steps(const StepPlan& P, char* base, const double* fd, const double*
                     if (one_span) span = t;
                 }
                 if (gr.stepk && gr.mixed)
-                    HIP_TRY(launch_stepk_mixed(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),
+                    HIP_TRY(launch_stepk_mixed(gr.n, gr.scheme, mixed_nonlin(gr), kb, std::min(kb, n_steps - st * kb),
                                                dat + gr.first, dti + tile0, gr.items, fd, d_w, src, dst, s));
                 else if (gr.stepk)
                     HIP_TRY(launch_stepk(gr.n, gr.scheme, gr.nonlin, kb, std::min(kb, n_steps - st * kb),

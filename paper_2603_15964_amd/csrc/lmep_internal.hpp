@@ -46,6 +46,10 @@ enum : int { SCH_LINEAR = 0, SCH_ETD1 = 1, SCH_ETD2RK = 2, SCH_ETDRK4 = 3 };
 // dt gamma) and the half step (p = 1 at dt/2: kinds 0, 1).
 enum : int { HARVEST_PLAIN = 0, HARVEST_RK4_FULL = 1, HARVEST_RK4_HALF = 2 };
 enum : int { NL_NONE = 0, NL_BURGERS = 1, NL_KDV = 2, NL_AC = 3 };
+// Launch code of the merged multi-step kernel only (never a DevProb value):
+// Allen-Cahn where every instance of the launch has coefficient g = 1, so the
+// kernel evaluates u - u^3 without the product by g (the same bits).
+constexpr int kNlAcUnit = 4;
 enum : int { WIN_CENTRED = 0, WIN_UPWIND = 1 };
 
 // Table of finite-difference weights on the centred integer stencil

@@ -70,7 +70,8 @@ __device__ __forceinline__ int64_t node_of(int64_t j, int64_t N, int bc) {
 
 template <int NL>
 __device__ __forceinline__ double pointwise_N(double x, double g) {
-    return g * (x - x * x * x);
+    if constexpr (NL == kNlAcUnit) return x - x * x * x;  // g = 1: the same value
+    else return g * (x - x * x * x);
 }
 
 // Interior window of a SIDE: offset O (stencil i + O .. i + O + n - 1), row
@@ -466,6 +467,9 @@ hipError_t dispatch_mixed(int nmax, int scheme, int nonlin, const DevProb* p, co
         case NL_KDV:
             return rk2 ? go_mixed<SCH_ETD2RK, NL_KDV, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s)
                        : go_mixed<SCH_ETD1, NL_KDV, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s);
+        case kNlAcUnit:
+            return rk2 ? go_mixed<SCH_ETD2RK, kNlAcUnit, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s)
+                       : go_mixed<SCH_ETD1, kNlAcUnit, KB>(nmax, p, ti, tiles, fd, w, ui, uo, ksteps, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -209,16 +209,29 @@ def test_full_size_kdv_multistep():
 
 
 @pytest.mark.parametrize("kb", [8, 16])
-@pytest.mark.parametrize("kind", ["allen_cahn_etd1", "kdv_etd2rk", "linear_dirichlet"])
+@pytest.mark.parametrize("kind", ["allen_cahn_etd1", "allen_cahn_etd2rk_g07", "allen_cahn_mixed_g", "kdv_etd2rk",
+                                  "linear_dirichlet"])
 def test_merged_stencil_sizes_equal_separate_launches(kind, kb):
     """LMEP_OPT_MERGE_GROUPS: instances of several stencil sizes in one
     launch (largest n first) give the separate launches' result bit for bit,
-    and that launch is the one that runs."""
+    and that launch is the one that runs; Allen-Cahn launches whose every
+    instance has coefficient 1 take the kernel without the product by g
+    (nonlinearity code 4), others the general one (code 3)."""
     _print_case("merged sizes", kind, kb)
     probs, states = [], []
     for k, (n, N) in enumerate([(5, 3000), (11, 2600), (7, 4100), (9, 2049), (11, 700), (3, 1500), (15, 2100)]):
         if kind == "allen_cahn_etd1":
             p, u = _ac(N, n, "periodic" if k % 2 else "neumann", "etd1")
+        elif kind == "allen_cahn_etd2rk_g07":
+            if n > 13:  # ETD2RK builds n + 2 <= 16
+                continue
+            # clamped Dirichlet windows of n >= 7 need a small diffusion number
+            p, u = _ac(N, n, "periodic" if k % 2 else "dirichlet", "etd2rk", mu=0.1)
+            p = dict(p, nl_coef=0.7)
+        elif kind == "allen_cahn_mixed_g":  # one instance with g != 1: the general kernel
+            p, u = _ac(N, n, "neumann", "etd1")
+            if k == 3:
+                p = dict(p, nl_coef=1.5)
         elif kind == "kdv_etd2rk":
             if n > 13:
                 continue
@@ -247,9 +260,13 @@ def test_merged_stencil_sizes_equal_separate_launches(kind, kb):
             if merge:
                 assert any(x.startswith("stepk_mixed_kernel<") for x in names), names
                 assert not any(x.startswith("stepk_kernel<") for x in names), names
+                if kind.startswith("allen_cahn"):
+                    code = 4 if kind == "allen_cahn_etd1" else 3
+                    assert f"stepk_mixed_kernel<{1 if 'etd1' in kind or 'mixed' in kind else 2},{code},{kb}>" in names, names
     finally:
         lmep.lmep_set_option(lmep.LMEP_OPT_MERGE_GROUPS, 0)
         lmep.lmep_set_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH, saved)
+    assert bool(torch.isfinite(outs[0]).all())
     assert torch.equal(outs[0], outs[1])
     got = lmep.Batch(probs, device=DEV).unpack(outs[1])
     for k, (p, u) in enumerate(zip(probs, states)):
