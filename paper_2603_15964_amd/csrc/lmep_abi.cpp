@@ -282,6 +282,18 @@ Layout layout(const lmep_problem* prob, int32_t count, int op) {
     return L;
 }
 
+// Rows [first, first + count) of a table hold one group, with item_begin the
+// prefix of `total` work items: when every instance has the same number of
+// items, each row records it and the kernels find a block's instance by a
+// division instead of a search.
+void mark_each(std::vector<DevProb>& tab, size_t first, size_t count, int64_t total) {
+    if (count == 0) return;
+    const int64_t each = total / (int64_t)count;
+    bool same = each > 0 && each * (int64_t)count == total && each <= INT32_MAX;
+    for (size_t k = 0; same && k < count; ++k) same = tab[first + k].item_begin == (int64_t)k * each;
+    for (size_t k = 0; k < count; ++k) tab[first + k].each = same ? (int32_t)each : 0;
+}
+
 DevProb to_dev(const lmep_problem& q, int index) {
     DevProb d;
     std::memset(&d, 0, sizeof(d));
@@ -422,6 +434,7 @@ std::vector<Group> plan_build(const lmep_problem* prob, int32_t count, Want want
         }
         g.count = (int)kv.second.size();
         g.items = items;
+        mark_each(tab, g.first, g.count, items);
         groups.push_back(g);
     }
     return groups;
@@ -498,6 +511,7 @@ std::vector<Group> plan_apply(const lmep_problem* prob, int32_t count, std::vect
         }
         g.count = (int)kv.second.size();
         g.items = tiles;
+        mark_each(tab, g.first, g.count, tiles);
         groups.push_back(g);
     }
     return groups;
@@ -1076,6 +1090,9 @@ int make_adj_plan(AdjPlan& P, const lmep_problem* prob, int32_t count, const Opt
             g.tiles += (prob[k].N + kAdjTile - 1) / kAdjTile;
             g.ftiles += (prob[k].N + adj_fused_tile(g.n) - 1) / adj_fused_tile(g.n);
         }
+        mark_each(ntab, g.first, g.cnt, g.nodes);
+        mark_each(P.ttab, g.first, g.cnt, g.tiles);
+        mark_each(ftab, g.first, g.cnt, g.ftiles);
         P.groups.push_back(g);
     }
     P.ntab = ntab.size();

@@ -64,8 +64,14 @@ __device__ __forceinline__ bool gather_interior(int64_t j, int64_t N, int n) {
     return j >= 2 * (n - 1) && j <= N - 1 - 2 * (n - 1);
 }
 
-// Instance owning work item `item` (binary search over item_begin).
+// Instance owning work item `item`: a division when the group records a common
+// item count per instance, else a binary search over item_begin.
 __device__ __forceinline__ int find_instance(const DevProb* __restrict__ probs, int nprob, int64_t item) {
+    const int each = probs[0].each;  // equal item counts: no search (the same answer)
+    if (each > 0) {
+        const uint64_t k = (uint64_t)item / (uint32_t)each;
+        return k < (uint64_t)nprob ? (int)k : nprob - 1;
+    }
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;

@@ -33,7 +33,8 @@ struct DevProb {
     int32_t n, bc, scheme, nonlin;
     int32_t p, frozen, index, harvest;  // harvest: what the build writes (HARVEST_*)
     double h, dt, c, nu, delta, react, nl_coef, bc_left, bc_right;
-    int32_t window, pad1;  // WIN_*
+    int32_t window;  // WIN_*
+    int32_t each;    // work items of every instance of the table's group when all are equal, else 0
     const double* x;       // node coordinates (non-uniform grids) or nullptr
     double pad2[1];
 };
