@@ -154,8 +154,10 @@ __device__ __forceinline__ void stencils_containing(int64_t j, int64_t N, int n,
 //      [0, T) take the W0 side, threads [T, 2T) the W1 side; the weights go
 //      to LDS times lambda of their node -- positions next to the tile are
 //      recomputed by the neighbouring blocks instead of being exchanged;
-//   3. ghat at the positions within n - 1 of the tile (gather over LDS);
-//   4. lambda_k of the tile's nodes (gather over LDS), written to HBM;
+//   3. ghat at the positions within n - 1 of the tile (gather over LDS, on
+//      threads [T, 2T)), while threads [0, T) sum the part of lambda_k that
+//      does not read ghat;
+//   4. the ghat terms of lambda_k (gather over LDS), lambda_k written to HBM;
 //   5. the tile's parameter terms summed in a fixed order into part[].
 // The per-node weights never reach HBM.  Every sum runs in a fixed order, so
 // the results do not depend on the launch or on how instances are batched.
@@ -307,45 +309,46 @@ __global__ __launch_bounds__(2 * T) void adj_fused_kernel(const DevProb* __restr
     }
     __syncthreads();
 
-    // 3. ghat at the weight slots within n - 1 of the tile
-    if (burgers && tid >= H && tid < T - H) {
-        const int64_t m = base + tid;
-        double acc = 0.0;
-        if (holds(m)) {
-            const int64_t mi = map_index(m, N, bc);
-            const double um = su[tid + H];
-            auto term = [&](int64_t x, int k) {
-                const int q = (int)(x - base);
-                acc += sW[(NN + k) * T + q] * (-g) * (um - su[q + H]);
-            };
-            if (gather_interior(mi, N, NN)) {
-#pragma unroll
-                for (int d = -R; d <= R; ++d) term(m + d, R - d);
-            } else {
-                stencils_containing(per ? m : mi, N, NN, bc, term);
-            }
-        }
-        sgh[tid] = acc;
-    }
-    __syncthreads();
-
-    // 4. lambda_k of the tile's nodes
+    // 3. ghat at the weight slots within n - 1 of the tile (threads [T, 2T)),
+    // while threads [0, TO) form the part of lambda_k that does not read ghat
     const int64_t j = t0 + tid;
-    if (tid < TO && j < N) {
+    const bool node_thread = tid < TO && j < N;
+    double acc = 0.0;  // lambda_k of node j, summed in the order of the stencil terms
+    if (tid >= T) {
+        const int q3 = tid - T;
+        if (burgers && q3 >= H && q3 < T - H) {
+            const int64_t m = base + q3;
+            double gacc = 0.0;
+            if (holds(m)) {
+                const int64_t mi = map_index(m, N, bc);
+                const double um = su[q3 + H];
+                auto term = [&](int64_t x, int k) {
+                    const int q = (int)(x - base);
+                    gacc += sW[(NN + k) * T + q] * (-g) * (um - su[q + H]);
+                };
+                if (gather_interior(mi, N, NN)) {
+#pragma unroll
+                    for (int d = -R; d <= R; ++d) term(m + d, R - d);
+                } else {
+                    stencils_containing(per ? m : mi, N, NN, bc, term);
+                }
+            }
+            sgh[q3] = gacc;
+        }
+    } else if (node_thread) {
+        // 4a. the gathers over the weights and the node's own window
         const int qj = HW + tid;  // weight slot of node j
         const double uj = su[qj + H];
         const bool etd = P.scheme == SCH_ETD1;
         double dNj = 0.0;
         if (etd && burgers) dNj = -g * sg[qj + H];
         if (etd && P.nonlin == NL_AC) dNj = g * (1.0 - 3.0 * uj * uj);
-        double acc = 0.0;
         auto term = [&](int64_t x, int k) {
             const int q = (int)(x - base);
             const double w0 = sW[k * T + q];
             acc += etd ? fma(dNj, sW[(NN + k) * T + q], w0) : w0;
         };
-        const bool inner = gather_interior(j, N, NN);
-        if (inner) {
+        if (gather_interior(j, N, NN)) {
 #pragma unroll
             for (int d = -R; d <= R; ++d) term(j + d, R - d);
         } else {
@@ -359,8 +362,14 @@ __global__ __launch_bounds__(2 * T) void adj_fused_kernel(const DevProb* __restr
             for (int k = 0; k < NN; ++k) sacc += sW[(NN + k) * T + qj] * sg[qj + H + o + k];
             acc += g * sacc + g * sdc[qj];
         }
+    }
+    __syncthreads();
+
+    // 4b. the ghat terms of lambda_k, then lambda_k to HBM
+    if (node_thread) {
+        const int qj = HW + tid;
         if (burgers) {
-            if (inner) {
+            if (gather_interior(j, N, NN)) {
 #pragma unroll
                 for (int d = -R; d <= R; ++d) acc += sgh[qj + d] * fd[fd_index(NN, 0, R, R - d)] * ih;
             } else {
