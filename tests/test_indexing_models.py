@@ -283,7 +283,7 @@ def adj_tile_problems(N, n, bc, tile):
         return 0 <= q < T and computed[q] and 0 <= q + H < SU and staged[q + H]
 
     ghat = [False] * T
-    for tid in range(H, T - H):  # step 3 (frozen-velocity ghat)
+    for tid in range(H, T - H):  # step 3 (frozen-velocity ghat; run by thread T + tid, the W1 side)
         m = base + tid
         if not holds(m):
             ghat[tid] = True  # written as 0 and read only as such
