@@ -97,6 +97,27 @@ def test_batched_reverse_step_equals_single():
         assert np.array_equal(g1.cpu().numpy(), gr[k])
 
 
+def test_equal_instances_reverse_step_equals_single():
+    """Instances with equal tile counts (each block finds its instance by a
+    division instead of a search): each equals its own reverse step bit for
+    bit."""
+    _case("equal-instance reverse step")
+    p = CASES[0][1]
+    us = [_state(p, 30 + k) for k in range(3)]
+    lams = [np.random.default_rng(50 + k).normal(size=p["N"]) for k in range(3)]
+    b = lmep.Batch([p] * 3, device=DEV)
+    lk, gr = b.adjoint_step(b.pack(us), b.pack(lams))
+    torch.cuda.synchronize()
+    got = b.unpack(lk)
+    gr = gr.cpu().numpy().reshape(-1, 3)
+    for k in range(3):
+        b1 = lmep.Batch([p], device=DEV)
+        l1, g1 = b1.adjoint_step(b1.pack(us[k]), b1.pack(lams[k]))
+        torch.cuda.synchronize()
+        assert np.array_equal(b1.unpack(l1)[0], got[k]), k
+        assert np.array_equal(g1.cpu().numpy(), gr[k]), k
+
+
 @pytest.mark.parametrize("every", [1, 4, 50, None])
 def test_checkpointed_gradient_matches_oracle_and_fd(every):
     """loss = 0.5 ||u(T) - target||^2, target made with nu * 1.1 (C5 recipe,

@@ -195,6 +195,27 @@ def test_taylor_batch_equals_single_and_graph_equals_eager():
         assert _state_err(single, oracle.run(p, u, 4)) <= 1e-10, k
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_equal_instances_batch_equals_single(persistent):
+    """Instances with equal work (each block then finds its instance by a
+    division instead of a search): each instance of the batch equals its own
+    single-instance run bit for bit, one step per launch and at 8 per launch."""
+    _print_case("equal-instance batch", persistent)
+    cases = [_problem(2500, 7, "dirichlet", seed=10 + k) for k in range(3)]
+    probs = [c[0] for c in cases]
+    states = [c[1] for c in cases]
+    flags = lmep.LMEP_F_PERSISTENT if persistent else 0
+    saved = lmep.lmep_get_option(lmep.LMEP_OPT_STEPS_PER_LAUNCH)
+    _set_kb(8)
+    try:
+        batched = _run(probs, states, 11, flags=flags)
+        for k, (p, u) in enumerate(zip(probs, states)):
+            assert np.array_equal(batched[k], _run([p], [u], 11, flags=flags)[0]), k
+    finally:
+        _set_kb(saved)
+    assert _state_err(batched[1], oracle.run(probs[1], states[1], 11)) <= 1e-10
+
+
 def test_taylor_counts_nodes_without_squarings():
     """LMEP_F_COUNT: a Taylor-built node counts as one matrix, no squarings."""
     _print_case("taylor counters")
