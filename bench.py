@@ -622,7 +622,7 @@ def main():
                          "or Pade scaling-and-squaring everywhere")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU: the batch is one GPU's share (multi-GPU sharding is a design, not code); --gpus must be 1"}), flush=True)
         raise SystemExit(2)
 
     import torch
