@@ -182,15 +182,25 @@ def test_multistep_rejects_uncovered_frozen_weights():
 
 
 # ---------------------------------------------------------- full size ----
-def test_full_size_allen_cahn_batch():
-    """The 4096-instance Allen-Cahn batch (sum N ~ 1.35e8) in the benchmark's
-    launch configuration: 16 multi-step steps equal the one-step path bit for
-    bit everywhere; four instances (smallest, largest, two others) match the
+@pytest.mark.parametrize("kb,merge", [(8, 0), (16, 1)])
+def test_full_size_allen_cahn_batch(kb, merge):
+    """The 4096-instance Allen-Cahn batch (sum N ~ 1.35e8), at 8 steps per
+    launch with a launch per stencil size and in the benchmark's launch
+    configuration (16 steps per launch, every size in one launch, the
+    unit-coefficient kernel): 16 steps equal the one-step path bit for bit
+    everywhere; four instances (smallest, largest, two others) match the
     oracle."""
-    _print_case("full size allen-cahn batch multistep")
+    _print_case("full size allen-cahn batch multistep", kb, merge)
     probs, states = workloads.allen_cahn_batch()
     steps = 16
-    ref, got = run_both(probs, states, steps, 8)
+    lmep.lmep_set_option(lmep.LMEP_OPT_MERGE_GROUPS, merge)
+    try:
+        ref, got = run_both(probs, states, steps, kb, lmep.LMEP_F_PROFILE)
+        names = [k[0] for k in lmep.lmep_profile_kernels()]
+    finally:
+        lmep.lmep_set_option(lmep.LMEP_OPT_MERGE_GROUPS, 0)
+    if merge:
+        assert names == ["stepk_mixed_kernel<1,4,16>"], names
     for k in range(len(probs)):
         if not np.array_equal(ref[k], got[k]):
             raise AssertionError(f"instance {k} differs: {np.max(np.abs(ref[k] - got[k]))}")
