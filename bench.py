@@ -670,6 +670,11 @@ def main():
                    config={"workload": desc, **res.pop("config")}, roofline=res.pop("roofline"))
         out.update(res)
     else:
+        # the plain path first: the timed steps then run at the clocks a
+        # sustained load holds, whatever the step counts asked for
+        plain = None
+        if len(problems) > 1 and not args.no_plain:
+            plain = plain_forward(problems, states, min(args.steps, 20))
         res, batch, w, ua = forward_line(problems, states, args.steps, args.warmup, flags, kb)
         roof, rows = kernel_rooflines(batch, w, ua, args.steps, flags, problems, args.workload)
         frozen = any(p.get("nonlin") == "burgers_frozen" for p in problems)
@@ -684,8 +689,8 @@ def main():
                            "tuned": (dict(tuned.choice.describe(), from_cache=tuned.from_cache) if tuned else None)},
                    roofline=roof, kernels=rows,
                    detail={"gpu_event_ms": res["gpu_event_ms"], "wall_ms": res["wall_ms"]})
-        if len(problems) > 1 and not args.no_plain:
-            pv, pk = plain_forward(problems, states, min(args.steps, 20))
+        if plain is not None:
+            pv, pk = plain
             out["plain"] = {"value": pv, "unit": "node-steps/s", "instances": pk, "steps": min(args.steps, 20),
                             "kind": "single-instance forward: instances one at a time, one lmep_step call each, "
                                     "one step per launch",
